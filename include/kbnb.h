@@ -1,0 +1,230 @@
+/*
+ * kbnb.h -- C ABI of the batched node-bound library for cardinality-
+ * constrained GLMs on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper, Sec. 1, eqs. intro_sparse_glm / intro_sparse_glm_mip):
+ *     min_beta  sum_i l(x_i^T beta, y_i) + lambda2 ||beta||_2^2
+ *     s.t.      ||beta||_0 <= k,  ||beta||_inf <= M,
+ * with the squared loss l = (y - s)^2 or the logistic loss
+ * l = log(1 + exp(-y s)), y in {-1, +1}.
+ *
+ * A branch-and-bound node fixes some support indicators: a fixed-in set J1
+ * (z_j = 1) and a fixed-out set J0 (z_j = 0); the rest are free (Sec. 3).  For
+ * each node the library computes the perspective-relaxation lower bound of
+ * Sec. 3 (eq. node_composite) by accelerated proximal gradient over a whole
+ * batch of nodes at once (Sec. 4.2, eq. pgd_step_matrix_form), certified in
+ * float64 by the Fenchel dual (eqs. prelim_fenchel_dual,
+ * batched_dual_value_component): every reported lower bound is a value of
+ * the dual function at some dual point, so it never exceeds the node's
+ * optimum.  Rounding and branching outputs follow Sec. 4.3 (after Thm. 4.1).
+ *
+ * Conventions
+ *  - Every call returns 0 (KBNB_OK) on success or a negative KBNB_E* code;
+ *    last_error() then describes the failure.  poll_bounds may return
+ *    KBNB_TIMEOUT (positive, not an error).
+ *  - Indices are 0-based int32.  Matrices are row-major.
+ *  - The caller owns every array it passes and may free it when the call
+ *    returns, except device arrays given with KBNB_MEM_DEVICE_BORROW, which
+ *    must outlive the problem.  Results are written into caller buffers.
+ *  - A problem handle is owned by the library until destroy_problem.  Calls
+ *    on one handle are serialised internally; different handles are
+ *    independent and may be used from different threads.
+ *  - Errors are atomic: a call that fails admits or changes nothing.
+ */
+#ifndef KBNB_H
+#define KBNB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define KBNB_OK 0
+#define KBNB_TIMEOUT 1             /* poll_bounds: nothing completed in time */
+#define KBNB_E_INVALID_ARGUMENT (-1)
+#define KBNB_E_OUT_OF_MEMORY (-2)
+#define KBNB_E_BUDGET_EXCEEDED (-3) /* the problem can never fit its HBM budget */
+#define KBNB_E_DEVICE (-4)          /* a HIP runtime call failed */
+#define KBNB_E_BAD_HANDLE (-5)
+#define KBNB_E_NO_DEVICE (-6)       /* no gfx950 device is visible */
+
+/* losses */
+#define KBNB_LOSS_SQUARED 0
+#define KBNB_LOSS_LOGISTIC 1
+
+/* storage type of X: the stored values define the instance exactly */
+#define KBNB_DTYPE_F64 0
+#define KBNB_DTYPE_F32 1
+#define KBNB_DTYPE_BF16 2 /* uint16 bfloat16 bit patterns */
+
+/* where X and y live */
+#define KBNB_MEM_HOST_COPY 0      /* host arrays, copied at create_problem */
+#define KBNB_MEM_DEVICE_COPY 1    /* device arrays, copied at create_problem */
+#define KBNB_MEM_DEVICE_BORROW 2  /* device arrays; X must be row-major with ldx ==
+                                     p rounded up to 16 and zero padding; kept */
+
+/* node status */
+#define KBNB_CONVERGED 0 /* (primal - lower_bound) <= rel_tol * |primal| */
+#define KBNB_PRUNED 1    /* lower_bound >= upper_bound - 1e-6 * |upper_bound| */
+#define KBNB_MAXITER 2   /* iteration cap reached; the bound is still valid */
+#define KBNB_ERROR 3     /* non-finite iterate; the bound is the last valid one */
+
+typedef struct kbnb_problem kbnb_problem;
+
+typedef struct {
+    int32_t n, p, k;   /* rows, features, sparsity budget (1 <= k <= p) */
+    int32_t loss;      /* KBNB_LOSS_* */
+    double lambda2;    /* ridge weight, > 0 */
+    double M;          /* box bound, > 0 */
+    int32_t x_dtype;   /* KBNB_DTYPE_* */
+    int32_t mem_flags; /* KBNB_MEM_* */
+    const void *X;     /* n x p, row-major, leading dimension ldx (elements) */
+    int64_t ldx;
+    const double *y;   /* length n (logistic: entries -1 or +1) */
+    void *hip_stream;  /* reserved (the library runs on its own stream); NULL */
+    uint64_t hbm_budget_bytes; /* device-memory budget of this problem; 0 = 8 GiB */
+    int32_t batch_width;       /* node slots; 0 = chosen from the budget (max 1024) */
+    int32_t cert_period;       /* iterations between float64 certificates; 0 = 8 */
+} kbnb_problem_desc;
+
+typedef struct {
+    uint64_t tag;               /* returned unchanged in the result */
+    int32_t n_in;               /* |J1| <= k */
+    const int32_t *fixed_in;    /* J1, distinct indices in [0, p) */
+    int32_t n_out;              /* |J0| */
+    const int32_t *fixed_out;   /* J0, disjoint from J1 */
+    const double *warm_start;   /* NULL or length p (J0 entries are ignored) */
+    double upper_bound;         /* incumbent for pruning; +inf = solve to rel_tol */
+    double rel_tol;             /* 0 -> 1e-6 */
+    int32_t max_iters;          /* 0 -> 20000 */
+} kbnb_node_desc;
+
+typedef struct {
+    uint64_t tag;
+    double lower_bound;   /* certified float64 dual value, <= the node optimum */
+    double primal_value;  /* float64 primal value of the returned iterate */
+    double rel_gap;       /* (primal_value - lower_bound) / max(|primal_value|, 1e-12) */
+    int32_t status;       /* KBNB_CONVERGED / PRUNED / MAXITER / ERROR */
+    int32_t iterations;
+    int32_t branch_index; /* argmax of |beta_j| over free j (lowest index on ties); -1 if none */
+    int32_t support_len;  /* |J1| + min(kbar, #free): length of the rounding support */
+} kbnb_bound_result;
+
+/*
+ * create_problem -- validate the instance, copy X and y to the device in the
+ * instance's storage type (plus a transposed copy for the X^T R products),
+ * estimate the smoothness constant by power iteration on the device, size
+ * the node-slot batch from the HBM budget, and start the problem's engine.
+ * Passage: Sec. 1 (problem) and App. E.4 (batch sizing from a memory budget).
+ * Returns KBNB_E_INVALID_ARGUMENT for bad sizes/values, KBNB_E_BUDGET_EXCEEDED
+ * if X alone does not fit the budget, KBNB_E_NO_DEVICE / KBNB_E_DEVICE for
+ * runtime failures.  On success *out holds a new handle.
+ */
+int create_problem(const kbnb_problem_desc *desc, kbnb_problem **out);
+
+/* destroy_problem -- cancel queued and running nodes, stop the engine, free
+ * every device and host allocation of the handle.  KBNB_E_BAD_HANDLE on NULL. */
+int destroy_problem(kbnb_problem *prob);
+
+/*
+ * submit_nodes -- queue `count` nodes for bounding; non-blocking.  The nodes
+ * are admitted into free batch slots as they free up (continuous batching)
+ * and iterate on the device until their status is final.
+ * Passage: Sec. 4.1 (assemble a batch of open nodes with constraints and
+ * warm starts), Sec. 3 (node = (J0, J1), kbar = k - |J1|).
+ * The whole call is validated first: indices in [0, p), no duplicates,
+ * J0 and J1 disjoint, |J1| <= k, finite warm start; otherwise nothing is
+ * queued and KBNB_E_INVALID_ARGUMENT is returned.
+ */
+int submit_nodes(kbnb_problem *prob, const kbnb_node_desc *nodes, int32_t count);
+
+/*
+ * poll_bounds -- collect up to `cap` completed nodes, in completion order.
+ * Waits up to timeout_us microseconds for at least one (0 = do not wait,
+ * negative = wait until one completes or nothing is queued or running).
+ * out[i] receives the result; *n_out the number written.  If `supports` is
+ * not NULL it receives, for result i, the rounding support (J1 plus the kbar
+ * largest free |beta_j|, ties to the lowest index; Sec. 4.3) sorted ascending
+ * in supports[i*k .. i*k+support_len-1], the rest set to -1.  If `betas` is
+ * not NULL it receives the float64 iterate of result i in betas[i*p .. +p-1].
+ * Returns KBNB_OK, or KBNB_TIMEOUT if nothing completed in time.
+ */
+int poll_bounds(kbnb_problem *prob, kbnb_bound_result *out, int32_t cap,
+                int32_t *n_out, int32_t *supports, double *betas, int32_t timeout_us);
+
+typedef struct {
+    double time_limit_s;     /* 0 -> no limit */
+    double rel_gap_tol;      /* stop when (UB - LB) / UB <= tol; 0 -> 1e-6 */
+    double node_rel_tol;     /* per-node relative gap; 0 -> 1e-6 */
+    int32_t max_fista_iters; /* per node; 0 -> 20000 */
+    int64_t max_nodes;       /* 0 -> unlimited */
+} kbnb_bnb_options;
+
+typedef struct {
+    double objective;   /* incumbent value v(S) = min over supp beta in S, |beta| <= M */
+    double lower_bound; /* certified global lower bound */
+    double rel_gap;
+    int64_t nodes;      /* nodes bounded */
+    int32_t status;     /* 0 optimal (gap <= tol), 1 time limit, 2 node limit */
+    int32_t support_len;
+    int32_t *support;   /* caller buffer of k entries: incumbent support (ascending) */
+    double *beta;       /* caller buffer of p entries (or NULL): incumbent coefficients */
+    int64_t incumbent_updates;
+    double seconds;
+} kbnb_bnb_result;
+
+/*
+ * branch_and_bound -- blocking best-bound branch and bound built on
+ * submit_nodes / poll_bounds (Sec. 4.1, Fig. 1): the host keeps the open-node
+ * queue; each batch of open nodes is bounded on the device; a node is pruned
+ * when its bound reaches the incumbent; otherwise its rounding support is
+ * re-optimised (Sec. 4.3) to update the incumbent, and the node is branched
+ * on the free coordinate with the largest |beta_j| into z_j = 0 / z_j = 1
+ * children warm-started from the parent iterate.  The problem's queue must be
+ * empty.  result->support must point to k int32 entries.
+ */
+int branch_and_bound(kbnb_problem *prob, const kbnb_bnb_options *opts,
+                     kbnb_bnb_result *result);
+
+/* last_error -- thread-local description of the last failing call. */
+const char *last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Step-level entry points: one step of the hot path over a batch, on the    */
+/* problem's device data, without the iteration loop.  They run the same     */
+/* kernels as the engine and are synchronous.  All arrays are host arrays.    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * prox_batch -- beta_b = prox_{eta G_Nb}(u_b) for m nodes (Sec. 4.2,
+ * "Evaluating proximal operators with non-uniform node structure";
+ * eq. pgd_step_vector_form; App. B PAVA).  states: m x p int8 (0 free,
+ * 1 fixed in, -1 fixed out); u, beta_out: m x p float64 (node-major).
+ * eta > 0.  Uses the problem's k, lambda2 and M.
+ */
+int prox_batch(kbnb_problem *prob, int32_t m, const int8_t *states, const double *u,
+               double eta, double *beta_out);
+
+/*
+ * certify_batch -- float64 primal and dual values for m nodes at the points
+ * beta_b (Sec. 4.4, eqs. batched_dual_candidate_matrix_form,
+ * batched_primal_value_component, batched_dual_value_component):
+ * zeta_b = -grad F(X beta_b), phi_b = F(X beta_b) + 2 lambda2 g_Nb(beta_b),
+ * psi_b = -F*(-zeta_b) - 2 lambda2 g*_Nb(X^T zeta_b / (2 lambda2)).
+ * states: m x p int8; betas: m x p float64.  Outputs phi, psi: m float64;
+ * supports (nullable): m x k int32 rounding supports; branch (nullable): m.
+ */
+int certify_batch(kbnb_problem *prob, int32_t m, const int8_t *states,
+                  const double *betas, double *phi, double *psi,
+                  int32_t *supports, int32_t *branch);
+
+/* Problem facts: p_out[0..5] = n, p, k, batch width, cert period, loss;
+ * d_out[0..3] = smoothness constant L, lambda2, M, device bytes in use. */
+int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KBNB_H */

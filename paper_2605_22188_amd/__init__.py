@@ -1,0 +1,288 @@
+"""Python binding of libkbnb (include/kbnb.h): argument marshalling only.
+
+Every computation happens in the HIP library; this module converts numpy
+arrays to the C structures and back.  There is no fallback: if libkbnb.so is
+missing or cannot be loaded, importing the functions raises.
+
+Functions carry the C names: create_problem, destroy_problem, submit_nodes,
+poll_bounds, branch_and_bound, last_error, prox_batch, certify_batch,
+problem_info.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkbnb.so")
+
+OK, TIMEOUT = 0, 1
+SQUARED, LOGISTIC = 0, 1
+DTYPE_F64, DTYPE_F32, DTYPE_BF16 = 0, 1, 2
+MEM_HOST_COPY, MEM_DEVICE_COPY, MEM_DEVICE_BORROW = 0, 1, 2
+CONVERGED, PRUNED, MAXITER, ERROR = 0, 1, 2, 3
+_DTYPES = {"f64": DTYPE_F64, "f32": DTYPE_F32, "bf16": DTYPE_BF16}
+
+
+class KbnbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"kbnb error {code}: {msg}")
+        self.code = code
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("p", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("loss", ctypes.c_int32), ("lambda2", ctypes.c_double), ("M", ctypes.c_double),
+                ("x_dtype", ctypes.c_int32), ("mem_flags", ctypes.c_int32),
+                ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p),
+                ("hip_stream", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("batch_width", ctypes.c_int32), ("cert_period", ctypes.c_int32)]
+
+
+class NodeDesc(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("n_in", ctypes.c_int32),
+                ("fixed_in", ctypes.c_void_p), ("n_out", ctypes.c_int32),
+                ("fixed_out", ctypes.c_void_p), ("warm_start", ctypes.c_void_p),
+                ("upper_bound", ctypes.c_double), ("rel_tol", ctypes.c_double),
+                ("max_iters", ctypes.c_int32)]
+
+
+class BoundResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("lower_bound", ctypes.c_double),
+                ("primal_value", ctypes.c_double), ("rel_gap", ctypes.c_double),
+                ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("branch_index", ctypes.c_int32), ("support_len", ctypes.c_int32)]
+
+
+class BnbOptions(ctypes.Structure):
+    _fields_ = [("time_limit_s", ctypes.c_double), ("rel_gap_tol", ctypes.c_double),
+                ("node_rel_tol", ctypes.c_double), ("max_fista_iters", ctypes.c_int32),
+                ("max_nodes", ctypes.c_int64)]
+
+
+class BnbResult(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_double), ("lower_bound", ctypes.c_double),
+                ("rel_gap", ctypes.c_double), ("nodes", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("support_len", ctypes.c_int32),
+                ("support", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+                ("incumbent_updates", ctypes.c_int64), ("seconds", ctypes.c_double)]
+
+
+EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
+           "branch_and_bound", "last_error", "prox_batch", "certify_batch", "problem_info"]
+
+_lib = None
+
+
+def load():
+    """Load libkbnb.so; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2605_22188_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        lib.create_problem.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(vp)]
+        lib.destroy_problem.argtypes = [vp]
+        lib.submit_nodes.argtypes = [vp, ctypes.POINTER(NodeDesc), i32]
+        lib.poll_bounds.argtypes = [vp, ctypes.POINTER(BoundResult), i32,
+                                    ctypes.POINTER(i32), vp, vp, i32]
+        lib.branch_and_bound.argtypes = [vp, ctypes.POINTER(BnbOptions), ctypes.POINTER(BnbResult)]
+        lib.last_error.restype = ctypes.c_char_p
+        lib.last_error.argtypes = []
+        lib.prox_batch.argtypes = [vp, i32, vp, vp, dbl, vp]
+        lib.certify_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        lib.problem_info.argtypes = [vp, vp, vp]
+        for name in EXPORTS:
+            if name != "last_error":
+                getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def last_error() -> str:
+    return load().last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise KbnbError(rc, last_error())
+    return rc
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Handle:
+    """Owns a problem handle and the host arrays the library may still read."""
+
+    def __init__(self, ptr, n, p, k, keep):
+        self.ptr = ptr
+        self.n, self.p, self.k = n, p, k
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            try:
+                destroy_problem(self)
+            except Exception:
+                pass
+
+
+def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_period=0,
+                   hbm_budget_bytes=0):
+    """X: host array holding the stored entries (float64 / float32 / uint16
+    bfloat16 bits), or a torch CUDA tensor (copied on the device)."""
+    lib = load()
+    xd = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    keep = []
+    if hasattr(X, "is_cuda") and X.is_cuda:
+        n, p = X.shape
+        Xc = X.contiguous()
+        keep.append(Xc)
+        xptr, ldx, mem = ctypes.c_void_p(Xc.data_ptr()), p, MEM_DEVICE_COPY
+        yc = y.contiguous().double()
+        keep.append(yc)
+        yptr = ctypes.c_void_p(yc.data_ptr())
+    else:
+        want = {DTYPE_F64: np.float64, DTYPE_F32: np.float32, DTYPE_BF16: np.uint16}[xd]
+        Xa = np.ascontiguousarray(X, dtype=want)
+        n, p = Xa.shape
+        ya = np.ascontiguousarray(y, dtype=np.float64)
+        keep += [Xa, ya]
+        xptr, ldx, mem, yptr = _p(Xa), p, MEM_HOST_COPY, _p(ya)
+    d = ProblemDesc(n=n, p=p, k=int(k), loss=int(loss), lambda2=float(lambda2), M=float(M),
+                    x_dtype=xd, mem_flags=mem, X=xptr, ldx=ldx, y=yptr, hip_stream=None,
+                    hbm_budget_bytes=int(hbm_budget_bytes), batch_width=int(batch_width),
+                    cert_period=int(cert_period))
+    out = ctypes.c_void_p()
+    _check(lib.create_problem(ctypes.byref(d), ctypes.byref(out)))
+    return Handle(out, n, p, int(k), keep if mem != MEM_HOST_COPY else [])
+
+
+def destroy_problem(h: Handle):
+    if h.ptr:
+        ptr, h.ptr = h.ptr, None
+        _check(load().destroy_problem(ptr))
+
+
+def submit_nodes(h: Handle, nodes, upper_bound=math.inf, rel_tol=0.0, max_iters=0, tags=None,
+                 warm_starts=None):
+    """nodes: sequence of (fixed_in, fixed_out) index arrays (or objects with
+    .fixed_in / .fixed_out).  Per-node upper_bound / rel_tol / max_iters may be
+    scalars or sequences."""
+    count = len(nodes)
+    arr = (NodeDesc * max(count, 1))()
+    keep = []
+
+    def pick(v, i):
+        return v[i] if hasattr(v, "__len__") else v
+    for i, nd in enumerate(nodes):
+        fin, fout = (nd.fixed_in, nd.fixed_out) if hasattr(nd, "fixed_in") else nd
+        fin = np.ascontiguousarray(fin, dtype=np.int32)
+        fout = np.ascontiguousarray(fout, dtype=np.int32)
+        keep += [fin, fout]
+        w = None
+        if warm_starts is not None and warm_starts[i] is not None:
+            w = np.ascontiguousarray(warm_starts[i], dtype=np.float64)
+            keep.append(w)
+        arr[i] = NodeDesc(tag=int(tags[i]) if tags is not None else i, n_in=len(fin),
+                          fixed_in=_p(fin) if len(fin) else None, n_out=len(fout),
+                          fixed_out=_p(fout) if len(fout) else None,
+                          warm_start=_p(w) if w is not None else None,
+                          upper_bound=float(pick(upper_bound, i)),
+                          rel_tol=float(pick(rel_tol, i)), max_iters=int(pick(max_iters, i)))
+    _check(load().submit_nodes(h.ptr, arr, count))
+
+
+def poll_bounds(h: Handle, cap=1024, timeout_us=-1, supports=True, betas=True):
+    """Returns a list of dicts (tag, lower_bound, primal_value, rel_gap, status,
+    iterations, branch_index, support, beta)."""
+    out = (BoundResult * cap)()
+    n = ctypes.c_int32(0)
+    sup = np.empty((cap, h.k), np.int32) if supports else None
+    bet = np.empty((cap, h.p), np.float64) if betas else None
+    rc = _check(load().poll_bounds(h.ptr, out, cap, ctypes.byref(n), _p(sup), _p(bet),
+                                   int(timeout_us)))
+    res = []
+    for i in range(n.value):
+        r = out[i]
+        d = dict(tag=r.tag, lower_bound=r.lower_bound, primal_value=r.primal_value,
+                 rel_gap=r.rel_gap, status=r.status, iterations=r.iterations,
+                 branch_index=r.branch_index, support_len=r.support_len)
+        if supports:
+            d["support"] = sup[i, :r.support_len].copy()
+        if betas:
+            d["beta"] = bet[i].copy()
+        res.append(d)
+    return res, rc
+
+
+def bound_nodes(h: Handle, nodes, **kw):
+    """Submit `nodes` and wait for all of them; results ordered like `nodes`."""
+    submit_nodes(h, nodes, tags=list(range(len(nodes))), **kw)
+    got = {}
+    while len(got) < len(nodes):
+        res, rc = poll_bounds(h, cap=max(1, len(nodes)), timeout_us=-1)
+        for r in res:
+            got[r["tag"]] = r
+        if not res and rc == TIMEOUT:
+            raise KbnbError(-4, "engine idle with nodes outstanding")
+    return [got[i] for i in range(len(nodes))]
+
+
+def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=0.0,
+                     max_fista_iters=0, max_nodes=0):
+    sup = np.full(h.k, -1, np.int32)
+    beta = np.zeros(h.p)
+    o = BnbOptions(time_limit_s=time_limit_s, rel_gap_tol=rel_gap_tol,
+                   node_rel_tol=node_rel_tol, max_fista_iters=max_fista_iters,
+                   max_nodes=max_nodes)
+    r = BnbResult(support=_p(sup), beta=_p(beta))
+    _check(load().branch_and_bound(h.ptr, ctypes.byref(o), ctypes.byref(r)))
+    return dict(objective=r.objective, lower_bound=r.lower_bound, rel_gap=r.rel_gap,
+                nodes=r.nodes, status=r.status, support=sup[:r.support_len].copy(),
+                beta=beta, incumbent_updates=r.incumbent_updates, seconds=r.seconds)
+
+
+def prox_batch(h: Handle, states, u, eta):
+    st = np.ascontiguousarray(states, dtype=np.int8)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    m = st.shape[0]
+    assert st.shape == (m, h.p) and uu.shape == (m, h.p)
+    out = np.empty((m, h.p))
+    _check(load().prox_batch(h.ptr, m, _p(st), _p(uu), float(eta), _p(out)))
+    return out
+
+
+def certify_batch(h: Handle, states, betas):
+    st = np.ascontiguousarray(states, dtype=np.int8)
+    bb = np.ascontiguousarray(betas, dtype=np.float64)
+    m = st.shape[0]
+    assert st.shape == (m, h.p) and bb.shape == (m, h.p)
+    phi, psi = np.empty(m), np.empty(m)
+    sup = np.empty((m, h.k), np.int32)
+    br = np.empty(m, np.int32)
+    _check(load().certify_batch(h.ptr, m, _p(st), _p(bb), _p(phi), _p(psi), _p(sup), _p(br)))
+    return phi, psi, sup, br
+
+
+def problem_info(h: Handle):
+    i = np.zeros(8, np.int64)
+    d = np.zeros(4)
+    _check(load().problem_info(h.ptr, _p(i), _p(d)))
+    return dict(n=int(i[0]), p=int(i[1]), k=int(i[2]), batch_width=int(i[3]),
+                cert_period=int(i[4]), loss=int(i[5]), gsplit=int(i[6]), rounds=int(i[7]),
+                L=float(d[0]), lambda2=float(d[1]), M=float(d[2]), device_bytes=float(d[3]))
+
+
+def create_from_instance(inst, **kw):
+    """Convenience: create a problem from a workloads.Instance-like object
+    (fields X_store, dtype, y, k, loss, lambda2, M)."""
+    return create_problem(inst.X_store, inst.y, inst.k, inst.loss, inst.lambda2, inst.M,
+                          dtype=inst.dtype, **kw)

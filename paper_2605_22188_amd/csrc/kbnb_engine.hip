@@ -1,0 +1,889 @@
+// kbnb_engine.hip -- host side of libkbnb: problem setup, the node-slot engine
+// (continuous batching over a fixed set of device slots), the C ABI of
+// include/kbnb.h and the branch-and-bound driver.
+//
+// Engine round (one worker thread per problem, one HIP stream):
+//   1. admit queued nodes into free slots (one H2D copy of packed records and
+//      one scatter kernel);
+//   2. replay the captured graph: `cert_period` FISTA steps (fwd, bwd, prox)
+//      followed by the float64 certificate (cfwd, cbwd, cfin);
+//   3. copy the per-slot status arrays back, retire the slots whose status is
+//      final (their iterates are gathered into one buffer and copied back),
+//      and hand the results to poll_bounds.
+// Slots that finish are refilled at the next round while the others keep
+// iterating, so the batch stays full while work is queued (Sec. 4.1 batch
+// assembly; App. E.4 sizing replaced by a device-memory budget).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <queue>
+#include <set>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/kbnb.h"
+#include "kbnb_internal.h"
+
+using namespace kbnb;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(KBNB_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+extern "C" const char *last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// problem object
+// ---------------------------------------------------------------------------
+struct PendingNode {
+    uint64_t tag;
+    std::vector<int8_t> st;  // ldp entries
+    std::vector<double> warm; // empty or p entries
+    int kbar;
+    double ub, tol;
+    int max_iter;
+};
+
+struct DoneNode {
+    kbnb_bound_result r;
+    std::vector<int32_t> sup;
+    std::vector<double> beta;
+};
+
+struct kbnb_problem {
+    // instance
+    int n = 0, p = 0, k = 0, loss = 0, xtype = 0;
+    double lambda2 = 0, M = 0, L = 0, eta = 0;
+    bool iter_f64 = false;
+    int ti_bytes = 4;
+    // sizes
+    int ldp = 0, npad = 0, pm = 0, m = 0, mpad = 0;
+    int gsplit = 1, gchunk = 0, qsplit = 1, qchunk = 0, tiles_n = 0;
+    int cert_period = 8;
+    uint64_t budget = 0, bytes = 0;
+    // device memory
+    void *arena = nullptr;
+    bool own_x = true;
+    void *X = nullptr, *XT = nullptr, *Yi = nullptr, *R = nullptr, *Gp = nullptr;
+    double *y = nullptr, *B = nullptr, *Bprev = nullptr, *Z = nullptr, *Qp = nullptr;
+    double *lsum = nullptr, *csum = nullptr, *gbuf = nullptr;
+    int8_t *st = nullptr;
+    uint8_t *stage_d = nullptr;
+    int32_t *gslots_d = nullptr;
+    SlotState ss{};
+    // pinned host mirrors
+    uint8_t *stage_h = nullptr;
+    int rec_bytes = 0;
+    int32_t *h_status = nullptr, *h_iter = nullptr, *h_jstar = nullptr, *h_slen = nullptr, *h_sup = nullptr;
+    double *h_lb = nullptr, *h_phi = nullptr, *h_gap = nullptr;
+    int32_t *h_gslots = nullptr;
+    double *h_gbuf = nullptr;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    Consts c{};
+    // engine
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<PendingNode> pending;
+    std::deque<DoneNode> done;
+    std::vector<uint64_t> slot_tag;
+    std::vector<int> free_slots;
+    int active = 0;
+    bool shutdown = false;
+    bool busy = false;  // a round is in flight
+    int engine_error = 0;
+    std::string engine_msg;
+    std::mutex api_mu;  // serialises calls on this handle
+    // stats
+    std::atomic<long> rounds{0};
+};
+
+static int round_pow2_down(int64_t v)
+{
+    int r = 1;
+    while ((int64_t)r * 2 <= v) r *= 2;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// per-slot bytes and arena layout
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t off[32];
+    size_t total;
+};
+
+static size_t per_slot_bytes(const kbnb_problem *P)
+{
+    const size_t ti = P->ti_bytes;
+    size_t b = 0;
+    b += (size_t)P->ldp * (ti + 8 + 8 + 1);            // Yi, B, Bprev, st
+    b += (size_t)P->npad * (ti + 8);                   // R, Z
+    b += (size_t)P->gsplit * P->ldp * ti;              // Gp
+    b += (size_t)P->qsplit * P->ldp * 8;               // Qp
+    b += (size_t)P->tiles_n * 16;                      // lsum, csum
+    b += (size_t)P->ldp * 8 + 128 + P->k * 4;          // gather buffer, scalars, support
+    return b;
+}
+
+static void choose_splits(kbnb_problem *P)
+{
+    // backward products: enough workgroups to cover the 256 CUs a few times
+    const int tiles = (P->pm / GEMM_BM) * (P->mpad / GEMM_BN);
+    const int kt = P->npad / GEMM_BK;  // 16-wide k chunks
+    int want = std::max(1, (768 + tiles - 1) / tiles);
+    want = std::min(want, std::max(1, kt / 4));
+    int chunk = (int)round_up((P->npad + want - 1) / want, GEMM_BK);
+    P->gchunk = chunk;
+    P->gsplit = (P->npad + chunk - 1) / chunk;
+    P->qchunk = chunk;
+    P->qsplit = P->gsplit;
+}
+
+static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
+{
+    const size_t ti = P->ti_bytes;
+    const size_t mp = P->mpad;
+    std::vector<std::pair<void **, size_t>> items;
+    size_t sizes[] = {
+        P->own_x ? xbytes : 0,                   // X
+        (size_t)P->pm * P->npad * xel,           // XT
+        (size_t)P->npad * 8,                     // y
+        mp * P->ldp * ti,                        // Yi
+        mp * P->npad * ti,                       // R
+        (size_t)P->gsplit * mp * P->ldp * ti,    // Gp
+        mp * P->ldp * 8,                         // B
+        mp * P->ldp * 8,                         // Bprev
+        mp * P->npad * 8,                        // Z
+        (size_t)P->qsplit * mp * P->ldp * 8,     // Qp
+        (size_t)P->tiles_n * mp * 8,             // lsum
+        (size_t)P->tiles_n * mp * 8,             // csum
+        mp * P->ldp,                             // st
+        mp * P->rec_bytes,                       // stage
+        mp * 4,                                  // gather slots
+        mp * P->ldp * 8,                         // gather buffer
+        mp * 8 * 7,                              // double slot arrays
+        mp * 4 * 7,                              // int slot arrays
+        mp * P->k * 4,                           // supports
+    };
+    const int nitems = sizeof(sizes) / sizeof(sizes[0]);
+    size_t off[32];
+    size_t total = 0;
+    for (int i = 0; i < nitems; ++i) {
+        off[i] = total;
+        total += round_up(sizes[i], 256);
+    }
+    if (P->budget && total > P->budget)
+        return fail(KBNB_E_BUDGET_EXCEEDED, "problem needs %zu bytes, budget %llu", total,
+                    (unsigned long long)P->budget);
+    void *a = nullptr;
+    hipError_t e = hipMalloc(&a, total);
+    if (e != hipSuccess) return fail(KBNB_E_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+    e = hipMemsetAsync(a, 0, total, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(a);
+        return fail(KBNB_E_DEVICE, "clearing device memory failed: %s", hipGetErrorString(e));
+    }
+    P->arena = a;
+    P->bytes = total;
+    char *base = (char *)a;
+    if (P->own_x) P->X = base + off[0];
+    P->XT = base + off[1];
+    P->y = (double *)(base + off[2]);
+    P->Yi = base + off[3];
+    P->R = base + off[4];
+    P->Gp = base + off[5];
+    P->B = (double *)(base + off[6]);
+    P->Bprev = (double *)(base + off[7]);
+    P->Z = (double *)(base + off[8]);
+    P->Qp = (double *)(base + off[9]);
+    P->lsum = (double *)(base + off[10]);
+    P->csum = (double *)(base + off[11]);
+    P->st = (int8_t *)(base + off[12]);
+    P->stage_d = (uint8_t *)(base + off[13]);
+    P->gslots_d = (int32_t *)(base + off[14]);
+    P->gbuf = (double *)(base + off[15]);
+    double *dd = (double *)(base + off[16]);
+    int32_t *ii = (int32_t *)(base + off[17]);
+    P->ss.theta = dd + 0 * mp;
+    P->ss.tmom = dd + 1 * mp;
+    P->ss.lb = dd + 2 * mp;
+    P->ss.phi = dd + 3 * mp;
+    P->ss.gap = dd + 4 * mp;
+    P->ss.ub = dd + 5 * mp;
+    P->ss.tol = dd + 6 * mp;
+    P->ss.status = ii + 0 * mp;
+    P->ss.iter = ii + 1 * mp;
+    P->ss.max_iter = ii + 2 * mp;
+    P->ss.kbar = ii + 3 * mp;
+    P->ss.jstar = ii + 4 * mp;
+    P->ss.slen = ii + 5 * mp;
+    P->ss.sup = (int32_t *)(base + off[18]);
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// graph of one engine round
+// ---------------------------------------------------------------------------
+static void enqueue_round(kbnb_problem *P)
+{
+    hipStream_t s = P->stream;
+    for (int it = 0; it < P->cert_period; ++it) {
+        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, P->c);
+        launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c);
+        launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
+    }
+    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c);
+    launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c);
+    launch_cert_finish(s, P->Qp, P->qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
+}
+
+static int build_graph(kbnb_problem *P)
+{
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return -1;
+    enqueue_round(P);
+    if (hipStreamEndCapture(P->stream, &g) != hipSuccess || !g) return -1;
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return -1;
+    P->graph = ge;
+    return 0;
+}
+
+__global__ void k_retire(const int32_t *__restrict__ slots, int count, int32_t *__restrict__ status)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < count) status[slots[r]] = SLOT_EMPTY;
+}
+
+__global__ void k_gather_cols(const double *__restrict__ B, int ldp, int p,
+                              const int32_t *__restrict__ slots, double *__restrict__ out)
+{
+    const int r = blockIdx.x;
+    const int64_t src = (int64_t)slots[r] * ldp;
+    for (int j = threadIdx.x; j < p; j += blockDim.x) out[(int64_t)r * p + j] = B[src + j];
+}
+
+// ---------------------------------------------------------------------------
+// engine worker
+// ---------------------------------------------------------------------------
+static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
+{
+    // 1. admission
+    int nadm = 0;
+    std::vector<int> adm_slots;
+    while (!P->pending.empty() && !P->free_slots.empty()) {
+        PendingNode nd = std::move(P->pending.front());
+        P->pending.pop_front();
+        const int slot = P->free_slots.back();
+        P->free_slots.pop_back();
+        uint8_t *rec = P->stage_h + (size_t)nadm * P->rec_bytes;
+        AdmitRec h{};
+        h.slot = slot;
+        h.kbar = nd.kbar;
+        h.max_iter = nd.max_iter;
+        h.has_warm = nd.warm.empty() ? 0 : 1;
+        h.ub = nd.ub;
+        h.tol = nd.tol;
+        memcpy(rec, &h, sizeof h);
+        memcpy(rec + sizeof(AdmitRec), nd.st.data(), P->ldp);
+        if (h.has_warm) {
+            const size_t woff = round_up(sizeof(AdmitRec) + P->ldp, 8);
+            memcpy(rec + woff, nd.warm.data(), sizeof(double) * P->p);
+        }
+        P->slot_tag[slot] = nd.tag;
+        ++P->active;
+        ++nadm;
+        adm_slots.push_back(slot);
+    }
+    if (P->active == 0) return 0;
+    P->busy = true;
+    lk.unlock();
+    hipStream_t s = P->stream;
+    int rc = 0;
+    do {
+        if (nadm) {
+            HIP_TRY(hipMemcpyAsync(P->stage_d, P->stage_h, (size_t)nadm * P->rec_bytes, hipMemcpyHostToDevice, s));
+            launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
+        }
+        if (P->graph) {
+            HIP_TRY(hipGraphLaunch(P->graph, s));
+        } else {
+            enqueue_round(P);
+        }
+        const size_t mb = (size_t)P->m;
+        HIP_TRY(hipMemcpyAsync(P->h_status, P->ss.status, mb * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(P->h_iter, P->ss.iter, mb * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(P->h_jstar, P->ss.jstar, mb * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(P->h_slen, P->ss.slen, mb * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(P->h_sup, P->ss.sup, mb * P->k * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(P->h_lb, P->ss.lb, mb * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(P->h_phi, P->ss.phi, mb * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(P->h_gap, P->ss.gap, mb * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        // 3. retire finished slots
+        int nfin = 0;
+        for (int b = 0; b < P->m; ++b) {
+            const int stt = P->h_status[b];
+            if (stt >= 0) P->h_gslots[nfin++] = b;
+        }
+        if (nfin) {
+            HIP_TRY(hipMemcpyAsync(P->gslots_d, P->h_gslots, (size_t)nfin * 4, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_gather_cols, dim3(nfin), dim3(256), 0, s, P->B, P->ldp, P->p, P->gslots_d, P->gbuf);
+            HIP_TRY(hipMemcpyAsync(P->h_gbuf, P->gbuf, (size_t)nfin * P->p * 8, hipMemcpyDeviceToHost, s));
+            // retired slots must not iterate again
+            hipLaunchKernelGGL(k_retire, dim3((nfin + 255) / 256), dim3(256), 0, s, P->gslots_d, nfin, P->ss.status);
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        lk.lock();
+        for (int r = 0; r < nfin; ++r) {
+            const int b = P->h_gslots[r];
+            DoneNode d;
+            d.r.tag = P->slot_tag[b];
+            d.r.lower_bound = P->h_lb[b];
+            d.r.primal_value = P->h_phi[b];
+            d.r.rel_gap = P->h_gap[b];
+            d.r.status = P->h_status[b];
+            d.r.iterations = P->h_iter[b];
+            d.r.branch_index = P->h_jstar[b];
+            d.r.support_len = P->h_slen[b];
+            d.sup.assign(P->h_sup + (size_t)b * P->k, P->h_sup + (size_t)(b + 1) * P->k);
+            d.beta.assign(P->h_gbuf + (size_t)r * P->p, P->h_gbuf + (size_t)(r + 1) * P->p);
+            P->done.push_back(std::move(d));
+            P->free_slots.push_back(b);
+            --P->active;
+        }
+        P->busy = false;
+        P->rounds++;
+        P->cv_done.notify_all();
+        return 0;
+    } while (0);
+    lk.lock();
+    P->busy = false;
+    return rc;
+}
+
+static void engine_main(kbnb_problem *P)
+{
+    std::unique_lock<std::mutex> lk(P->mu);
+    for (;;) {
+        P->cv_work.wait(lk, [&] { return P->shutdown || P->active > 0 || !P->pending.empty(); });
+        if (P->shutdown) break;
+        int rc = engine_round(P, lk);
+        if (rc != 0) {
+            P->engine_error = rc;
+            P->engine_msg = g_last_error;
+            // fail every queued and running node
+            P->pending.clear();
+            P->busy = false;
+            P->cv_done.notify_all();
+            break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// power iteration for lambda_max(X^T X), float64, on the device
+// ---------------------------------------------------------------------------
+static int estimate_L(kbnb_problem *P)
+{
+    const int n = P->n, p = P->p;
+    double *dv = nullptr, *ds = nullptr, *dw = nullptr;
+    HIP_TRY(hipMalloc(&dv, sizeof(double) * p));
+    HIP_TRY(hipMalloc(&ds, sizeof(double) * P->npad));
+    HIP_TRY(hipMalloc(&dw, sizeof(double) * p));
+    std::vector<double> v(p), w(p);
+    // deterministic start with no special direction: splitmix-style hashing
+    double nrm = 0;
+    for (int j = 0; j < p; ++j) {
+        uint64_t z = 0x9E3779B97F4A7C15ull * (uint64_t)(j + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v[j] = 0.5 + (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        nrm += v[j] * v[j];
+    }
+    nrm = std::sqrt(nrm);
+    for (auto &x : v) x /= nrm;
+    double lam = 0, prev = 0;
+    int rc = 0;
+    for (int it = 0; it < 3000; ++it) {
+        if (hipMemcpyAsync(dv, v.data(), sizeof(double) * p, hipMemcpyHostToDevice, P->stream) != hipSuccess) { rc = -1; break; }
+        launch_matvec_f64(P->stream, P->xtype, P->X, P->ldp, n, p, dv, ds);
+        launch_matvec_f64(P->stream, P->xtype, P->XT, P->npad, p, n, ds, dw);
+        if (hipMemcpyAsync(w.data(), dw, sizeof(double) * p, hipMemcpyDeviceToHost, P->stream) != hipSuccess) { rc = -1; break; }
+        if (hipStreamSynchronize(P->stream) != hipSuccess) { rc = -1; break; }
+        double rq = 0, ww = 0;
+        for (int j = 0; j < p; ++j) {
+            rq += v[j] * w[j];
+            ww += w[j] * w[j];
+        }
+        ww = std::sqrt(ww);
+        if (!(ww > 0)) break;
+        for (int j = 0; j < p; ++j) v[j] = w[j] / ww;
+        lam = rq;
+        if (it > 20 && std::fabs(lam - prev) <= 1e-12 * lam) break;
+        prev = lam;
+    }
+    (void)hipFree(dv);
+    (void)hipFree(ds);
+    (void)hipFree(dw);
+    if (rc) return fail(KBNB_E_DEVICE, "power iteration failed");
+    const double cl = (P->loss == KBNB_LOSS_SQUARED) ? 2.0 : 0.25;
+    P->L = 1.02 * cl * std::max(lam, 1e-300);
+    P->eta = 1.0 / P->L;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy
+// ---------------------------------------------------------------------------
+static int device_ok()
+{
+    int cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0)
+        return fail(KBNB_E_NO_DEVICE, "no HIP device is visible");
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(KBNB_E_NO_DEVICE, "hipGetDeviceProperties failed");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(KBNB_E_NO_DEVICE, "device %s is not gfx950", prop.gcnArchName);
+    return 0;
+}
+
+static void free_problem(kbnb_problem *P)
+{
+    if (!P) return;
+    if (P->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> g(P->mu);
+            P->shutdown = true;
+        }
+        P->cv_work.notify_all();
+        P->worker.join();
+    }
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    if (P->graph) (void)hipGraphExecDestroy(P->graph);
+    if (P->arena) (void)hipFree(P->arena);
+    void *pins[] = {P->stage_h, P->h_status, P->h_iter, P->h_jstar, P->h_slen, P->h_sup,
+                    P->h_lb, P->h_phi, P->h_gap, P->h_gslots, P->h_gbuf};
+    for (void *q : pins)
+        if (q) (void)hipHostFree(q);
+    if (P->stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+}
+
+extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
+{
+    if (!d || !out) return fail(KBNB_E_INVALID_ARGUMENT, "NULL argument");
+    *out = nullptr;
+    if (d->n <= 0 || d->p <= 0 || d->k <= 0 || d->k > d->p)
+        return fail(KBNB_E_INVALID_ARGUMENT, "need n > 0, 0 < k <= p (n=%d p=%d k=%d)", d->n, d->p, d->k);
+    if (d->p > 2048) return fail(KBNB_E_INVALID_ARGUMENT, "p=%d exceeds the supported maximum 2048", d->p);
+    if (d->k > 128) return fail(KBNB_E_INVALID_ARGUMENT, "k=%d exceeds the supported maximum 128", d->k);
+    if (d->loss != KBNB_LOSS_SQUARED && d->loss != KBNB_LOSS_LOGISTIC)
+        return fail(KBNB_E_INVALID_ARGUMENT, "unknown loss %d", d->loss);
+    if (!(d->lambda2 > 0) || !std::isfinite(d->lambda2) || !(d->M > 0) || !std::isfinite(d->M))
+        return fail(KBNB_E_INVALID_ARGUMENT, "lambda2 and M must be finite and positive");
+    if (d->x_dtype < 0 || d->x_dtype > 2) return fail(KBNB_E_INVALID_ARGUMENT, "unknown x_dtype %d", d->x_dtype);
+    if (d->mem_flags < 0 || d->mem_flags > 2) return fail(KBNB_E_INVALID_ARGUMENT, "unknown mem_flags %d", d->mem_flags);
+    if (!d->X || !d->y) return fail(KBNB_E_INVALID_ARGUMENT, "X and y must be given");
+    if (d->ldx < d->p) return fail(KBNB_E_INVALID_ARGUMENT, "ldx=%lld < p", (long long)d->ldx);
+    if (d->batch_width < 0 || d->batch_width > 4096) return fail(KBNB_E_INVALID_ARGUMENT, "batch_width out of range");
+    if (d->cert_period < 0 || d->cert_period > 1000) return fail(KBNB_E_INVALID_ARGUMENT, "cert_period out of range");
+    int rc = device_ok();
+    if (rc) return rc;
+    if (d->mem_flags == KBNB_MEM_HOST_COPY) {
+        for (int i = 0; i < d->n; ++i) {
+            const double yi = d->y[i];
+            if (!std::isfinite(yi)) return fail(KBNB_E_INVALID_ARGUMENT, "y[%d] is not finite", i);
+            if (d->loss == KBNB_LOSS_LOGISTIC && yi != 1.0 && yi != -1.0)
+                return fail(KBNB_E_INVALID_ARGUMENT, "logistic y[%d]=%g is not +-1", i, yi);
+        }
+    }
+
+    kbnb_problem *P = new kbnb_problem();
+    P->n = d->n; P->p = d->p; P->k = d->k; P->loss = d->loss;
+    P->lambda2 = d->lambda2; P->M = d->M;
+    P->xtype = d->x_dtype;
+    P->iter_f64 = (d->x_dtype == KBNB_DTYPE_F64);
+    P->ti_bytes = P->iter_f64 ? 8 : 4;
+    P->ldp = (int)round_up(P->p, 16);
+    P->npad = (int)round_up(P->n, 64);
+    P->pm = (int)round_up(P->ldp, 64);
+    P->tiles_n = P->npad / GEMM_BM;
+    P->cert_period = d->cert_period ? d->cert_period : 8;
+    P->budget = d->hbm_budget_bytes ? d->hbm_budget_bytes : (8ull << 30);
+    P->own_x = (d->mem_flags != KBNB_MEM_DEVICE_BORROW);
+    const size_t xel = (d->x_dtype == KBNB_DTYPE_F64) ? 8 : (d->x_dtype == KBNB_DTYPE_F32 ? 4 : 2);
+    const size_t xbytes = (size_t)P->npad * P->ldp * xel;
+    P->rec_bytes = (int)round_up(round_up(sizeof(AdmitRec) + P->ldp, 8) + 8 * (size_t)P->ldp, 256);
+
+    if (hipStreamCreate(&P->stream) != hipSuccess) {
+        delete P;
+        return fail(KBNB_E_DEVICE, "hipStreamCreate failed");
+    }
+    // batch width from the budget
+    int m = d->batch_width;
+    if (m == 0) {
+        P->mpad = 64; P->m = 64;
+        choose_splits(P);
+        const size_t fixed = 2 * xbytes + (size_t)P->npad * 8 + (1 << 20);
+        const size_t per = per_slot_bytes(P) + P->rec_bytes;
+        int64_t cap = (P->budget > fixed) ? (int64_t)((P->budget - fixed) / per) : 0;
+        if (cap < 1) {
+            free_problem(P);
+            return fail(KBNB_E_BUDGET_EXCEEDED, "the budget cannot hold X and one node slot");
+        }
+        m = std::min<int64_t>(1024, round_pow2_down(cap));
+    }
+    P->m = m;
+    P->mpad = (int)round_up(m, GEMM_BN);
+    choose_splits(P);
+    P->slot_tag.assign(P->m, 0);
+    for (int b = P->m - 1; b >= 0; --b) P->free_slots.push_back(b);
+
+    rc = alloc_arena(P, xbytes, xel);
+    if (rc) { free_problem(P); return rc; }
+    if (P->own_x) {
+        if (d->mem_flags == KBNB_MEM_HOST_COPY) {
+            hipError_t e = hipMemcpy2D(P->X, (size_t)P->ldp * xel, d->X, (size_t)d->ldx * xel,
+                                       (size_t)P->p * xel, P->n, hipMemcpyHostToDevice);
+            if (e != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "copying X failed: %s", hipGetErrorString(e)); }
+        } else {
+            hipError_t e = hipMemcpy2D(P->X, (size_t)P->ldp * xel, d->X, (size_t)d->ldx * xel,
+                                       (size_t)P->p * xel, P->n, hipMemcpyDeviceToDevice);
+            if (e != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "copying X failed: %s", hipGetErrorString(e)); }
+        }
+    } else {
+        if (d->ldx != P->ldp) { free_problem(P); return fail(KBNB_E_INVALID_ARGUMENT, "DEVICE_BORROW needs ldx == %d", P->ldp); }
+        P->X = const_cast<void *>(d->X);
+    }
+    {
+        hipError_t e = hipMemcpy(P->y, d->y, sizeof(double) * P->n,
+                                 d->mem_flags == KBNB_MEM_HOST_COPY ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "copying y failed: %s", hipGetErrorString(e)); }
+    }
+    launch_transpose(P->stream, P->xtype, P->X, P->XT, P->n, P->p, P->ldp, P->npad, P->pm);
+    if (hipStreamSynchronize(P->stream) != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "transpose failed"); }
+    // pinned host mirrors
+    {
+        const size_t mb = P->mpad;
+        bool okp = hipHostMalloc((void **)&P->stage_h, mb * P->rec_bytes, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_status, mb * 4, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_iter, mb * 4, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_jstar, mb * 4, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_slen, mb * 4, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_sup, mb * P->k * 4, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_lb, mb * 8, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_phi, mb * 8, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_gap, mb * 8, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_gslots, mb * 4, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_gbuf, mb * P->p * 8, 0) == hipSuccess;
+        if (!okp) { free_problem(P); return fail(KBNB_E_OUT_OF_MEMORY, "pinned host allocation failed"); }
+    }
+    // all slots start empty
+    {
+        std::vector<int32_t> empty(P->mpad, SLOT_EMPTY);
+        if (hipMemcpy(P->ss.status, empty.data(), 4 * P->mpad, hipMemcpyHostToDevice) != hipSuccess) {
+            free_problem(P);
+            return fail(KBNB_E_DEVICE, "slot init failed");
+        }
+    }
+    rc = estimate_L(P);
+    if (rc) { free_problem(P); return rc; }
+    P->c.n = P->n; P->c.p = P->p; P->c.k = P->k; P->c.loss = P->loss;
+    P->c.ldp = P->ldp; P->c.npad = P->npad; P->c.pm = P->pm; P->c.mpad = P->mpad; P->c.m = P->m;
+    P->c.lambda2 = P->lambda2; P->c.M = P->M; P->c.eta = P->eta;
+    if (build_graph(P) != 0) {
+        (void)hipGetLastError();
+        P->graph = nullptr;  // direct launches each round
+    }
+    if (hipStreamSynchronize(P->stream) != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "setup failed"); }
+    P->worker = std::thread(engine_main, P);
+    *out = P;
+    return KBNB_OK;
+}
+
+extern "C" int destroy_problem(kbnb_problem *P)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    free_problem(P);
+    return KBNB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// submit / poll
+// ---------------------------------------------------------------------------
+static int build_state(const kbnb_problem *P, const kbnb_node_desc &nd, std::vector<int8_t> &st, int &kbar)
+{
+    st.assign(P->ldp, -1);
+    for (int j = 0; j < P->p; ++j) st[j] = 0;
+    if (nd.n_in < 0 || nd.n_out < 0) return fail(KBNB_E_INVALID_ARGUMENT, "negative set size");
+    if (nd.n_in > P->k) return fail(KBNB_E_INVALID_ARGUMENT, "|J1|=%d exceeds k=%d", nd.n_in, P->k);
+    if ((nd.n_in && !nd.fixed_in) || (nd.n_out && !nd.fixed_out)) return fail(KBNB_E_INVALID_ARGUMENT, "NULL index list");
+    for (int r = 0; r < nd.n_in; ++r) {
+        const int j = nd.fixed_in[r];
+        if (j < 0 || j >= P->p) return fail(KBNB_E_INVALID_ARGUMENT, "fixed_in index %d out of range", j);
+        if (st[j] != 0) return fail(KBNB_E_INVALID_ARGUMENT, "duplicate index %d", j);
+        st[j] = 1;
+    }
+    for (int r = 0; r < nd.n_out; ++r) {
+        const int j = nd.fixed_out[r];
+        if (j < 0 || j >= P->p) return fail(KBNB_E_INVALID_ARGUMENT, "fixed_out index %d out of range", j);
+        if (st[j] != 0) return fail(KBNB_E_INVALID_ARGUMENT, "index %d is fixed twice", j);
+        st[j] = -1;
+    }
+    kbar = P->k - nd.n_in;
+    return 0;
+}
+
+static int submit_locked(kbnb_problem *P, const kbnb_node_desc *nodes, int count)
+{
+    std::vector<PendingNode> staged;
+    staged.reserve(count);
+    for (int i = 0; i < count; ++i) {
+        const kbnb_node_desc &nd = nodes[i];
+        PendingNode pn;
+        int rc = build_state(P, nd, pn.st, pn.kbar);
+        if (rc) return fail(rc, "node %d: %s", i, g_last_error.c_str());
+        if (nd.warm_start) {
+            pn.warm.assign(nd.warm_start, nd.warm_start + P->p);
+            for (int j = 0; j < P->p; ++j)
+                if (!std::isfinite(pn.warm[j])) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: warm start not finite", i);
+        }
+        if (std::isnan(nd.upper_bound)) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: upper bound is NaN", i);
+        if (nd.rel_tol < 0 || std::isnan(nd.rel_tol)) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: bad rel_tol", i);
+        if (nd.max_iters < 0) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: negative max_iters", i);
+        pn.tag = nd.tag;
+        pn.ub = nd.upper_bound;
+        pn.tol = nd.rel_tol > 0 ? nd.rel_tol : 1e-6;
+        pn.max_iter = nd.max_iters > 0 ? nd.max_iters : 20000;
+        staged.push_back(std::move(pn));
+    }
+    {
+        std::lock_guard<std::mutex> g(P->mu);
+        if (P->engine_error) return fail(P->engine_error, "engine stopped: %s", P->engine_msg.c_str());
+        for (auto &pn : staged) P->pending.push_back(std::move(pn));
+    }
+    P->cv_work.notify_all();
+    return KBNB_OK;
+}
+
+extern "C" int submit_nodes(kbnb_problem *P, const kbnb_node_desc *nodes, int32_t count)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (count < 0 || (count > 0 && !nodes)) return fail(KBNB_E_INVALID_ARGUMENT, "bad node array");
+    return submit_locked(P, nodes, count);
+}
+
+static int poll_impl(kbnb_problem *P, kbnb_bound_result *out, int cap, int *n_out, int32_t *supports,
+                     double *betas, int timeout_us)
+{
+    std::unique_lock<std::mutex> lk(P->mu);
+    auto ready = [&] {
+        return !P->done.empty() || P->engine_error ||
+               (P->pending.empty() && P->active == 0);
+    };
+    if (timeout_us < 0) P->cv_done.wait(lk, ready);
+    else if (timeout_us > 0) P->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+    int cnt = 0;
+    while (cnt < cap && !P->done.empty()) {
+        DoneNode &d = P->done.front();
+        out[cnt] = d.r;
+        if (supports)
+            for (int r = 0; r < P->k; ++r) supports[(size_t)cnt * P->k + r] = d.sup[r];
+        if (betas) memcpy(betas + (size_t)cnt * P->p, d.beta.data(), sizeof(double) * P->p);
+        P->done.pop_front();
+        ++cnt;
+    }
+    *n_out = cnt;
+    if (cnt == 0 && P->engine_error) return fail(P->engine_error, "engine stopped: %s", P->engine_msg.c_str());
+    return cnt ? KBNB_OK : KBNB_TIMEOUT;
+}
+
+extern "C" int poll_bounds(kbnb_problem *P, kbnb_bound_result *out, int32_t cap, int32_t *n_out,
+                           int32_t *supports, double *betas, int32_t timeout_us)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (!out || !n_out || cap < 0) return fail(KBNB_E_INVALID_ARGUMENT, "bad output arguments");
+    return poll_impl(P, out, cap, n_out, supports, betas, timeout_us);
+}
+
+extern "C" int problem_info(kbnb_problem *P, int64_t *i_out, double *d_out)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (i_out) {
+        i_out[0] = P->n; i_out[1] = P->p; i_out[2] = P->k; i_out[3] = P->m;
+        i_out[4] = P->cert_period; i_out[5] = P->loss;
+        i_out[6] = P->gsplit; i_out[7] = P->rounds.load();
+    }
+    if (d_out) {
+        d_out[0] = P->L; d_out[1] = P->lambda2; d_out[2] = P->M; d_out[3] = (double)P->bytes;
+    }
+    return KBNB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// step-level entry points (synchronous, own stream and buffers)
+// ---------------------------------------------------------------------------
+struct TmpStream {
+    hipStream_t s = nullptr;
+    std::vector<void *> bufs;
+    ~TmpStream()
+    {
+        if (s) (void)hipStreamSynchronize(s);
+        for (void *b : bufs) (void)hipFree(b);
+        if (s) (void)hipStreamDestroy(s);
+    }
+    template <typename T> int alloc(T **p, size_t count)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+            return fail(KBNB_E_OUT_OF_MEMORY, "hipMalloc failed");
+        bufs.push_back(q);
+        *p = (T *)q;
+        return 0;
+    }
+};
+
+static int check_states(const kbnb_problem *P, int m, const int8_t *states, std::vector<int8_t> &st,
+                        std::vector<int32_t> &kbar)
+{
+    st.assign((size_t)m * P->ldp, -1);
+    kbar.assign(m, 0);
+    for (int b = 0; b < m; ++b) {
+        int nin = 0;
+        for (int j = 0; j < P->p; ++j) {
+            const int8_t s = states[(size_t)b * P->p + j];
+            if (s < -1 || s > 1) return fail(KBNB_E_INVALID_ARGUMENT, "state value %d", (int)s);
+            st[(size_t)b * P->ldp + j] = s;
+            nin += (s == 1);
+        }
+        if (nin > P->k) return fail(KBNB_E_INVALID_ARGUMENT, "node %d fixes %d > k indices in", b, nin);
+        kbar[b] = P->k - nin;
+    }
+    return 0;
+}
+
+extern "C" int prox_batch(kbnb_problem *P, int32_t m, const int8_t *states, const double *u, double eta,
+                          double *beta_out)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (m <= 0 || !states || !u || !beta_out || !(eta > 0))
+        return fail(KBNB_E_INVALID_ARGUMENT, "bad prox_batch arguments");
+    std::lock_guard<std::mutex> g(P->api_mu);
+    std::vector<int8_t> st;
+    std::vector<int32_t> kbar;
+    int rc = check_states(P, m, states, st, kbar);
+    if (rc) return rc;
+    std::vector<double> uh((size_t)m * P->ldp, 0.0);
+    for (int b = 0; b < m; ++b)
+        for (int j = 0; j < P->p; ++j) uh[(size_t)b * P->ldp + j] = u[(size_t)b * P->p + j];
+    TmpStream T;
+    HIP_TRY(hipStreamCreate(&T.s));
+    double *dU, *dB;
+    int8_t *dst;
+    int32_t *dk;
+    if ((rc = T.alloc(&dU, uh.size())) || (rc = T.alloc(&dB, uh.size())) || (rc = T.alloc(&dst, st.size())) ||
+        (rc = T.alloc(&dk, (size_t)m)))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(dU, uh.data(), uh.size() * 8, hipMemcpyHostToDevice, T.s));
+    HIP_TRY(hipMemcpyAsync(dst, st.data(), st.size(), hipMemcpyHostToDevice, T.s));
+    HIP_TRY(hipMemcpyAsync(dk, kbar.data(), (size_t)m * 4, hipMemcpyHostToDevice, T.s));
+    Consts c = P->c;
+    launch_prox_batch(T.s, dU, dst, dk, dB, m, eta, c);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> bh(uh.size());
+    HIP_TRY(hipMemcpyAsync(bh.data(), dB, bh.size() * 8, hipMemcpyDeviceToHost, T.s));
+    HIP_TRY(hipStreamSynchronize(T.s));
+    for (int b = 0; b < m; ++b)
+        for (int j = 0; j < P->p; ++j) beta_out[(size_t)b * P->p + j] = bh[(size_t)b * P->ldp + j];
+    return KBNB_OK;
+}
+
+extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, const double *betas,
+                             double *phi, double *psi, int32_t *supports, int32_t *branch)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (m <= 0 || !states || !betas || !phi || !psi) return fail(KBNB_E_INVALID_ARGUMENT, "bad certify_batch arguments");
+    std::lock_guard<std::mutex> g(P->api_mu);
+    std::vector<int8_t> st;
+    std::vector<int32_t> kbar;
+    int rc = check_states(P, m, states, st, kbar);
+    if (rc) return rc;
+    const int mpad = (int)round_up(m, GEMM_BN);
+    std::vector<double> bh((size_t)mpad * P->ldp, 0.0);
+    for (int b = 0; b < m; ++b)
+        for (int j = 0; j < P->p; ++j) bh[(size_t)b * P->ldp + j] = betas[(size_t)b * P->p + j];
+    st.resize((size_t)mpad * P->ldp, -1);
+    kbar.resize(mpad, 0);
+    TmpStream T;
+    HIP_TRY(hipStreamCreate(&T.s));
+    Consts c = P->c;
+    c.mpad = mpad;
+    c.m = m;
+    double *dB, *dZ, *dQ, *dl, *dc, *dlb, *dphi;
+    int8_t *dst;
+    int32_t *dk, *dsup, *djs, *dslen;
+    const int qsplit = P->qsplit;
+    if ((rc = T.alloc(&dB, bh.size())) || (rc = T.alloc(&dZ, (size_t)mpad * P->npad)) ||
+        (rc = T.alloc(&dQ, (size_t)qsplit * mpad * P->ldp)) || (rc = T.alloc(&dl, (size_t)P->tiles_n * mpad)) ||
+        (rc = T.alloc(&dc, (size_t)P->tiles_n * mpad)) || (rc = T.alloc(&dlb, (size_t)mpad)) ||
+        (rc = T.alloc(&dphi, (size_t)mpad)) || (rc = T.alloc(&dst, st.size())) || (rc = T.alloc(&dk, (size_t)mpad)) ||
+        (rc = T.alloc(&dsup, (size_t)mpad * P->k)) || (rc = T.alloc(&djs, (size_t)mpad)) ||
+        (rc = T.alloc(&dslen, (size_t)mpad)))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(dB, bh.data(), bh.size() * 8, hipMemcpyHostToDevice, T.s));
+    HIP_TRY(hipMemcpyAsync(dst, st.data(), st.size(), hipMemcpyHostToDevice, T.s));
+    HIP_TRY(hipMemcpyAsync(dk, kbar.data(), (size_t)mpad * 4, hipMemcpyHostToDevice, T.s));
+    SlotState ss{};
+    ss.lb = dlb; ss.phi = dphi; ss.kbar = dk; ss.sup = dsup; ss.jstar = djs; ss.slen = dslen;
+    launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c);
+    launch_cert_bwd(T.s, P->xtype, P->XT, dZ, dQ, qsplit, P->qchunk, c);
+    launch_cert_finish(T.s, dQ, qsplit, dl, dc, P->tiles_n, dB, dst, ss, c, 0);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(psi, dlb, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));
+    HIP_TRY(hipMemcpyAsync(phi, dphi, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));
+    if (supports) HIP_TRY(hipMemcpyAsync(supports, dsup, (size_t)m * P->k * 4, hipMemcpyDeviceToHost, T.s));
+    if (branch) HIP_TRY(hipMemcpyAsync(branch, djs, (size_t)m * 4, hipMemcpyDeviceToHost, T.s));
+    HIP_TRY(hipStreamSynchronize(T.s));
+    return KBNB_OK;
+}

@@ -1,0 +1,94 @@
+// kbnb_internal.h -- device-buffer layout and kernel launchers of the node-bound
+// engine.  Internal to libkbnb: the public interface is include/kbnb.h.
+//
+// Layout in HBM (all node data is node-major: element (j, b) of a p x m batch
+// matrix lives at [b * ldp + j], so one node's column is contiguous):
+//   X   [npad][ldp]  instance storage type, row-major, zero padding
+//   XT  [pm][npad]   the transpose of X (the X^T R products read it k-contiguous)
+//   Yi  [mpad][ldp]  extrapolated point in the iteration type (MFMA operand)
+//   R   [mpad][npad] l'(X Y) in the iteration type
+//   Gp  [gsplit][mpad][ldp] split-K partials of X^T R
+//   B, Bprev [mpad][ldp] float64 iterates beta^t, beta^{t-1}
+//   Z   [mpad][npad] float64 dual point zeta = -l'(X beta)
+//   Qp  [qsplit][mpad][ldp] float64 split-K partials of X^T zeta
+//   lsum, csum [tiles_n][mpad] float64 per-row-tile sums of l(X beta) and l*(-zeta)
+//   st  [mpad][ldp] int8 node coordinate state (0 free, 1 in, -1 out / padding)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace kbnb {
+
+constexpr int SLOT_EMPTY = -2;
+constexpr int SLOT_RUNNING = -1;
+// final statuses match kbnb.h: 0 converged, 1 pruned, 2 maxiter, 3 error
+
+constexpr int GEMM_BM = 64;
+constexpr int GEMM_BN = 64;
+constexpr int GEMM_BK = 16;
+
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Per-slot scalar state (struct of arrays, device memory).
+struct SlotState {
+    double *theta;    // extrapolation weight for the next step
+    double *tmom;     // FISTA t_k
+    double *lb;       // best certified dual value
+    double *phi;      // best primal value
+    double *gap;      // relative gap at the last certificate
+    double *ub;       // pruning incumbent
+    double *tol;      // relative tolerance
+    int32_t *status;  // SLOT_EMPTY / SLOT_RUNNING / final status
+    int32_t *iter;    // iterations done
+    int32_t *max_iter;
+    int32_t *kbar;    // k - |J1|
+    int32_t *jstar;   // branching index
+    int32_t *slen;    // rounding-support length
+    int32_t *sup;     // [mpad][k] rounding support, ascending, -1 padded
+};
+
+// Problem constants passed by value to kernels.
+struct Consts {
+    int n, p, k, loss;
+    int ldp, npad, pm, mpad, m;
+    double lambda2, M, eta;
+};
+
+// Staged node for admission into a slot (host -> device).
+struct AdmitRec {
+    int32_t slot, kbar, max_iter, has_warm;
+    double ub, tol;
+};
+
+enum XType { XT_F64 = 0, XT_F32 = 1, XT_BF16 = 2 };
+
+// ---- launchers (kbnb_kernels.hip) -----------------------------------------
+// iteration GEMMs (Ti = float for float32/bfloat16... instances, double for float64)
+void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
+                      void *R, const double *y, const Consts &c);
+void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
+                void *Gp, int gsplit, int gchunk, const Consts &c);
+void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, double *B,
+                      double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c);
+// certificate
+void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,
+                     const double *y, double *lsum, double *csum, const Consts &c);
+void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, double *Qp,
+                     int qsplit, int qchunk, const Consts &c);
+void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const double *lsum,
+                        const double *csum, int tiles_n, const double *B, const int8_t *st,
+                        SlotState ss, const Consts &c, int update_state);
+// admission of staged nodes into slots
+void launch_admit(hipStream_t s, bool iter_f64, const uint8_t *stage, int count, int rec_bytes,
+                  double *B, double *Bprev, void *Yi, int8_t *st, SlotState ss, const Consts &c);
+// standalone prox over a batch (u given), for the step-level entry point
+void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const int32_t *kbar,
+                       double *Bout, int m, double eta, const Consts &c);
+// power iteration pieces: out[r] = sum_c A[r][c] v[c] in float64
+void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int rows, int cols,
+                       const double *v, double *out);
+// convert/transposed copies
+void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
+                      int npad, int pm);
+
+}  // namespace kbnb

@@ -1,0 +1,1017 @@
+// kbnb_kernels.hip -- gfx950 kernels of the batched node-bound hot path.
+//
+// One FISTA step over a batch of m nodes (paper Sec. 4.2, eqs.
+// gradient_matrix_form and pgd_step_matrix_form) is three launches:
+//   fwd   S = X Y (MFMA), epilogue R = l'(S, y)           (forward contraction + loss)
+//   bwd   G = X^T R (MFMA, split-K partials)              (backward contraction)
+//   prox  per node: U = Y - eta G, masked TopSum-Huber prox, momentum/restart
+// and every few steps the float64 certificate (Sec. 4.4) is three more:
+//   cfwd  S = X B in float64 (MFMA f64), epilogue zeta = -l'(S), column sums of
+//         l(S) and l*(-zeta)
+//   cbwd  Q = X^T zeta in float64 (MFMA f64, split-K partials)
+//   cfin  per node: g*(Q / 2 lambda2) by TopSum selection, g(B) in closed form,
+//         primal/dual values, status, rounding support and branching index.
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdint>
+
+#include "kbnb_internal.h"
+
+namespace kbnb {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct V4;
+template <> struct V4<float> { typedef f32x4 t; };
+template <> struct V4<double> { typedef f64x4 t; };
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Global loads of 4 consecutive elements, converted to the compute type.
+// bfloat16 storage is uint16 bit patterns; the conversion is exact.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ld4(const float *p, float o[4])
+{
+    float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const float *p, double o[4])
+{
+    float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const double *p, double o[4])
+{
+    double2 a = *reinterpret_cast<const double2 *>(p);
+    double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+__device__ __forceinline__ void ld4(const double *p, float o[4])
+{
+    double2 a = *reinterpret_cast<const double2 *>(p);
+    double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    o[0] = (float)a.x; o[1] = (float)a.y; o[2] = (float)b.x; o[3] = (float)b.y;
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h)
+{
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+__device__ __forceinline__ void ld4(const uint16_t *p, float o[4])
+{
+    uint2 v = *reinterpret_cast<const uint2 *>(p);
+    o[0] = bf16_to_f((uint16_t)(v.x & 0xffff)); o[1] = bf16_to_f((uint16_t)(v.x >> 16));
+    o[2] = bf16_to_f((uint16_t)(v.y & 0xffff)); o[3] = bf16_to_f((uint16_t)(v.y >> 16));
+}
+__device__ __forceinline__ void ld4(const uint16_t *p, double o[4])
+{
+    float f[4];
+    ld4(p, f);
+    o[0] = f[0]; o[1] = f[1]; o[2] = f[2]; o[3] = f[3];
+}
+
+// ---------------------------------------------------------------------------
+// Scalar losses (paper Sec. 4.2 separable f; Sec. 4.4 l and l*).
+//   squared  l = (y - s)^2, l' = 2 (s - y), l*(v) = v y + v^2 / 4
+//   logistic l = log(1 + e^{-ys}), l' = -y / (1 + e^{ys}),
+//            l*(-zeta) = t log t + (1 - t) log(1 - t), t = y zeta in [0, 1]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dloss_f(int loss, float s, float y)
+{
+    if (loss == 0) return 2.0f * (s - y);
+    return -y / (1.0f + __expf(y * s));
+}
+__device__ __forceinline__ double dloss_d(int loss, double s, double y)
+{
+    if (loss == 0) return 2.0 * (s - y);
+    return -y / (1.0 + exp(y * s));
+}
+__device__ __forceinline__ double loss_d(int loss, double s, double y)
+{
+    if (loss == 0) {
+        double r = y - s;
+        return r * r;
+    }
+    double z = -y * s;
+    return fmax(z, 0.0) + log1p(exp(-fabs(z)));
+}
+// l*(-zeta, y)
+__device__ __forceinline__ double conj_neg_d(int loss, double zeta, double y)
+{
+    if (loss == 0) return -zeta * y + 0.25 * zeta * zeta;
+    double t = y * zeta;
+    if (t < 0.0 || t > 1.0) return INFINITY;
+    double a = (t > 0.0) ? t * log(t) : 0.0;
+    double b = (t < 1.0) ? (1.0 - t) * log1p(-t) : 0.0;
+    return a + b;
+}
+
+template <typename T> __device__ __forceinline__ T dloss_t(int loss, T s, T y);
+template <> __device__ __forceinline__ float dloss_t<float>(int loss, float s, float y) { return dloss_f(loss, s, y); }
+template <> __device__ __forceinline__ double dloss_t<double>(int loss, double s, double y) { return dloss_d(loss, s, y); }
+
+// ---------------------------------------------------------------------------
+// MFMA contraction  C[col][row] = sum_k A[row][k] * Bm[col][k]
+// over k in this workgroup's split range, both operands k-contiguous.
+// Tile 64 x 64 x 16, 256 threads as 2 x 2 waves of 32 x 32 (2 x 2 MFMA
+// 16x16x4 blocks).  Within a 16-wide k chunk, lane group g = lane / 16 owns
+// k = 4g .. 4g+3, so each lane reads its four A (and B) values of a chunk
+// with one LDS vector read; MFMA step s contracts k in {s, 4+s, 8+s, 12+s}.
+// Epilogue modes:
+//   EPI_DLOSS  C = l'(acc, y[row]) for row < n, 0 otherwise  (R of the step)
+//   EPI_STORE  C[split] = acc for row < rows_valid            (split-K partials)
+//   EPI_CERT   C = zeta = -l'(acc, y[row]) for row < n, plus per-column sums
+//              of l(acc) and l*(-zeta) over this tile's rows.
+// ---------------------------------------------------------------------------
+enum { EPI_DLOSS = 0, EPI_STORE = 1, EPI_CERT = 2 };
+
+struct GemmArgs {
+    const void *A;
+    int64_t lda;
+    const void *B;
+    int64_t ldb;
+    void *C;
+    int64_t ldc;
+    int64_t split_stride;  // elements between split partial buffers
+    int k_len;             // total k extent (multiple of 16)
+    int k_chunk;           // k per split (multiple of 16)
+    int tiles_m;
+    int rows_valid;        // store rows < rows_valid (EPI_STORE)
+    int n;                 // rows with data (EPI_DLOSS / EPI_CERT)
+    int loss;
+    const double *y;
+    double *lsum;          // [tiles_m][ldsum]
+    double *csum;
+    int64_t ldsum;
+};
+
+template <typename TA, typename TB, typename TC, int MODE>
+__global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
+{
+    constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK;
+    constexpr int PAD = (sizeof(TC) == 8) ? 2 : 4;
+    constexpr int LS = BK + PAD;  // LDS row stride (elements)
+    typedef typename V4<TC>::t acc_t;
+    __shared__ TC As[2][BM * LS];
+    __shared__ TC Bs[2][BN * LS];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+    // The f64 16x16x4 MFMA returns row g + 4r of its block in lane group g,
+    // register r (the f32 one returns row 4g + r).  Feeding A row
+    // 4 (i % 4) + i / 4 into row slot i makes both layouts "lane group g,
+    // register r holds row 4g + r", so one epilogue serves both.
+    const int arow = (sizeof(TC) == 8) ? ((lr & 3) * 4 + (lr >> 2)) : lr;
+    const int tm = blockIdx.x % g.tiles_m, tn = blockIdx.x / g.tiles_m;
+    const int split = blockIdx.y;
+    const int row0 = tm * BM, col0 = tn * BN;
+    const int kbeg = split * g.k_chunk;
+    const int kend = min(g.k_len, kbeg + g.k_chunk);
+
+    const TA *A = reinterpret_cast<const TA *>(g.A);
+    const TB *Bg = reinterpret_cast<const TB *>(g.B);
+    // each thread stages one 4-element group of A and one of B per chunk
+    const int sr = tid >> 2, sq = (tid & 3) * 4;
+    const TA *a_src = A + (int64_t)(row0 + sr) * g.lda + sq;
+    const TB *b_src = Bg + (int64_t)(col0 + sr) * g.ldb + sq;
+
+    acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = acc_t{0, 0, 0, 0};
+
+    TC ra[4], rb[4];
+    if (kbeg < kend) {
+        ld4(a_src + kbeg, ra);
+        ld4(b_src + kbeg, rb);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            As[0][sr * LS + sq + e] = ra[e];
+            Bs[0][sr * LS + sq + e] = rb[e];
+        }
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int kk = kbeg; kk < kend; kk += BK) {
+        const bool more = kk + BK < kend;
+        if (more) {
+            ld4(a_src + kk + BK, ra);
+            ld4(b_src + kk + BK, rb);
+        }
+        TC av[2][4], bv[2][4];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const TC *pa = &As[buf][(wm * 32 + f * 16 + arow) * LS + lg * 4];
+            const TC *pb = &Bs[buf][(wn * 32 + f * 16 + lr) * LS + lg * 4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                av[f][s] = pa[s];
+                bv[f][s] = pb[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = mfma16(av[i][s], bv[j][s], acc[i][j]);
+        if (more) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                As[buf ^ 1][sr * LS + sq + e] = ra[e];
+                Bs[buf ^ 1][sr * LS + sq + e] = rb[e];
+            }
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    // ---- epilogue ----------------------------------------------------------
+    // acc[i][j][r] holds C at row = row0 + wm*32 + i*16 + lg*4 + r,
+    //                        col = col0 + wn*32 + j*16 + lr.
+    if constexpr (MODE == EPI_DLOSS) {
+        TC *C = reinterpret_cast<TC *>(g.C);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = col0 + wn * 32 + j * 16 + lr;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int rb0 = row0 + wm * 32 + i * 16 + lg * 4;
+                acc_t o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rb0 + r;
+                    o[r] = (row < g.n) ? dloss_t<TC>(g.loss, acc[i][j][r], (TC)g.y[row]) : (TC)0;
+                }
+                *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = o;
+            }
+        }
+    } else if constexpr (MODE == EPI_STORE) {
+        TC *C = reinterpret_cast<TC *>(g.C) + (int64_t)split * g.split_stride;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = col0 + wn * 32 + j * 16 + lr;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int rb0 = row0 + wm * 32 + i * 16 + lg * 4;
+                if (rb0 + 3 < g.rows_valid) {
+                    *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = acc[i][j];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (rb0 + r < g.rows_valid)
+                            C[(int64_t)col * g.ldc + rb0 + r] = acc[i][j][r];
+                }
+            }
+        }
+    } else {  // EPI_CERT (TC is double)
+        double *C = reinterpret_cast<double *>(g.C);
+        __shared__ double red_l[2][64];
+        __shared__ double red_c[2][64];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = col0 + wn * 32 + j * 16 + lr;
+            double sl = 0.0, sc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int rb0 = row0 + wm * 32 + i * 16 + lg * 4;
+                f64x4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rb0 + r;
+                    if (row < g.n) {
+                        const double s = acc[i][j][r], yy = g.y[row];
+                        const double z = -dloss_d(g.loss, s, yy);
+                        o[r] = z;
+                        sl += loss_d(g.loss, s, yy);
+                        sc += conj_neg_d(g.loss, z, yy);
+                    } else {
+                        o[r] = 0.0;
+                    }
+                }
+                *reinterpret_cast<f64x4 *>(C + (int64_t)col * g.ldc + rb0) = o;
+            }
+            // reduce over the 4 lane groups holding this column
+            sl += __shfl_xor(sl, 16);
+            sl += __shfl_xor(sl, 32);
+            sc += __shfl_xor(sc, 16);
+            sc += __shfl_xor(sc, 32);
+            if (lg == 0) {
+                red_l[wm][wn * 32 + j * 16 + lr] = sl;
+                red_c[wm][wn * 32 + j * 16 + lr] = sc;
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int col = col0 + tid;
+            g.lsum[(int64_t)tm * g.ldsum + col] = red_l[0][tid] + red_l[1][tid];
+            g.csum[(int64_t)tm * g.ldsum + col] = red_c[0][tid] + red_c[1][tid];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+// argmax with ties to the lowest index; (v, i) pairs, i = INT_MAX for none
+__device__ __forceinline__ void wave_argmax(double &v, int &i)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double v2 = __shfl_xor(v, o);
+        int i2 = __shfl_xor(i, o);
+        if (v2 > v || (v2 == v && i2 < i)) {
+            v = v2;
+            i = i2;
+        }
+    }
+}
+
+// Huber prox: argmin_v 1/2 (v - x)^2 + c H_M(v)
+__device__ __forceinline__ double prox_huber(double x, double c, double M)
+{
+    if (fabs(x) <= M * (1.0 + c)) return x / (1.0 + c);
+    return (x > 0.0) ? x - c * M : x + c * M;
+}
+__device__ __forceinline__ double huber(double q, double M)
+{
+    const double a = fabs(q);
+    return (a <= M) ? 0.5 * q * q : M * a - 0.5 * M * M;
+}
+
+// Bitonic sort of PP (key, idx) pairs in LDS by one 64-lane wave:
+// key descending, idx ascending on equal keys (a strict total order).
+template <int PP>
+__device__ void bitonic_desc(double *key, int *idx)
+{
+    const int l = threadIdx.x;
+    for (int size = 2; size <= PP; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = l; t < PP / 2; t += 64) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const double ki = key[i], kj = key[j];
+                const int ii = idx[i], ij = idx[j];
+                const bool i_first = (ki > kj) || (ki == kj && ii < ij);
+                const bool want_desc = ((i & size) == 0);
+                if (want_desc != i_first) {
+                    key[i] = kj; key[j] = ki;
+                    idx[i] = ij; idx[j] = ii;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Masked prox of one node (paper Sec. 4.2 "Evaluating proximal operators with
+// non-uniform node structure", eq. pgd_step_vector_form; App. B):
+//   J0 -> 0;  J1 -> u / (1 + 2 eta lambda2) clipped to [-M, M];
+//   free coordinates: keys |u| (padding -1 sorts below every free key),
+//   descending sort, then the PAVA of App. B for weights rho on the first
+//   kbar positions and 0 after: violations can only start at the kbar/kbar+1
+//   boundary, so one pooled block [a, b] grows from there while it violates
+//   its left or right neighbour; the block value is prox_{mean weight H_M} of
+//   the mean key (in rho-scaled units).  Then beta = sgn(u)(|u| - v / rho):
+//   positions before the block keep the ridge-and-clip value, block positions
+//   |u| - V / rho, positions after it exactly 0.
+// Requires the node's u in LDS (uu[j]) and its states; writes beta to LDS.
+// ---------------------------------------------------------------------------
+template <int PP>
+struct ProxLds {
+    double key[PP];
+    int idx[PP];
+    int rank[PP];
+    double uu[PP];
+    double bb[PP];
+};
+
+struct PavaBlock {
+    int a, b;   // pooled block [a, b] in sorted order (empty if a > b)
+    double V;   // block value (rho-scaled)
+    int top;    // positions < top (outside the block) are weighted singletons
+};
+
+template <int PP>
+__device__ void masked_prox(ProxLds<PP> &L, const int8_t *st, int p, int kbar, double eta,
+                            double lambda2, double M)
+{
+    const int l = threadIdx.x;
+    const double rho = 1.0 / (2.0 * eta * lambda2);
+    const double shrink = 1.0 + 2.0 * eta * lambda2;
+    int nfree = 0;
+    for (int j = l; j < PP; j += 64) {
+        const bool fr = (j < p) && st[j] == 0;
+        L.key[j] = fr ? fabs(L.uu[j]) : -1.0;
+        L.idx[j] = j;
+        nfree += fr ? 1 : 0;
+    }
+    const int pf = wave_sum_i(nfree);
+    __syncthreads();
+    bitonic_desc<PP>(L.key, L.idx);
+    for (int r = l; r < pf; r += 64) L.rank[L.idx[r]] = r;
+    __syncthreads();
+
+    // wave-uniform PAVA from the budget boundary
+    PavaBlock blk;
+    blk.a = 0; blk.b = -1; blk.V = 0.0;
+    if (kbar <= 0) {
+        blk.top = 0;
+    } else if (kbar >= pf) {
+        blk.top = pf;
+    } else {
+        blk.top = kbar;
+        const double wl = rho * L.key[kbar - 1], wr = rho * L.key[kbar];
+        if (prox_huber(wl, rho, M) < wr) {
+            int a = kbar - 1, b = kbar, cnt = 2;
+            double sw = wl + wr, sr = rho;
+            double V = prox_huber(sw / cnt, sr / cnt, M);
+            for (;;) {
+                bool moved = false;
+                if (a > 0) {
+                    const double wn = rho * L.key[a - 1];
+                    if (prox_huber(wn, rho, M) < V) {
+                        --a; ++cnt; sw += wn; sr += rho;
+                        V = prox_huber(sw / cnt, sr / cnt, M);
+                        moved = true;
+                    }
+                }
+                if (b + 1 < pf) {
+                    const double wn = rho * L.key[b + 1];
+                    if (V < wn) {
+                        ++b; ++cnt; sw += wn;
+                        V = prox_huber(sw / cnt, sr / cnt, M);
+                        moved = true;
+                    }
+                }
+                if (!moved) break;
+            }
+            blk.a = a; blk.b = b; blk.V = V; blk.top = a;
+        }
+    }
+    for (int j = l; j < p; j += 64) {
+        const double u = L.uu[j];
+        const double au = fabs(u), sg = (u > 0.0) ? 1.0 : ((u < 0.0) ? -1.0 : 0.0);
+        double bj;
+        const int s = st[j];
+        if (s < 0) {
+            bj = 0.0;
+        } else if (s > 0) {
+            bj = sg * fmin(au / shrink, M);
+        } else {
+            const int r = L.rank[j];
+            if (r < blk.top) bj = sg * fmin(au / shrink, M);
+            else if (r >= blk.a && r <= blk.b) bj = sg * (au - blk.V / rho);
+            else bj = 0.0;
+        }
+        L.bb[j] = bj;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Prox + FISTA momentum for every running slot (one wave per slot).
+// ---------------------------------------------------------------------------
+template <typename Ti, int PP>
+__global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int gsplit,
+                                                   double *__restrict__ B, double *__restrict__ Bprev,
+                                                   Ti *__restrict__ Yi, const int8_t *__restrict__ stg,
+                                                   SlotState ss, Consts c)
+{
+    __shared__ ProxLds<PP> L;
+    const int b = blockIdx.x;
+    const int l = threadIdx.x;
+    if (ss.status[b] != SLOT_RUNNING) return;
+    const int p = c.p;
+    const int64_t off = (int64_t)b * c.ldp;
+    const int64_t sstride = (int64_t)c.mpad * c.ldp;
+    const double th = ss.theta[b];
+    const int8_t *st = stg + off;
+    for (int j = l; j < p; j += 64) {
+        double gj = 0.0;
+        for (int s = 0; s < gsplit; ++s) gj += (double)Gp[s * sstride + off + j];
+        const double bj = B[off + j], bp = Bprev[off + j];
+        const double yj = bj + th * (bj - bp);
+        L.uu[j] = yj - c.eta * gj;
+    }
+    __syncthreads();
+    masked_prox<PP>(L, st, p, ss.kbar[b], c.eta, c.lambda2, c.M);
+    // restart test (y - beta+)^T (beta+ - beta) > 0, then momentum
+    double dot = 0.0;
+    for (int j = l; j < p; j += 64) {
+        const double bj = B[off + j], bp = Bprev[off + j];
+        const double yj = bj + th * (bj - bp);
+        const double bn = L.bb[j];
+        dot += (yj - bn) * (bn - bj);
+    }
+    dot = wave_sum(dot);
+    const double t = ss.tmom[b];
+    double tn, thn;
+    if (dot > 0.0) {
+        tn = 1.0;
+        thn = 0.0;
+    } else {
+        tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        thn = (t - 1.0) / tn;
+    }
+    for (int j = l; j < p; j += 64) {
+        const double bj = B[off + j];
+        const double bn = L.bb[j];
+        Bprev[off + j] = bj;
+        B[off + j] = bn;
+        Yi[off + j] = (Ti)(bn + thn * (bn - bj));
+    }
+    if (l == 0) {
+        ss.tmom[b] = tn;
+        ss.theta[b] = thn;
+        ss.iter[b] = ss.iter[b] + 1;
+    }
+}
+
+// Standalone prox over a batch (step-level entry point).
+template <int PP>
+__global__ __launch_bounds__(64) void k_prox_batch(const double *__restrict__ U, const int8_t *__restrict__ stg,
+                                                    const int32_t *__restrict__ kbar, double *__restrict__ Bout,
+                                                    double eta, Consts c)
+{
+    __shared__ ProxLds<PP> L;
+    const int b = blockIdx.x, l = threadIdx.x;
+    const int64_t off = (int64_t)b * c.ldp;
+    for (int j = l; j < c.p; j += 64) L.uu[j] = U[off + j];
+    __syncthreads();
+    masked_prox<PP>(L, stg + off, c.p, kbar[b], eta, c.lambda2, c.M);
+    for (int j = l; j < c.p; j += 64) Bout[off + j] = L.bb[j];
+}
+
+// ---------------------------------------------------------------------------
+// Certificate finish (one wave per slot): paper Sec. 4.4,
+// eqs. batched_primal_value_component / batched_dual_value_component.
+//   q = (sum of Q partials) / (2 lambda2)
+//   g*(q) = sum_{J1} H_M(q_j) + TopSum_kbar{H_M(q_j)}_{free}  (kbar rounds of
+//           wave argmax; fewer free entries than kbar sums them all)
+//   g(beta) by Thm. 4.1: J1 contributes beta^2/2; on the free set with
+//           a = |beta| sorted descending (top kbar by the same selection),
+//           at most kbar nonzeros -> sum a^2/2; otherwise the first s in
+//           0..kbar-1 with a_(s) >= tau >= a_(s+1), tau = (sum_{r>s} a_r)/(kbar-s)
+//           gives sum_{r<=s} a_r^2/2 + tau (sum_{r>s} a_r)/2.  Points outside
+//           dom g (|beta_j| > M, beta on J0, free sum > M kbar, relative slack
+//           1e-9) give +inf.
+//   Phi = sum l(X beta) + 2 lambda2 g(beta);  Psi = -sum l*(-zeta) - 2 lambda2 g*(q)
+//   LB = max(LB, Psi), Phi_best = min(Phi_best, Phi); status update.
+//   Rounding support = J1 + the kbar selected free indices (ascending);
+//   branching index = the first selected (argmax |beta_j| over free, lowest
+//   index on ties) -- Sec. 4.3.
+// ---------------------------------------------------------------------------
+template <int PP>
+struct CertLds {
+    double h[PP];
+    double a[PP];
+    double topa[128];
+    int topi[128];
+    int sup[256];
+};
+
+template <int PP>
+__global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Qp, int qsplit,
+                                                     const double *__restrict__ lsum,
+                                                     const double *__restrict__ csum, int tiles_n,
+                                                     const double *__restrict__ B,
+                                                     const int8_t *__restrict__ stg, SlotState ss,
+                                                     Consts c, int update_state)
+{
+    __shared__ CertLds<PP> L;
+    const int b = blockIdx.x, l = threadIdx.x;
+    if (update_state && ss.status[b] != SLOT_RUNNING) return;
+    const int p = c.p;
+    const int64_t off = (int64_t)b * c.ldp;
+    const int64_t qstride = (int64_t)c.mpad * c.ldp;
+    const int8_t *st = stg + off;
+    const int kbar = ss.kbar[b];
+    const double inv2l = 1.0 / (2.0 * c.lambda2);
+    const double slack = 1.0 + 1e-9;
+
+    // smooth parts
+    double fl = 0.0, fc = 0.0;
+    for (int t = l; t < tiles_n; t += 64) {
+        fl += lsum[(int64_t)t * c.mpad + b];
+        fc += csum[(int64_t)t * c.mpad + b];
+    }
+    fl = wave_sum(fl);
+    fc = wave_sum(fc);
+
+    // per-coordinate pass
+    double gin = 0.0, g1 = 0.0, sum_a = 0.0, sum_a2 = 0.0;
+    int nnz = 0, bad = 0;
+    for (int j = l; j < PP; j += 64) {
+        double hj = -1.0, aj = -1.0;
+        if (j < p) {
+            double q = 0.0;
+            for (int s = 0; s < qsplit; ++s) q += Qp[s * qstride + off + j];
+            q *= inv2l;
+            const double bj = B[off + j];
+            const double ab = fabs(bj);
+            const int s = st[j];
+            if (s < 0) {
+                if (bj != 0.0) bad = 1;
+            } else {
+                if (ab > c.M * slack) bad = 1;
+                if (s > 0) {
+                    gin += huber(q, c.M);
+                    g1 += 0.5 * bj * bj;
+                } else {
+                    hj = huber(q, c.M);
+                    aj = ab;
+                    sum_a += ab;
+                    sum_a2 += ab * ab;
+                    nnz += (ab > 0.0) ? 1 : 0;
+                }
+            }
+        }
+        L.h[j] = hj;
+        L.a[j] = aj;
+    }
+    gin = wave_sum(gin);
+    g1 = wave_sum(g1);
+    sum_a = wave_sum(sum_a);
+    sum_a2 = wave_sum(sum_a2);
+    nnz = wave_sum_i(nnz);
+    bad = wave_sum_i(bad);
+    __syncthreads();
+
+    // TopSum_kbar of H over the free set
+    double topsum = 0.0;
+    for (int r = 0; r < kbar; ++r) {
+        double v = -1.0;
+        int vi = 0x7fffffff;
+        for (int j = l; j < PP; j += 64) {
+            const double hv = L.h[j];
+            if (hv > v) { v = hv; vi = j; }
+        }
+        wave_argmax(v, vi);
+        if (v < 0.0) break;
+        topsum += v;
+        if (l == 0) L.h[vi] = -1.0;
+        __syncthreads();
+    }
+    // kbar largest |beta| over the free set (ties to the lowest index)
+    int ntop = 0;
+    const int kcap = kbar < 128 ? kbar : 128;
+    for (int r = 0; r < kcap; ++r) {
+        double v = -1.0;
+        int vi = 0x7fffffff;
+        for (int j = l; j < PP; j += 64) {
+            const double av = L.a[j];
+            if (av > v) { v = av; vi = j; }
+        }
+        wave_argmax(v, vi);
+        if (v < 0.0) break;
+        if (l == 0) {
+            L.topa[r] = v;
+            L.topi[r] = vi;
+            L.a[vi] = -1.0;
+        }
+        ++ntop;
+        __syncthreads();
+    }
+    __syncthreads();
+    // branching index: the largest free |beta| (needs at least one free entry)
+    int jstar = -1;
+    if (kbar > 0) {
+        jstar = (ntop > 0) ? L.topi[0] : -1;
+    } else {
+        double v = -1.0;
+        int vi = 0x7fffffff;
+        for (int j = l; j < PP; j += 64) {
+            const double av = L.a[j];
+            if (av > v) { v = av; vi = j; }
+        }
+        wave_argmax(v, vi);
+        jstar = (v >= 0.0) ? vi : -1;
+    }
+
+    // g on the free set
+    double gfree;
+    if (bad) {
+        gfree = INFINITY;
+    } else if (nnz <= kbar) {
+        gfree = 0.5 * sum_a2;
+    } else if (kbar <= 0 || sum_a > c.M * kbar * slack) {
+        gfree = INFINITY;
+    } else {
+        gfree = INFINITY;
+        double head = 0.0, head2 = 0.0;  // sums over the s capped entries
+        double best_viol = INFINITY, best_val = INFINITY;
+        for (int s = 0; s < kbar; ++s) {
+            const double tail = sum_a - head;
+            const double tau = tail / (double)(kbar - s);
+            const double up = (s == 0) ? INFINITY : L.topa[s - 1];
+            const double lo = L.topa[s];
+            const double val = 0.5 * head2 + 0.5 * tau * tail;
+            if (up >= tau * (1.0 - 1e-12) && tau >= lo * (1.0 - 1e-12)) {
+                gfree = val;
+                break;
+            }
+            const double viol = fmax(fmax(tau - up, lo - tau), 0.0) / tau;
+            if (viol < best_viol) { best_viol = viol; best_val = val; }
+            head += L.topa[s];
+            head2 += L.topa[s] * L.topa[s];
+        }
+        if (!(gfree < INFINITY)) gfree = best_val;
+    }
+    const double phi = fl + 2.0 * c.lambda2 * (g1 + gfree);
+    const double psi = -fc - 2.0 * c.lambda2 * (gin + topsum);
+
+    // rounding support: J1 plus the selected free indices, ascending
+    if (l == 0) {
+        int len = 0;
+        for (int j = 0; j < p && len < 256; ++j)
+            if (st[j] > 0) L.sup[len++] = j;
+        for (int r = 0; r < ntop && len < 256; ++r) L.sup[len++] = L.topi[r];
+        for (int x = 1; x < len; ++x) {
+            const int v = L.sup[x];
+            int y = x - 1;
+            while (y >= 0 && L.sup[y] > v) { L.sup[y + 1] = L.sup[y]; --y; }
+            L.sup[y + 1] = v;
+        }
+        int32_t *so = ss.sup + (int64_t)b * c.k;
+        for (int r = 0; r < c.k; ++r) so[r] = (r < len) ? L.sup[r] : -1;
+        ss.slen[b] = len < c.k ? len : c.k;
+        ss.jstar[b] = jstar;
+        if (update_state) {
+            // a NaN value means the iterate broke down: the node keeps its last
+            // certified bound and stops with status ERROR
+            const bool nan = (psi != psi) || (phi != phi);
+            double LB = ss.lb[b], PH = ss.phi[b];
+            if (!nan && psi > LB) LB = psi;
+            if (!nan && phi < PH) PH = phi;
+            const double gap = (PH < INFINITY && LB > -INFINITY) ? (PH - LB) / fmax(fabs(PH), 1e-12) : INFINITY;
+            ss.lb[b] = LB;
+            ss.phi[b] = PH;
+            ss.gap[b] = gap;
+            const double ub = ss.ub[b];
+            int stt = SLOT_RUNNING;
+            if (nan) stt = 3;
+            else if (LB >= ub - 1e-6 * fabs(ub)) stt = 1;
+            else if (gap <= ss.tol[b]) stt = 0;
+            else if (ss.iter[b] >= ss.max_iter[b]) stt = 2;
+            ss.status[b] = stt;
+        } else {
+            ss.lb[b] = psi;
+            ss.phi[b] = phi;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Admission: scatter staged node records into their slots.
+// Record: AdmitRec, then st[ldp] int8, then (aligned to 8) warm[ldp] float64.
+// ---------------------------------------------------------------------------
+template <typename Ti>
+__global__ __launch_bounds__(64) void k_admit(const uint8_t *__restrict__ stage, int rec_bytes,
+                                               double *B, double *Bprev, Ti *Yi, int8_t *stg,
+                                               SlotState ss, Consts c)
+{
+    const uint8_t *rec = stage + (int64_t)blockIdx.x * rec_bytes;
+    const AdmitRec h = *reinterpret_cast<const AdmitRec *>(rec);
+    const int8_t *sst = reinterpret_cast<const int8_t *>(rec + sizeof(AdmitRec));
+    const int64_t woff = round_up((int64_t)sizeof(AdmitRec) + c.ldp, 8);
+    const double *warm = reinterpret_cast<const double *>(rec + woff);
+    const int b = h.slot;
+    const int64_t off = (int64_t)b * c.ldp;
+    for (int j = threadIdx.x; j < c.ldp; j += 64) {
+        const int8_t s = sst[j];
+        const double w = (h.has_warm && s >= 0 && j < c.p) ? warm[j] : 0.0;
+        stg[off + j] = s;
+        B[off + j] = w;
+        Bprev[off + j] = w;
+        Yi[off + j] = (Ti)w;
+    }
+    if (threadIdx.x == 0) {
+        ss.theta[b] = 0.0;
+        ss.tmom[b] = 1.0;
+        ss.lb[b] = -INFINITY;
+        ss.phi[b] = INFINITY;
+        ss.gap[b] = INFINITY;
+        ss.ub[b] = h.ub;
+        ss.tol[b] = h.tol;
+        ss.iter[b] = 0;
+        ss.max_iter[b] = h.max_iter;
+        ss.kbar[b] = h.kbar;
+        ss.jstar[b] = -1;
+        ss.slen[b] = 0;
+        ss.status[b] = SLOT_RUNNING;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Float64 matrix-vector product (power iteration): out[r] = sum_c A[r][c] v[c].
+// One wave per row.
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(256) void k_matvec(const TA *__restrict__ A, int64_t lda, int rows,
+                                                 int cols, const double *__restrict__ v,
+                                                 double *__restrict__ out)
+{
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    if (r >= rows) return;
+    const TA *a = A + (int64_t)r * lda;
+    double s = 0.0;
+    for (int j = l; j < cols; j += 64) {
+        double aj;
+        if constexpr (sizeof(TA) == 2) aj = (double)bf16_to_f(a[j]);
+        else aj = (double)a[j];
+        s += aj * v[j];
+    }
+    s = wave_sum(s);
+    if (l == 0) out[r] = s;
+}
+
+// Transposed copy XT[j][i] = X[i][j] (padding stays zero: XT is pre-zeroed).
+template <typename TA>
+__global__ __launch_bounds__(256) void k_transpose(const TA *__restrict__ X, TA *__restrict__ XT,
+                                                    int n, int p, int ldp, int npad)
+{
+    __shared__ TA tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // bx over j, by over i
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = by + r, j = bx + tx;
+        tile[r][tx] = (i < n && j < p) ? X[(int64_t)i * ldp + j] : (TA)0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int j = bx + r, i = by + tx;
+        if (j < p && i < n) XT[(int64_t)j * npad + i] = tile[tx][r];
+    }
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+template <typename TA, typename TB, typename TC, int MODE>
+static void gemm(hipStream_t s, const GemmArgs &g, int tiles_n, int splits)
+{
+    dim3 grid(g.tiles_m * tiles_n, splits);
+    hipLaunchKernelGGL((k_gemm_tn<TA, TB, TC, MODE>), grid, dim3(256), 0, s, g);
+}
+
+void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
+                      void *R, const double *y, const Consts &c)
+{
+    GemmArgs g{};
+    g.A = X; g.lda = c.ldp; g.B = Yi; g.ldb = c.ldp; g.C = R; g.ldc = c.npad;
+    g.k_len = c.ldp; g.k_chunk = c.ldp; g.tiles_m = c.npad / GEMM_BM;
+    g.n = c.n; g.loss = c.loss; g.y = y;
+    const int tn = c.mpad / GEMM_BN;
+    if (iter_f64) gemm<double, double, double, EPI_DLOSS>(s, g, tn, 1);
+    else if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS>(s, g, tn, 1);
+    else gemm<uint16_t, float, float, EPI_DLOSS>(s, g, tn, 1);
+}
+
+void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
+                void *Gp, int gsplit, int gchunk, const Consts &c)
+{
+    GemmArgs g{};
+    g.A = XT; g.lda = c.npad; g.B = R; g.ldb = c.npad; g.C = Gp; g.ldc = c.ldp;
+    g.split_stride = (int64_t)c.mpad * c.ldp;
+    g.k_len = c.npad; g.k_chunk = gchunk; g.tiles_m = c.pm / GEMM_BM; g.rows_valid = c.ldp;
+    const int tn = c.mpad / GEMM_BN;
+    if (iter_f64) gemm<double, double, double, EPI_STORE>(s, g, tn, gsplit);
+    else if (xtype == XT_F32) gemm<float, float, float, EPI_STORE>(s, g, tn, gsplit);
+    else gemm<uint16_t, float, float, EPI_STORE>(s, g, tn, gsplit);
+}
+
+void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,
+                     const double *y, double *lsum, double *csum, const Consts &c)
+{
+    GemmArgs g{};
+    g.A = X; g.lda = c.ldp; g.B = B; g.ldb = c.ldp; g.C = Z; g.ldc = c.npad;
+    g.k_len = c.ldp; g.k_chunk = c.ldp; g.tiles_m = c.npad / GEMM_BM;
+    g.n = c.n; g.loss = c.loss; g.y = y; g.lsum = lsum; g.csum = csum; g.ldsum = c.mpad;
+    const int tn = c.mpad / GEMM_BN;
+    if (xtype == XT_F64) gemm<double, double, double, EPI_CERT>(s, g, tn, 1);
+    else if (xtype == XT_F32) gemm<float, double, double, EPI_CERT>(s, g, tn, 1);
+    else gemm<uint16_t, double, double, EPI_CERT>(s, g, tn, 1);
+}
+
+void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, double *Qp,
+                     int qsplit, int qchunk, const Consts &c)
+{
+    GemmArgs g{};
+    g.A = XT; g.lda = c.npad; g.B = Z; g.ldb = c.npad; g.C = Qp; g.ldc = c.ldp;
+    g.split_stride = (int64_t)c.mpad * c.ldp;
+    g.k_len = c.npad; g.k_chunk = qchunk; g.tiles_m = c.pm / GEMM_BM; g.rows_valid = c.ldp;
+    const int tn = c.mpad / GEMM_BN;
+    if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, tn, qsplit);
+    else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, tn, qsplit);
+    else gemm<uint16_t, double, double, EPI_STORE>(s, g, tn, qsplit);
+}
+
+#define KBNB_PP_DISPATCH(P, CALL)                     \
+    do {                                              \
+        if ((P) <= 64) { constexpr int PP = 64; CALL; } \
+        else if ((P) <= 128) { constexpr int PP = 128; CALL; } \
+        else if ((P) <= 256) { constexpr int PP = 256; CALL; } \
+        else if ((P) <= 512) { constexpr int PP = 512; CALL; } \
+        else if ((P) <= 1024) { constexpr int PP = 1024; CALL; } \
+        else { constexpr int PP = 2048; CALL; } \
+    } while (0)
+
+void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, double *B,
+                      double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c)
+{
+    if (iter_f64) {
+        KBNB_PP_DISPATCH(c.p, hipLaunchKernelGGL((k_prox_iter<double, PP>), dim3(c.m), dim3(64), 0, s,
+                                                 (const double *)Gp, gsplit, B, Bprev, (double *)Yi, st, ss, c));
+    } else {
+        KBNB_PP_DISPATCH(c.p, hipLaunchKernelGGL((k_prox_iter<float, PP>), dim3(c.m), dim3(64), 0, s,
+                                                 (const float *)Gp, gsplit, B, Bprev, (float *)Yi, st, ss, c));
+    }
+}
+
+void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const int32_t *kbar,
+                       double *Bout, int m, double eta, const Consts &c)
+{
+    KBNB_PP_DISPATCH(c.p, hipLaunchKernelGGL((k_prox_batch<PP>), dim3(m), dim3(64), 0, s, U, st, kbar,
+                                             Bout, eta, c));
+}
+
+void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const double *lsum,
+                        const double *csum, int tiles_n, const double *B, const int8_t *st,
+                        SlotState ss, const Consts &c, int update_state)
+{
+    KBNB_PP_DISPATCH(c.p, hipLaunchKernelGGL((k_cert_finish<PP>), dim3(c.m), dim3(64), 0, s, Qp, qsplit,
+                                             lsum, csum, tiles_n, B, st, ss, c, update_state));
+}
+
+void launch_admit(hipStream_t s, bool iter_f64, const uint8_t *stage, int count, int rec_bytes,
+                  double *B, double *Bprev, void *Yi, int8_t *st, SlotState ss, const Consts &c)
+{
+    if (count <= 0) return;
+    if (iter_f64)
+        hipLaunchKernelGGL((k_admit<double>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
+                           (double *)Yi, st, ss, c);
+    else
+        hipLaunchKernelGGL((k_admit<float>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
+                           (float *)Yi, st, ss, c);
+}
+
+void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int rows, int cols,
+                       const double *v, double *out)
+{
+    dim3 grid((rows + 3) / 4);
+    if (xtype == XT_F64)
+        hipLaunchKernelGGL((k_matvec<double>), grid, dim3(256), 0, s, (const double *)A, lda, rows, cols, v, out);
+    else if (xtype == XT_F32)
+        hipLaunchKernelGGL((k_matvec<float>), grid, dim3(256), 0, s, (const float *)A, lda, rows, cols, v, out);
+    else
+        hipLaunchKernelGGL((k_matvec<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)A, lda, rows, cols, v, out);
+}
+
+void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
+                      int npad, int pm)
+{
+    (void)pm;
+    dim3 grid((p + 31) / 32, (n + 31) / 32);
+    if (xtype == XT_F64)
+        hipLaunchKernelGGL((k_transpose<double>), grid, dim3(256), 0, s, (const double *)X, (double *)XT, n, p, ldp, npad);
+    else if (xtype == XT_F32)
+        hipLaunchKernelGGL((k_transpose<float>), grid, dim3(256), 0, s, (const float *)X, (float *)XT, n, p, ldp, npad);
+    else
+        hipLaunchKernelGGL((k_transpose<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)X, (uint16_t *)XT, n, p, ldp, npad);
+}
+
+}  // namespace kbnb

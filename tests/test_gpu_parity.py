@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Every test prints its case before the first GPU call, so a failing GPU run
+names it.  Tolerances:
+  * prox, primal and dual values at the same input: both sides compute the
+    same float64 formulas in different orders; relative 1e-11 (values are
+    sums of up to n terms of magnitude ~1, so rounding stays near 1e-13);
+  * node bounds: validity LB_gpu <= Phi_oracle (the oracle's primal value is
+    an upper bound on the node optimum, at 1e-12 relative slack for
+    rounding) and accuracy LB_gpu >= Psi_oracle - 1e-6 |Psi_oracle|, where
+    the oracle is run to a 1e-10 relative gap;
+  * rounding supports and branching indices at the same beta: bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_22188_amd as K
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def edge_states(r, p, k, m):
+    """Random node states plus the degenerate budgets: kbar 0, 1, #free-1,
+    #free, > #free, and no free coordinate at all."""
+    states = []
+    for b in range(m):
+        st = np.zeros(p, np.int8)
+        perm = r.permutation(p)
+        kind = b % 8
+        if kind == 0:      # kbar = 0
+            n1, n0 = k, int(r.integers(0, p - k + 1))
+        elif kind == 1:    # kbar = 1
+            n1, n0 = k - 1, int(r.integers(0, p - k + 1))
+        elif kind == 2:    # #free = kbar + 1
+            n1 = int(r.integers(0, k))
+            n0 = p - n1 - (k - n1) - 1
+        elif kind == 3:    # #free = kbar
+            n1 = int(r.integers(0, k))
+            n0 = p - n1 - (k - n1)
+        elif kind == 4:    # #free < kbar
+            n1 = 0
+            n0 = p - max(1, k // 2)
+        elif kind == 5:    # nothing free
+            n1 = min(k, p)
+            n0 = p - n1
+        else:
+            n1 = int(r.integers(0, k + 1))
+            n0 = int(r.integers(0, p - n1 + 1))
+        n0 = max(0, min(n0, p - n1))
+        st[perm[:n1]] = 1
+        st[perm[n1:n1 + n0]] = -1
+        states.append(st)
+    return np.array(states)
+
+
+@pytest.mark.parametrize("p,k", [(30, 5), (200, 10), (257, 12), (1000, 10), (2048, 40)])
+def test_prox_batch_matches_oracle(p, k):
+    announce(f"prox_batch p={p} k={k}")
+    r = rng(100 + p)
+    inst = W.small_instance(64, p, k, W.SQUARED, seed=p, M=1.5, lambda2=0.8)
+    h = K.create_from_instance(inst, batch_width=64)
+    P = oracle.Problem.from_instance(inst)
+    m = 48
+    states = edge_states(r, p, k, m)
+    u = r.normal(size=(m, p)) * r.uniform(0.2, 3.0, size=(m, 1))
+    u[::3] = np.round(u[::3], 1)  # many exact ties
+    for eta in (0.05, 0.7, 4e-4):
+        got = K.prox_batch(h, states, u, eta)
+        for b in range(m):
+            ref = P.prox(states[b], eta, u[b])
+            err = np.max(np.abs(got[b] - ref))
+            assert err <= 1e-12 * max(1.0, np.max(np.abs(u[b]))), (b, eta, err)
+            assert np.array_equal(got[b] == 0.0, ref == 0.0), (b, eta)
+    K.destroy_problem(h)
+
+
+def _certify_case(inst, m, seed):
+    r = rng(seed)
+    h = K.create_from_instance(inst, batch_width=64)
+    P = oracle.Problem.from_instance(inst)
+    p, k = inst.p, inst.k
+    states = edge_states(r, p, k, m)
+    betas = np.empty((m, p))
+    for b in range(m):
+        u = r.normal(size=p) * r.uniform(0.05, 1.0)
+        betas[b] = P.prox(states[b], r.uniform(0.05, 2.0) / 10, u)
+    betas[::4] = np.round(betas[::4], 2)   # ties in |beta|
+    for b in range(0, m, 4):               # keep them in dom g
+        betas[b] = P.prox(states[b], 1e-9, betas[b])
+    phi, psi, sup, br = K.certify_batch(h, states, betas)
+    for b in range(m):
+        phi_o = P.primal(states[b], betas[b])
+        psi_o = P.dual(states[b], P.dual_point(betas[b]))
+        assert phi[b] == pytest.approx(phi_o, rel=1e-11), b
+        assert psi[b] == pytest.approx(psi_o, rel=1e-11), b
+        s_o, br_o = P.round_branch(states[b], betas[b])
+        assert list(sup[b][:len(s_o)]) == list(s_o), b
+        assert np.all(sup[b][len(s_o):] == -1), b
+        assert br[b] == br_o, b
+    K.destroy_problem(h)
+
+
+def test_certify_batch_logistic_5000x200():
+    announce("certify_batch logistic 5000x200 f32")
+    _certify_case(W.node_bounds_logistic_5000x200(), 64, 7)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_certify_batch_ragged_dtypes(dtype):
+    announce(f"certify_batch squared 777x61 {dtype}")
+    inst = W.small_instance(777, 61, 7, W.SQUARED, seed=3, dtype=dtype)
+    _certify_case(inst, 40, 11)
+
+
+def _bound_parity(inst, nodes, batch_width, cert_period, warm=None, sample=None):
+    h = K.create_from_instance(inst, batch_width=batch_width, cert_period=cert_period)
+    P = oracle.Problem.from_instance(inst)
+    res = K.bound_nodes(h, nodes, rel_tol=1e-6, warm_starts=warm)
+    idx = range(len(nodes)) if sample is None else sample
+    for i in idx:
+        st = W.node_state(inst.p, nodes[i])
+        ref = P.node_bound(st, tol=1e-10, max_iter=100000)
+        g = res[i]
+        assert g["status"] == K.CONVERGED, (i, g)
+        assert g["rel_gap"] <= 1e-6
+        assert g["lower_bound"] <= ref["phi"] + 1e-12 * abs(ref["phi"]), (i, g["lower_bound"], ref)
+        assert g["lower_bound"] >= ref["lb"] - 1e-6 * abs(ref["lb"]), (i, g["lower_bound"], ref)
+        # the returned rounding support is the top-kbar of the returned beta
+        s_o, br_o = P.round_branch(st, g["beta"])
+        assert list(g["support"]) == list(s_o)
+        assert g["branch_index"] == br_o
+    K.destroy_problem(h)
+    return res
+
+
+@pytest.mark.parametrize("loss", [W.SQUARED, W.LOGISTIC])
+def test_node_bounds_small_all_nodes(loss):
+    announce(f"node bounds 700x50 loss={loss}, 100 nodes on 64 slots")
+    inst = W.small_instance(700, 50, 6, loss, seed=5 + loss, rho=0.6)
+    nodes = W.random_nodes(50, 100, 3, 15, seed=77)
+    _bound_parity(inst, nodes, batch_width=64, cert_period=4)
+
+
+def test_node_bounds_logistic_5000x200_launch():
+    announce("node bounds logistic 5000x200, one 256-node launch, 16 sampled")
+    inst = W.node_bounds_logistic_5000x200()
+    nodes = W.launch_nodes_5000x200(0)
+    sample = list(range(0, 256, 16))
+    res = _bound_parity(inst, nodes, batch_width=256, cert_period=8, sample=sample)
+    assert all(r["status"] == K.CONVERGED for r in res)
+
+
+def test_node_bounds_float64_instance():
+    announce("node bounds squared 500x30 f64")
+    inst = W.plain_bnb_squared_500x30()
+    nodes = W.random_nodes(30, 40, 4, 10, seed=9)
+    _bound_parity(inst, nodes, batch_width=64, cert_period=8)
+
+
+def test_batch_width_one():
+    announce("node bounds batch width 1")
+    inst = W.small_instance(300, 20, 4, W.LOGISTIC, seed=2)
+    nodes = W.random_nodes(20, 5, 2, 5, seed=3)
+    _bound_parity(inst, nodes, batch_width=1, cert_period=8)
+
+
+def test_warm_start_and_prune_decisions():
+    announce("prune decisions logistic 2000x80")
+    inst = W.small_instance(2000, 80, 8, W.LOGISTIC, seed=12)
+    P = oracle.Problem.from_instance(inst)
+    nodes = W.random_nodes(80, 60, 4, 20, seed=13)
+    refs = [P.node_bound(W.node_state(80, nd), tol=1e-10) for nd in nodes]
+    r = rng(14)
+    ubs = np.array([ref["phi"] * (1 + r.choice([-0.02, 0.02])) for ref in refs])
+    h = K.create_from_instance(inst, batch_width=64, cert_period=4)
+    warm = [ref["beta"] if i % 2 else None for i, ref in enumerate(refs)]
+    res = K.bound_nodes(h, nodes, upper_bound=ubs, rel_tol=1e-6, warm_starts=warm)
+    band = 0
+    for ref, ub, g in zip(refs, ubs, res):
+        v = ref["lb"]
+        thr = ub - 1e-6 * abs(ub)
+        if abs(v - thr) <= 2e-6 * abs(ub):
+            band += 1
+            continue
+        assert (g["status"] == K.PRUNED) == (v >= thr), (v, ub, g)
+        assert g["lower_bound"] <= ref["phi"] * (1 + 1e-12)
+    assert band == 0
+    K.destroy_problem(h)
+
+
+def test_invalid_nodes_are_rejected_atomically():
+    announce("invalid submissions")
+    inst = W.small_instance(100, 10, 3, W.SQUARED, seed=1)
+    h = K.create_from_instance(inst, batch_width=8)
+    good = ([0], [1, 2])
+    for bad in [([10], []), ([0, 0], []), ([0], [0]), ([0, 1, 2, 3], []), ([-1], [])]:
+        with pytest.raises(K.KbnbError):
+            K.submit_nodes(h, [good, bad])
+    K.submit_nodes(h, [])
+    res, rc = K.poll_bounds(h, cap=4, timeout_us=0)
+    assert res == [] and rc == K.TIMEOUT
+    out = K.bound_nodes(h, [good])
+    assert out[0]["status"] == K.CONVERGED
+    K.destroy_problem(h)
+
+
+def test_bnb_plain_squared_500x30_on_gpu():
+    announce("branch_and_bound squared 500x30 f64")
+    inst = W.plain_bnb_squared_500x30()
+    P = oracle.Problem.from_instance(inst)
+    ref = P.bnb()
+    h = K.create_from_instance(inst, batch_width=64)
+    out = K.branch_and_bound(h)
+    assert out["status"] == 0
+    assert list(out["support"]) == list(ref["support"])
+    assert out["objective"] == pytest.approx(ref["objective"], rel=1e-6)
+    assert out["lower_bound"] <= ref["objective"] * (1 + 1e-9)
+    K.destroy_problem(h)
