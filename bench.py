@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Certified node bounds per second on the batched node-bound path.
+
+Workload (the paper's batched node-bound setting, synthetic data): logistic
+loss, X 5000 x 200 float32 with AR(1) column correlation rho = 0.5, k = 10,
+10 true nonzeros of magnitude 1, lambda2 = 1, M = 2; each step bounds one
+batch of 256 nodes (|J1| ~ U{0..5}, |J0| ~ U{0..60}, batch seed 1000 + step)
+to a 1e-6 relative duality gap, with UB = +inf so every node is solved.
+
+A step = submit the batch's 256 node descriptors through submit_nodes and
+collect all 256 certified bounds through poll_bounds.  X and y are resident
+in device memory before the timed region; the node descriptors (about 100
+bytes each) cross PCIe inside it.
+
+Printed JSON line: the contract fields plus
+  roofline      the dominant kernel's algorithmic rate against its peak, from
+                a kernel-timed pass (hipEvent pairs on the engine stream)
+  cpu_baseline  the float64 oracle on a bounded sample of the same nodes
+  comparator    the same library at batch width 1 (one node at a time)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "certified node bounds/s at 1e-6 rel. accuracy; time-to-zero-gap; p50/p99 latency"
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_batch(K, h, nodes, tol):
+    """Submit one batch and wait for every result; returns (results, latencies_s)."""
+    t0 = time.perf_counter()
+    K.submit_nodes(h, nodes, tags=list(range(len(nodes))), rel_tol=tol)
+    got, lat = {}, []
+    while len(got) < len(nodes):
+        res, rc = K.poll_bounds(h, cap=len(nodes), timeout_us=-1, supports=False, betas=False)
+        now = time.perf_counter()
+        for r in res:
+            got[r["tag"]] = r
+            lat.append(now - t0)
+        if not res and rc == K.TIMEOUT:
+            raise RuntimeError("engine idle with nodes outstanding")
+    return [got[i] for i in range(len(nodes))], lat
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--cert-period", type=int, default=8)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cpu-nodes", type=int, default=24,
+                    help="oracle sample size for the CPU baseline (0 = skip)")
+    ap.add_argument("--comparator-nodes", type=int, default=32,
+                    help="nodes bounded one at a time at batch width 1 (0 = skip)")
+    ap.add_argument("--profile-steps", type=int, default=3)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        msg = ("this benchmark runs on exactly one GPU: the batched node-bound path is "
+               "measured on one device; multi-GPU sharding is described, not run")
+        print(msg, file=sys.stderr)
+        if int(os.environ.get("RANK", "0")) == 0:
+            print(json.dumps({"metric": METRIC, "error": msg, "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2605_22188_amd as K
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    inst = W.node_bounds_logistic_5000x200()
+    X = torch.from_numpy(inst.X_store).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    h = K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
+                         batch_width=args.batch, cert_period=args.cert_period)
+    t_setup = time.perf_counter() - t_setup
+    info = K.problem_info(h)
+    log(f"problem ready in {t_setup:.2f}s: {info}")
+
+    total = args.warmup + args.steps + args.profile_steps
+    batches = [W.launch_nodes_5000x200(i, args.batch) for i in range(total)]
+
+    for w in range(args.warmup):
+        run_batch(K, h, batches[w], args.tol)
+    log(f"warmup done ({args.warmup} steps)")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat_all, iters, status_bad, gaps = [], [], 0, []
+    for s in range(args.steps):
+        res, lat = run_batch(K, h, batches[args.warmup + s], args.tol)
+        lat_all += lat
+        for r in res:
+            iters.append(r["iterations"])
+            gaps.append(r["rel_gap"])
+            status_bad += r["status"] != K.CONVERGED
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nodes_done = args.steps * args.batch
+    value = nodes_done / elapsed
+    log(f"timed: {nodes_done} nodes in {elapsed:.4f}s -> {value:.1f} node bounds/s")
+
+    # kernel-timed pass (same configuration, fresh batches)
+    K.kernel_stats(h, 1)
+    for s in range(args.profile_steps):
+        run_batch(K, h, batches[args.warmup + args.steps + s], args.tol)
+    ks = K.kernel_stats(h, 0)
+    n, p = inst.n, inst.p
+    launches = ks["launches"]
+    tot = ks["total_ms"]
+    iter_launches = max(1, launches["fwd_xy"])
+    useful_per_launch = ks["useful_cols"] / iter_launches       # sum_b (p - |J0_b|)
+    slots_per_launch = ks["running_cols"] / iter_launches
+    alg = {  # algorithmic flops per launch
+        "fwd_xy": 2.0 * n * useful_per_launch,
+        "bwd_xtr": 2.0 * n * useful_per_launch,
+        "cert_xb": 2.0 * n * useful_per_launch,
+        "cert_xtz": 2.0 * n * useful_per_launch,
+    }
+    dtype_of = {"fwd_xy": "f32", "bwd_xtr": "f32", "cert_xb": "f64", "cert_xtz": "f64"}
+    kern = {}
+    for name in K.KERNEL_NAMES:
+        if launches[name]:
+            avg_ms = tot[name] / launches[name]
+            d = dict(avg_us=avg_ms * 1e3, launches=int(launches[name]),
+                     share=tot[name] / max(1e-12, sum(tot.values())))
+            if name in alg:
+                d["alg_tflops"] = alg[name] / (avg_ms * 1e-3) / 1e12
+                d["frac_of_peak"] = d["alg_tflops"] / PEAK_TFLOPS[dtype_of[name]]
+            kern[name] = d
+    dominant = max((k for k in kern), key=lambda k: tot[k])
+    if dominant in alg:
+        a = kern[dominant]["alg_tflops"]
+        pk = PEAK_TFLOPS[dtype_of[dominant]]
+        roofline = {"bound": "mfma", "achieved": round(a, 3), "peak": pk, "unit": "TFLOP/s",
+                    "frac": round(a / pk, 4), "traffic": None, "kernel": dominant,
+                    "avg_us": round(kern[dominant]["avg_us"], 3),
+                    "alg_flops_per_launch": alg[dominant]}
+    else:
+        roofline = {"bound": "alu", "achieved": None, "peak": None, "unit": None,
+                    "frac": None, "traffic": None, "kernel": dominant}
+    log(f"kernels: {json.dumps(kern)}")
+
+    # comparator: the same library, one node at a time
+    comparator = None
+    if args.comparator_nodes > 0:
+        h1 = K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
+                              batch_width=1, cert_period=args.cert_period)
+        sample = batches[0][:args.comparator_nodes]
+        run_batch(K, h1, sample[:2], args.tol)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        for nd in sample:
+            run_batch(K, h1, [nd], args.tol)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - tc
+        crate = len(sample) / tc
+        comparator = {"value": round(crate, 2), "unit": "node bounds/s", "batch_width": 1,
+                      "nodes": len(sample), "speedup": round(value / crate, 2)}
+        K.destroy_problem(h1)
+        log(f"comparator batch width 1: {crate:.1f} node bounds/s")
+
+    cpu = None
+    if args.cpu_nodes > 0:
+        import oracle
+        P = oracle.Problem.from_instance(inst)
+        P.lipschitz()
+        sample = batches[0][:args.cpu_nodes]
+        tcpu = time.perf_counter()
+        for nd in sample:
+            P.node_bound(W.node_state(p, nd), tol=args.tol)
+        tcpu = time.perf_counter() - tcpu
+        cpu = {"value": round(len(sample) / tcpu, 4), "unit": "node bounds/s", "cores": 1,
+               "kind": "oracle",
+               "sample": (f"first {len(sample)} nodes of batch seed 1000 of the 5000x200 logistic "
+                          f"workload, rel. tol {args.tol:g}, float64, one thread, "
+                          f"{tcpu:.1f}s")}
+        log(f"cpu oracle: {cpu['value']} node bounds/s")
+
+    lat_ms = np.array(lat_all) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "node bounds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "logistic_5000x200_f32_256nodes", "n": n, "p": p, "k": inst.k,
+                   "loss": "logistic", "nodes_per_step": args.batch,
+                   "batch_width": info["batch_width"], "rel_tol": args.tol,
+                   "cert_period": args.cert_period, "certificate_dtype": "f64",
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4),
+                       "measure": "submit of the step's batch to the node's result at poll"},
+        "iterations": {"mean": round(float(np.mean(iters)), 2), "max": int(np.max(iters))},
+        "not_converged": int(status_bad),
+        "max_rel_gap": float(np.max(gaps)),
+        "useful_fraction": round(useful_per_launch / max(1.0, slots_per_launch * p), 4),
+        "roofline": roofline,
+        "kernels": kern,
+        "cpu_baseline": cpu,
+        "comparator": comparator,
+        "setup_s": round(t_setup, 3),
+    }
+    K.destroy_problem(h)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -224,6 +224,21 @@ int certify_batch(kbnb_problem *prob, int32_t m, const int8_t *states,
  * d_out[0..3] = smoothness constant L, lambda2, M, device bytes in use. */
 int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
 
+/*
+ * kernel_stats -- instrumentation of the engine's kernels (for roofline
+ * reporting).  mode 1: reset the counters and time every kernel of the
+ * following rounds with a hipEvent pair on the engine stream (rounds are then
+ * issued as direct launches instead of the captured graph); mode 0: stop
+ * timing; mode -1: leave the mode unchanged.  out (nullable, 18 doubles)
+ * receives the counters before the mode change: out[0..7] total milliseconds
+ * of the kernel types {forward X Y, backward X^T R, prox, certificate X B,
+ * certificate X^T zeta, certificate finish, admission, split-K reduction},
+ * out[8..15] their launch counts, out[16] the sum over timed iteration
+ * launches of sum_b (p - |J0_b|) over the nodes in the batch, out[17] the sum
+ * over timed iteration launches of the number of nodes in the batch.
+ */
+int kernel_stats(kbnb_problem *prob, int32_t mode, double *out);
+
 #ifdef __cplusplus
 }
 #endif

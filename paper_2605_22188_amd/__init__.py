@@ -72,7 +72,8 @@ class BnbResult(ctypes.Structure):
 
 
 EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
-           "branch_and_bound", "last_error", "prox_batch", "certify_batch", "problem_info"]
+           "branch_and_bound", "last_error", "prox_batch", "certify_batch", "problem_info",
+           "kernel_stats"]
 
 _lib = None
 
@@ -97,6 +98,7 @@ def load():
         lib.prox_batch.argtypes = [vp, i32, vp, vp, dbl, vp]
         lib.certify_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         lib.problem_info.argtypes = [vp, vp, vp]
+        lib.kernel_stats.argtypes = [vp, i32, vp]
         for name in EXPORTS:
             if name != "last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -286,3 +288,17 @@ def create_from_instance(inst, **kw):
     (fields X_store, dtype, y, k, loss, lambda2, M)."""
     return create_problem(inst.X_store, inst.y, inst.k, inst.loss, inst.lambda2, inst.M,
                           dtype=inst.dtype, **kw)
+
+
+KERNEL_NAMES = ["fwd_xy", "bwd_xtr", "prox", "cert_xb", "cert_xtz", "cert_finish", "admit",
+                "reduce"]
+
+
+def kernel_stats(h: Handle, mode=-1):
+    """mode 1: reset and start timing kernels; 0: stop; -1: read only.
+    Returns the counters as they were before the mode change."""
+    out = np.zeros(18)
+    _check(load().kernel_stats(h.ptr, int(mode), _p(out)))
+    ms = dict(zip(KERNEL_NAMES, out[0:8]))
+    cnt = dict(zip(KERNEL_NAMES, out[8:16].astype(np.int64)))
+    return dict(total_ms=ms, launches=cnt, useful_cols=float(out[16]), running_cols=float(out[17]))

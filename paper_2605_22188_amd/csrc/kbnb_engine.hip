@@ -70,7 +70,7 @@ struct PendingNode {
     uint64_t tag;
     std::vector<int8_t> st;  // ldp entries
     std::vector<double> warm; // empty or p entries
-    int kbar;
+    int kbar, n0;
     double ub, tol;
     int max_iter;
 };
@@ -88,7 +88,7 @@ struct kbnb_problem {
     bool iter_f64 = false;
     int ti_bytes = 4;
     // sizes
-    int ldp = 0, npad = 0, pm = 0, m = 0, mpad = 0;
+    int ldp = 0, npad = 0, pm = 0, m = 0, mpad = 0, pp = 256;
     int gsplit = 1, gchunk = 0, qsplit = 1, qchunk = 0, tiles_n = 0;
     int cert_period = 8;
     uint64_t budget = 0, bytes = 0;
@@ -98,6 +98,8 @@ struct kbnb_problem {
     void *X = nullptr, *XT = nullptr, *Yi = nullptr, *R = nullptr, *Gp = nullptr;
     double *y = nullptr, *B = nullptr, *Bprev = nullptr, *Z = nullptr, *Qp = nullptr;
     double *lsum = nullptr, *csum = nullptr, *gbuf = nullptr;
+    void *Gsum = nullptr;      // reduced gradient [mpad][ldp], iteration type
+    double *Qsum = nullptr;    // reduced X^T zeta [mpad][ldp]
     int8_t *st = nullptr;
     uint8_t *stage_d = nullptr;
     int32_t *gslots_d = nullptr;
@@ -109,6 +111,9 @@ struct kbnb_problem {
     double *h_lb = nullptr, *h_phi = nullptr, *h_gap = nullptr;
     int32_t *h_gslots = nullptr;
     double *h_gbuf = nullptr;
+    char *slot_dev = nullptr;   // contiguous device block of the slot arrays
+    char *slot_host = nullptr;  // pinned mirror of that block
+    size_t slot_bytes = 0;
     hipStream_t stream = nullptr;
     hipGraphExec_t graph = nullptr;
     Consts c{};
@@ -128,6 +133,14 @@ struct kbnb_problem {
     std::mutex api_mu;  // serialises calls on this handle
     // stats
     std::atomic<long> rounds{0};
+    // kernel timing (instrumentation): per kernel type total ms and launches
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    double kt_ms[8] = {0};
+    int64_t kt_n[8] = {0};
+    double useful_cols = 0;   // sum over timed iteration launches of sum_b (p - |J0_b|)
+    double running_cols = 0;  // sum over timed iteration launches of running slots
+    std::vector<int> slot_n0; // |J0| of the node in each slot
 };
 
 static int round_pow2_down(int64_t v)
@@ -155,6 +168,8 @@ static size_t per_slot_bytes(const kbnb_problem *P)
     b += (size_t)P->qsplit * P->ldp * 8;               // Qp
     b += (size_t)P->tiles_n * 16;                      // lsum, csum
     b += (size_t)P->ldp * 8 + 128 + P->k * 4;          // gather buffer, scalars, support
+    b += (size_t)P->ldp * (ti + 8);                    // reduced G and Q
+    b += (size_t)P->pp * 4;                            // sort permutation
     return b;
 }
 
@@ -163,7 +178,7 @@ static void choose_splits(kbnb_problem *P)
     // backward products: enough workgroups to cover the 256 CUs a few times
     const int tiles = (P->pm / GEMM_BM) * (P->mpad / GEMM_BN);
     const int kt = P->npad / GEMM_BK;  // 16-wide k chunks
-    int want = std::max(1, (768 + tiles - 1) / tiles);
+    int want = std::max(1, (256 + tiles - 1) / tiles);
     want = std::min(want, std::max(1, kt / 4));
     int chunk = (int)round_up((P->npad + want - 1) / want, GEMM_BK);
     P->gchunk = chunk;
@@ -197,6 +212,9 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         mp * 8 * 7,                              // double slot arrays
         mp * 4 * 7,                              // int slot arrays
         mp * P->k * 4,                           // supports
+        mp * P->ldp * ti,                        // G (reduced)
+        mp * P->ldp * 8,                         // Q (reduced)
+        mp * (size_t)P->pp * 4,                  // sort permutations
     };
     const int nitems = sizeof(sizes) / sizeof(sizes[0]);
     size_t off[32];
@@ -252,6 +270,11 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
     P->ss.jstar = ii + 4 * mp;
     P->ss.slen = ii + 5 * mp;
     P->ss.sup = (int32_t *)(base + off[18]);
+    P->ss.perm = (int32_t *)(base + off[21]);
+    P->Gsum = base + off[19];
+    P->Qsum = (double *)(base + off[20]);
+    P->slot_dev = base + off[16];
+    P->slot_bytes = off[18] + sizes[18] - off[16];
     return 0;
 }
 
@@ -262,13 +285,53 @@ static void enqueue_round(kbnb_problem *P)
 {
     hipStream_t s = P->stream;
     for (int it = 0; it < P->cert_period; ++it) {
-        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, P->c);
-        launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c);
+        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, P->c, P->ss.status);
+        launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c, P->ss.status);
         launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
     }
-    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c);
-    launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c);
+    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c, P->ss.status);
+    launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
     launch_cert_finish(s, P->Qp, P->qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
+}
+
+// Kernel types for the timing instrumentation.
+enum { KT_FWD = 0, KT_BWD = 1, KT_PROX = 2, KT_CFWD = 3, KT_CBWD = 4, KT_CFIN = 5, KT_ADMIT = 6, KT_RED = 7 };
+
+// Same launches as enqueue_round, each bracketed by a hipEvent pair on the
+// engine stream; the elapsed times are read after the round synchronises.
+static int enqueue_round_timed(kbnb_problem *P, std::vector<int> &kinds)
+{
+    hipStream_t s = P->stream;
+    const size_t need = 2 * (4 * (size_t)P->cert_period + 4);
+    while (P->ev.size() < need) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        P->ev.push_back(e);
+    }
+    kinds.clear();
+    size_t q = 0;
+    auto mark = [&](int kind) { kinds.push_back(kind); return P->ev[q++]; };
+    for (int it = 0; it < P->cert_period; ++it) {
+        HIP_TRY(hipEventRecord(mark(KT_FWD), s));
+        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, P->c, P->ss.status);
+        HIP_TRY(hipEventRecord(P->ev[q++], s));
+        HIP_TRY(hipEventRecord(mark(KT_BWD), s));
+        launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c, P->ss.status);
+        HIP_TRY(hipEventRecord(P->ev[q++], s));
+        HIP_TRY(hipEventRecord(mark(KT_PROX), s));
+        launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
+        HIP_TRY(hipEventRecord(P->ev[q++], s));
+    }
+    HIP_TRY(hipEventRecord(mark(KT_CFWD), s));
+    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c, P->ss.status);
+    HIP_TRY(hipEventRecord(P->ev[q++], s));
+    HIP_TRY(hipEventRecord(mark(KT_CBWD), s));
+    launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
+    HIP_TRY(hipEventRecord(P->ev[q++], s));
+    HIP_TRY(hipEventRecord(mark(KT_CFIN), s));
+    launch_cert_finish(s, P->Qp, P->qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
+    HIP_TRY(hipEventRecord(P->ev[q++], s));
+    return 0;
 }
 
 static int build_graph(kbnb_problem *P)
@@ -327,11 +390,22 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
             memcpy(rec + woff, nd.warm.data(), sizeof(double) * P->p);
         }
         P->slot_tag[slot] = nd.tag;
+        P->slot_n0[slot] = nd.n0;
         ++P->active;
         ++nadm;
         adm_slots.push_back(slot);
     }
     if (P->active == 0) return 0;
+    double run_useful = 0, run_slots = 0;
+    if (P->timing) {
+        std::vector<char> is_free(P->m, 0);
+        for (int b : P->free_slots) is_free[b] = 1;
+        for (int b = 0; b < P->m; ++b)
+            if (!is_free[b]) {
+                run_useful += P->p - P->slot_n0[b];
+                run_slots += 1;
+            }
+    }
     P->busy = true;
     lk.unlock();
     hipStream_t s = P->stream;
@@ -341,21 +415,28 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
             HIP_TRY(hipMemcpyAsync(P->stage_d, P->stage_h, (size_t)nadm * P->rec_bytes, hipMemcpyHostToDevice, s));
             launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
         }
-        if (P->graph) {
+        std::vector<int> kinds;
+        const bool timed = P->timing;
+        if (timed) {
+            int trc = enqueue_round_timed(P, kinds);
+            if (trc) return trc;
+        } else if (P->graph) {
             HIP_TRY(hipGraphLaunch(P->graph, s));
         } else {
             enqueue_round(P);
         }
-        const size_t mb = (size_t)P->m;
-        HIP_TRY(hipMemcpyAsync(P->h_status, P->ss.status, mb * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(P->h_iter, P->ss.iter, mb * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(P->h_jstar, P->ss.jstar, mb * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(P->h_slen, P->ss.slen, mb * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(P->h_sup, P->ss.sup, mb * P->k * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(P->h_lb, P->ss.lb, mb * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(P->h_phi, P->ss.phi, mb * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(P->h_gap, P->ss.gap, mb * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(P->slot_host, P->slot_dev, P->slot_bytes, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (timed) {
+            for (size_t e = 0; e < kinds.size(); ++e) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, P->ev[2 * e], P->ev[2 * e + 1]));
+                P->kt_ms[kinds[e]] += ms;
+                P->kt_n[kinds[e]] += 1;
+            }
+            P->useful_cols += run_useful * P->cert_period;
+            P->running_cols += run_slots * P->cert_period;
+        }
         // 3. retire finished slots
         int nfin = 0;
         for (int b = 0; b < P->m; ++b) {
@@ -501,9 +582,9 @@ static void free_problem(kbnb_problem *P)
     }
     if (P->stream) (void)hipStreamSynchronize(P->stream);
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
+    for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     if (P->arena) (void)hipFree(P->arena);
-    void *pins[] = {P->stage_h, P->h_status, P->h_iter, P->h_jstar, P->h_slen, P->h_sup,
-                    P->h_lb, P->h_phi, P->h_gap, P->h_gslots, P->h_gbuf};
+    void *pins[] = {P->stage_h, P->slot_host, P->h_gslots, P->h_gbuf};
     for (void *q : pins)
         if (q) (void)hipHostFree(q);
     if (P->stream) (void)hipStreamDestroy(P->stream);
@@ -546,6 +627,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->iter_f64 = (d->x_dtype == KBNB_DTYPE_F64);
     P->ti_bytes = P->iter_f64 ? 8 : 4;
     P->ldp = (int)round_up(P->p, 16);
+    while (P->pp < P->p) P->pp *= 2;
     P->npad = (int)round_up(P->n, 64);
     P->pm = (int)round_up(P->ldp, 64);
     P->tiles_n = P->npad / GEMM_BM;
@@ -578,6 +660,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->mpad = (int)round_up(m, GEMM_BN);
     choose_splits(P);
     P->slot_tag.assign(P->m, 0);
+    P->slot_n0.assign(P->m, 0);
     for (int b = P->m - 1; b >= 0; --b) P->free_slots.push_back(b);
 
     rc = alloc_arena(P, xbytes, xel);
@@ -607,16 +690,20 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     {
         const size_t mb = P->mpad;
         bool okp = hipHostMalloc((void **)&P->stage_h, mb * P->rec_bytes, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_status, mb * 4, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_iter, mb * 4, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_jstar, mb * 4, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_slen, mb * 4, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_sup, mb * P->k * 4, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_lb, mb * 8, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_phi, mb * 8, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_gap, mb * 8, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->slot_host, P->slot_bytes, 0) == hipSuccess &&
                    hipHostMalloc((void **)&P->h_gslots, mb * 4, 0) == hipSuccess &&
                    hipHostMalloc((void **)&P->h_gbuf, mb * P->p * 8, 0) == hipSuccess;
+        if (okp) {
+            auto view = [&](const void *dev) { return P->slot_host + ((const char *)dev - P->slot_dev); };
+            P->h_status = (int32_t *)view(P->ss.status);
+            P->h_iter = (int32_t *)view(P->ss.iter);
+            P->h_jstar = (int32_t *)view(P->ss.jstar);
+            P->h_slen = (int32_t *)view(P->ss.slen);
+            P->h_sup = (int32_t *)view(P->ss.sup);
+            P->h_lb = (double *)view(P->ss.lb);
+            P->h_phi = (double *)view(P->ss.phi);
+            P->h_gap = (double *)view(P->ss.gap);
+        }
         if (!okp) { free_problem(P); return fail(KBNB_E_OUT_OF_MEMORY, "pinned host allocation failed"); }
     }
     // all slots start empty
@@ -631,6 +718,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     if (rc) { free_problem(P); return rc; }
     P->c.n = P->n; P->c.p = P->p; P->c.k = P->k; P->c.loss = P->loss;
     P->c.ldp = P->ldp; P->c.npad = P->npad; P->c.pm = P->pm; P->c.mpad = P->mpad; P->c.m = P->m;
+    P->c.pp = P->pp;
     P->c.lambda2 = P->lambda2; P->c.M = P->M; P->c.eta = P->eta;
     if (build_graph(P) != 0) {
         (void)hipGetLastError();
@@ -693,6 +781,7 @@ static int submit_locked(kbnb_problem *P, const kbnb_node_desc *nodes, int count
         if (nd.rel_tol < 0 || std::isnan(nd.rel_tol)) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: bad rel_tol", i);
         if (nd.max_iters < 0) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: negative max_iters", i);
         pn.tag = nd.tag;
+        pn.n0 = nd.n_out;
         pn.ub = nd.upper_bound;
         pn.tol = nd.rel_tol > 0 ? nd.rel_tol : 1e-6;
         pn.max_iter = nd.max_iters > 0 ? nd.max_iters : 20000;
@@ -860,12 +949,13 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     Consts c = P->c;
     c.mpad = mpad;
     c.m = m;
-    double *dB, *dZ, *dQ, *dl, *dc, *dlb, *dphi;
+    double *dB, *dZ, *dQ, *dQs, *dl, *dc, *dlb, *dphi;
     int8_t *dst;
     int32_t *dk, *dsup, *djs, *dslen;
     const int qsplit = P->qsplit;
     if ((rc = T.alloc(&dB, bh.size())) || (rc = T.alloc(&dZ, (size_t)mpad * P->npad)) ||
-        (rc = T.alloc(&dQ, (size_t)qsplit * mpad * P->ldp)) || (rc = T.alloc(&dl, (size_t)P->tiles_n * mpad)) ||
+        (rc = T.alloc(&dQ, (size_t)qsplit * mpad * P->ldp)) || (rc = T.alloc(&dQs, (size_t)mpad * P->ldp)) ||
+        (rc = T.alloc(&dl, (size_t)P->tiles_n * mpad)) ||
         (rc = T.alloc(&dc, (size_t)P->tiles_n * mpad)) || (rc = T.alloc(&dlb, (size_t)mpad)) ||
         (rc = T.alloc(&dphi, (size_t)mpad)) || (rc = T.alloc(&dst, st.size())) || (rc = T.alloc(&dk, (size_t)mpad)) ||
         (rc = T.alloc(&dsup, (size_t)mpad * P->k)) || (rc = T.alloc(&djs, (size_t)mpad)) ||
@@ -876,8 +966,8 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     HIP_TRY(hipMemcpyAsync(dk, kbar.data(), (size_t)mpad * 4, hipMemcpyHostToDevice, T.s));
     SlotState ss{};
     ss.lb = dlb; ss.phi = dphi; ss.kbar = dk; ss.sup = dsup; ss.jstar = djs; ss.slen = dslen;
-    launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c);
-    launch_cert_bwd(T.s, P->xtype, P->XT, dZ, dQ, qsplit, P->qchunk, c);
+    launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c, nullptr);
+    launch_cert_bwd(T.s, P->xtype, P->XT, dZ, dQ, qsplit, P->qchunk, c, nullptr);
     launch_cert_finish(T.s, dQ, qsplit, dl, dc, P->tiles_n, dB, dst, ss, c, 0);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(psi, dlb, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));
@@ -885,5 +975,27 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     if (supports) HIP_TRY(hipMemcpyAsync(supports, dsup, (size_t)m * P->k * 4, hipMemcpyDeviceToHost, T.s));
     if (branch) HIP_TRY(hipMemcpyAsync(branch, djs, (size_t)m * 4, hipMemcpyDeviceToHost, T.s));
     HIP_TRY(hipStreamSynchronize(T.s));
+    return KBNB_OK;
+}
+
+extern "C" int kernel_stats(kbnb_problem *P, int32_t mode, double *out)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    std::lock_guard<std::mutex> g(P->mu);
+    if (out) {
+        for (int i = 0; i < 8; ++i) {
+            out[i] = P->kt_ms[i];
+            out[8 + i] = (double)P->kt_n[i];
+        }
+        out[16] = P->useful_cols;
+        out[17] = P->running_cols;
+    }
+    if (mode == 1) {
+        for (int i = 0; i < 8; ++i) { P->kt_ms[i] = 0; P->kt_n[i] = 0; }
+        P->useful_cols = P->running_cols = 0;
+        P->timing = true;
+    } else if (mode == 0) {
+        P->timing = false;
+    }
     return KBNB_OK;
 }

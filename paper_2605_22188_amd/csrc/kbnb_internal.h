@@ -7,10 +7,10 @@
 //   XT  [pm][npad]   the transpose of X (the X^T R products read it k-contiguous)
 //   Yi  [mpad][ldp]  extrapolated point in the iteration type (MFMA operand)
 //   R   [mpad][npad] l'(X Y) in the iteration type
-//   Gp  [gsplit][mpad][ldp] split-K partials of X^T R
+//   Gp  [gsplit][mpad][ldp] split-K partials of X^T R;  G [mpad][ldp] their sum
 //   B, Bprev [mpad][ldp] float64 iterates beta^t, beta^{t-1}
 //   Z   [mpad][npad] float64 dual point zeta = -l'(X beta)
-//   Qp  [qsplit][mpad][ldp] float64 split-K partials of X^T zeta
+//   Qp  [qsplit][mpad][ldp] float64 split-K partials of X^T zeta;  Q their sum
 //   lsum, csum [tiles_n][mpad] float64 per-row-tile sums of l(X beta) and l*(-zeta)
 //   st  [mpad][ldp] int8 node coordinate state (0 free, 1 in, -1 out / padding)
 #pragma once
@@ -45,12 +45,14 @@ struct SlotState {
     int32_t *jstar;   // branching index
     int32_t *slen;    // rounding-support length
     int32_t *sup;     // [mpad][k] rounding support, ascending, -1 padded
+    int32_t *perm;    // [mpad][pp] sorted order of the node's |u| at its last step
 };
 
 // Problem constants passed by value to kernels.
 struct Consts {
     int n, p, k, loss;
     int ldp, npad, pm, mpad, m;
+    int pp;  // per-node sort width: next power of two >= max(p, 256)
     double lambda2, M, eta;
 };
 
@@ -64,17 +66,23 @@ enum XType { XT_F64 = 0, XT_F32 = 1, XT_BF16 = 2 };
 
 // ---- launchers (kbnb_kernels.hip) -----------------------------------------
 // iteration GEMMs (Ti = float for float32/bfloat16... instances, double for float64)
+// `status` (nullable) lets a GEMM tile skip when none of its 64 nodes is running
 void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
-                      void *R, const double *y, const Consts &c);
+                      void *R, const double *y, const Consts &c, const int32_t *status);
 void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
-                void *Gp, int gsplit, int gchunk, const Consts &c);
+                void *Gp, int gsplit, int gchunk, const Consts &c, const int32_t *status);
+// G = sum of split-K partials (float, or double when f64), running columns only
+void launch_reduce(hipStream_t s, bool f64, const void *parts, int nsplit, void *out,
+                   const Consts &c, const int32_t *status);
+// the per-node kernels sum the split-K partials themselves
 void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, double *B,
                       double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c);
 // certificate
 void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,
-                     const double *y, double *lsum, double *csum, const Consts &c);
+                     const double *y, double *lsum, double *csum, const Consts &c,
+                     const int32_t *status);
 void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, double *Qp,
-                     int qsplit, int qchunk, const Consts &c);
+                     int qsplit, int qchunk, const Consts &c, const int32_t *status);
 void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const double *lsum,
                         const double *csum, int tiles_n, const double *B, const int8_t *st,
                         SlotState ss, const Consts &c, int update_state);

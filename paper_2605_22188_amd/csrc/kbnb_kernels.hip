@@ -114,6 +114,34 @@ __device__ __forceinline__ double conj_neg_d(int loss, double zeta, double y)
     return a + b;
 }
 
+// Certificate terms at one entry s of X beta: zeta = -l'(s), l(s) and
+// l*(-zeta).  Logistic, with z = y s, e = exp(-|z|), L1 = log1p(e):
+//   t = sigma(-z) = (z >= 0 ? e : 1) / (1 + e),  zeta = y t,
+//   l(s) = max(-z, 0) + L1,
+//   log t = -(max(z, 0) + L1),  log(1 - t) = -(max(-z, 0) + L1),
+//   l*(-zeta) = t log t + (1 - t) log(1 - t)
+//             = -L1 - t max(z, 0) - (1 - t) max(-z, 0),
+// one exp and one log1p per entry.
+__device__ __forceinline__ void cert_terms(int loss, double s, double y, double &zeta,
+                                           double &lval, double &cval)
+{
+    if (loss == 0) {
+        const double r = y - s;
+        zeta = 2.0 * r;
+        lval = r * r;
+        cval = -zeta * y + 0.25 * zeta * zeta;
+        return;
+    }
+    const double z = y * s;
+    const double e = exp(-fabs(z));
+    const double L1 = log1p(e);
+    const double t = ((z >= 0.0) ? e : 1.0) / (1.0 + e);
+    zeta = y * t;
+    const double zp = fmax(z, 0.0), zn = fmax(-z, 0.0);
+    lval = zn + L1;
+    cval = -L1 - t * zp - (1.0 - t) * zn;
+}
+
 template <typename T> __device__ __forceinline__ T dloss_t(int loss, T s, T y);
 template <> __device__ __forceinline__ float dloss_t<float>(int loss, float s, float y) { return dloss_f(loss, s, y); }
 template <> __device__ __forceinline__ double dloss_t<double>(int loss, double s, double y) { return dloss_d(loss, s, y); }
@@ -144,6 +172,7 @@ struct GemmArgs {
     int k_len;             // total k extent (multiple of 16)
     int k_chunk;           // k per split (multiple of 16)
     int tiles_m;
+    const int32_t *col_status;  // nullable: skip tiles with no running column
     int rows_valid;        // store rows < rows_valid (EPI_STORE)
     int n;                 // rows with data (EPI_DLOSS / EPI_CERT)
     int loss;
@@ -156,9 +185,18 @@ struct GemmArgs {
 template <typename TA, typename TB, typename TC, int MODE>
 __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
 {
-    constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK;
+    constexpr int BM = GEMM_BM, BN = GEMM_BN;
+    // k depth of one LDS stage: 64 (float) or 32 (double) so that a stage's
+    // MFMA work (64 or 32 instructions per wave) covers the next stage's
+    // global-load latency.  A stage is NH sub-blocks of 16; in sub-block h
+    // lane group lg holds k = 16 h + 4 lg .. + 3 (one vector LDS read), and
+    // MFMA step s contracts k in {16 h + 4 g + s : g = 0..3}.
+    constexpr int BK = (sizeof(TC) == 8) ? 32 : 64;
+    constexpr int NH = BK / 16;
     constexpr int PAD = (sizeof(TC) == 8) ? 2 : 4;
-    constexpr int LS = BK + PAD;  // LDS row stride (elements)
+    constexpr int LS = BK + PAD;                      // LDS row stride (elements)
+    constexpr int GPR = BK / 4;                       // 4-element groups per row
+    constexpr int LPT = (BM * GPR) / 256;             // groups per thread per operand
     typedef typename V4<TC>::t acc_t;
     __shared__ TC As[2][BM * LS];
     __shared__ TC Bs[2][BN * LS];
@@ -177,13 +215,20 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     const int row0 = tm * BM, col0 = tn * BN;
     const int kbeg = split * g.k_chunk;
     const int kend = min(g.k_len, kbeg + g.k_chunk);
+    if (g.col_status) {
+        // nodes that finished keep their columns, but a tile whose 64 nodes
+        // are all finished (or empty) has nothing to compute
+        const int run = (tid < BN) ? (g.col_status[col0 + tid] == SLOT_RUNNING) : 0;
+        if (!__syncthreads_or(run)) return;
+    }
+    // 16-row MFMA blocks wholly at or beyond row_limit hold only padding
+    const int row_limit = (MODE == EPI_STORE) ? g.rows_valid : (g.tiles_m * BM);
+    bool blk_on[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) blk_on[i] = row0 + wm * 32 + i * 16 < row_limit;
 
     const TA *A = reinterpret_cast<const TA *>(g.A);
     const TB *Bg = reinterpret_cast<const TB *>(g.B);
-    // each thread stages one 4-element group of A and one of B per chunk
-    const int sr = tid >> 2, sq = (tid & 3) * 4;
-    const TA *a_src = A + (int64_t)(row0 + sr) * g.lda + sq;
-    const TB *b_src = Bg + (int64_t)(col0 + sr) * g.ldb + sq;
 
     acc_t acc[2][2];
 #pragma unroll
@@ -192,49 +237,76 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
         for (int j = 0; j < 2; ++j)
             acc[i][j] = acc_t{0, 0, 0, 0};
 
-    TC ra[4], rb[4];
-    if (kbeg < kend) {
-        ld4(a_src + kbeg, ra);
-        ld4(b_src + kbeg, rb);
+    // staging: thread t loads groups t, t + 256, ... of each operand tile;
+    // group x covers row x / GPR, k = 4 (x % GPR) .. + 3 of the stage
+    TC ra[LPT][4], rb[LPT][4];
+    auto load_stage = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            As[0][sr * LS + sq + e] = ra[e];
-            Bs[0][sr * LS + sq + e] = rb[e];
+        for (int v = 0; v < LPT; ++v) {
+            const int x = tid + 256 * v;
+            const int r = x / GPR, kq = 4 * (x % GPR);
+            // branch-free: a group past kend re-reads k = kbeg (always valid)
+            // and is zeroed, so all loads of the stage are in flight together
+            const bool ok = k0 + kq < kend;
+            const int kk = ok ? k0 + kq : kbeg;
+            ld4(A + (int64_t)(row0 + r) * g.lda + kk, ra[v]);
+            ld4(Bg + (int64_t)(col0 + r) * g.ldb + kk, rb[v]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ra[v][e] = ok ? ra[v][e] : (TC)0;
+                rb[v][e] = ok ? rb[v][e] : (TC)0;
+            }
         }
+    };
+    auto store_stage = [&](int bufi) {
+#pragma unroll
+        for (int v = 0; v < LPT; ++v) {
+            const int x = tid + 256 * v;
+            const int r = x / GPR, kq = 4 * (x % GPR);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                As[bufi][r * LS + kq + e] = ra[v][e];
+                Bs[bufi][r * LS + kq + e] = rb[v][e];
+            }
+        }
+    };
+
+    if (kbeg < kend) {
+        load_stage(kbeg);
+        store_stage(0);
     }
     __syncthreads();
     int buf = 0;
     for (int kk = kbeg; kk < kend; kk += BK) {
         const bool more = kk + BK < kend;
-        if (more) {
-            ld4(a_src + kk + BK, ra);
-            ld4(b_src + kk + BK, rb);
-        }
-        TC av[2][4], bv[2][4];
+        if (more) load_stage(kk + BK);
+        // only the k sub-blocks of 16 that hold data are contracted (the
+        // last stage may be partial; k_len is a multiple of 16)
+        const int kvalid = min(BK, kend - kk);
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            const TC *pa = &As[buf][(wm * 32 + f * 16 + arow) * LS + lg * 4];
-            const TC *pb = &Bs[buf][(wn * 32 + f * 16 + lr) * LS + lg * 4];
+        for (int h = 0; h < NH; ++h) {
+            if (16 * h >= kvalid) break;
+            TC av[2][4], bv[2][4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                av[f][s] = pa[s];
-                bv[f][s] = pb[s];
+            for (int f = 0; f < 2; ++f) {
+                const TC *pa = &As[buf][(wm * 32 + f * 16 + arow) * LS + 16 * h + 4 * lg];
+                const TC *pb = &Bs[buf][(wn * 32 + f * 16 + lr) * LS + 16 * h + 4 * lg];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    av[f][s] = pa[s];
+                    bv[f][s] = pb[s];
+                }
             }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    if (blk_on[i])
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            acc[i][j] = mfma16(av[i][s], bv[j][s], acc[i][j]);
         }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = mfma16(av[i][s], bv[j][s], acc[i][j]);
-        if (more) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                As[buf ^ 1][sr * LS + sq + e] = ra[e];
-                Bs[buf ^ 1][sr * LS + sq + e] = rb[e];
-            }
-        }
+        if (more) store_stage(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
@@ -293,11 +365,11 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
                 for (int r = 0; r < 4; ++r) {
                     const int row = rb0 + r;
                     if (row < g.n) {
-                        const double s = acc[i][j][r], yy = g.y[row];
-                        const double z = -dloss_d(g.loss, s, yy);
+                        double z, lv, cv;
+                        cert_terms(g.loss, acc[i][j][r], g.y[row], z, lv, cv);
                         o[r] = z;
-                        sl += loss_d(g.loss, s, yy);
-                        sc += conj_neg_d(g.loss, z, yy);
+                        sl += lv;
+                        sc += cv;
                     } else {
                         o[r] = 0.0;
                     }
@@ -396,113 +468,337 @@ __device__ void bitonic_desc(double *key, int *idx)
 }
 
 // ---------------------------------------------------------------------------
-// Masked prox of one node (paper Sec. 4.2 "Evaluating proximal operators with
-// non-uniform node structure", eq. pgd_step_vector_form; App. B):
-//   J0 -> 0;  J1 -> u / (1 + 2 eta lambda2) clipped to [-M, M];
-//   free coordinates: keys |u| (padding -1 sorts below every free key),
-//   descending sort, then the PAVA of App. B for weights rho on the first
-//   kbar positions and 0 after: violations can only start at the kbar/kbar+1
-//   boundary, so one pooled block [a, b] grows from there while it violates
-//   its left or right neighbour; the block value is prox_{mean weight H_M} of
-//   the mean key (in rho-scaled units).  Then beta = sgn(u)(|u| - v / rho):
-//   positions before the block keep the ridge-and-clip value, block positions
-//   |u| - V / rho, positions after it exactly 0.
-// Requires the node's u in LDS (uu[j]) and its states; writes beta to LDS.
+// Per-node kernels run one 64-lane wave per node.  Lane l owns the contiguous
+// coordinates j = E l .. E l + E - 1 (E = PP / 64 with PP >= 256 a power of
+// two >= p), i.e. E / 4 whole groups of four, so a node's column is read and
+// written with 16-byte vector accesses.  Groups at or beyond ldp (the padded
+// column length, a multiple of 16) are not touched.
 // ---------------------------------------------------------------------------
-template <int PP>
-struct ProxLds {
-    double key[PP];
-    int idx[PP];
-    int rank[PP];
-    double uu[PP];
-    double bb[PP];
-};
-
-struct PavaBlock {
-    int a, b;   // pooled block [a, b] in sorted order (empty if a > b)
-    double V;   // block value (rho-scaled)
-    int top;    // positions < top (outside the block) are weighted singletons
-};
-
-template <int PP>
-__device__ void masked_prox(ProxLds<PP> &L, const int8_t *st, int p, int kbar, double eta,
-                            double lambda2, double M)
+__device__ __forceinline__ void ld4_i8(const int8_t *p, int o[4])
 {
-    const int l = threadIdx.x;
-    const double rho = 1.0 / (2.0 * eta * lambda2);
-    const double shrink = 1.0 + 2.0 * eta * lambda2;
-    int nfree = 0;
-    for (int j = l; j < PP; j += 64) {
-        const bool fr = (j < p) && st[j] == 0;
-        L.key[j] = fr ? fabs(L.uu[j]) : -1.0;
-        L.idx[j] = j;
-        nfree += fr ? 1 : 0;
-    }
-    const int pf = wave_sum_i(nfree);
-    __syncthreads();
-    bitonic_desc<PP>(L.key, L.idx);
-    for (int r = l; r < pf; r += 64) L.rank[L.idx[r]] = r;
-    __syncthreads();
+    const char4 v = *reinterpret_cast<const char4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void st4(float *p, const double v[4])
+{
+    *reinterpret_cast<float4 *>(p) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+}
+__device__ __forceinline__ void st4(double *p, const double v[4])
+{
+    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+}
 
-    // wave-uniform PAVA from the budget boundary
-    PavaBlock blk;
-    blk.a = 0; blk.b = -1; blk.V = 0.0;
-    if (kbar <= 0) {
-        blk.top = 0;
-    } else if (kbar >= pf) {
-        blk.top = pf;
-    } else {
-        blk.top = kbar;
-        const double wl = rho * L.key[kbar - 1], wr = rho * L.key[kbar];
-        if (prox_huber(wl, rho, M) < wr) {
-            int a = kbar - 1, b = kbar, cnt = 2;
-            double sw = wl + wr, sr = rho;
-            double V = prox_huber(sw / cnt, sr / cnt, M);
-            for (;;) {
-                bool moved = false;
-                if (a > 0) {
-                    const double wn = rho * L.key[a - 1];
-                    if (prox_huber(wn, rho, M) < V) {
-                        --a; ++cnt; sw += wn; sr += rho;
-                        V = prox_huber(sw / cnt, sr / cnt, M);
-                        moved = true;
-                    }
-                }
-                if (b + 1 < pf) {
-                    const double wn = rho * L.key[b + 1];
-                    if (V < wn) {
-                        ++b; ++cnt; sw += wn;
-                        V = prox_huber(sw / cnt, sr / cnt, M);
-                        moved = true;
-                    }
-                }
-                if (!moved) break;
+
+// Sum of split-K partials for a lane's chunk: acc[e] += sum_s src[s * stride + e]
+// for e < 4 * NQ.  Loads are issued in batches of SB splits before any is
+// added, so up to SB * NQ 16-byte loads per lane are in flight at once.
+template <typename T, int NQ>
+__device__ __forceinline__ void sum_splits(const T *__restrict__ src, int nsplit, int64_t stride,
+                                           int j0, int ldp, double (&acc)[4 * NQ])
+{
+    constexpr int SB = (sizeof(T) == 4) ? ((NQ >= 8) ? 4 : ((NQ >= 4) ? 8 : ((NQ >= 2) ? 16 : 32)))
+                                        : ((NQ >= 8) ? 2 : ((NQ >= 4) ? 4 : ((NQ >= 2) ? 8 : 16)));
+    for (int s0 = 0; s0 < nsplit; s0 += SB) {
+        T v[SB][4 * NQ];
+        // branch-free: out-of-range groups load the chunk's first element
+        // (always valid) and are zeroed by a select, so every load of the
+        // batch is issued before the first wait
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const bool ok = (s0 + i < nsplit) && (j0 + 4 * q < ldp);
+                ld4(src + (ok ? ((int64_t)(s0 + i) * stride + 4 * q) : (int64_t)0), &v[i][4 * q]);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[i][4 * q + e] = ok ? v[i][4 * q + e] : (T)0;
             }
-            blk.a = a; blk.b = b; blk.V = V; blk.top = a;
         }
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+#pragma unroll
+            for (int e = 0; e < 4 * NQ; ++e) acc[e] += (double)v[i][e];
     }
-    for (int j = l; j < p; j += 64) {
-        const double u = L.uu[j];
-        const double au = fabs(u), sg = (u > 0.0) ? 1.0 : ((u < 0.0) ? -1.0 : 0.0);
-        double bj;
-        const int s = st[j];
-        if (s < 0) {
-            bj = 0.0;
-        } else if (s > 0) {
-            bj = sg * fmin(au / shrink, M);
-        } else {
-            const int r = L.rank[j];
-            if (r < blk.top) bj = sg * fmin(au / shrink, M);
-            else if (r >= blk.a && r <= blk.b) bj = sg * (au - blk.V / rho);
-            else bj = 0.0;
-        }
-        L.bb[j] = bj;
-    }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// Prox + FISTA momentum for every running slot (one wave per slot).
+// Masked prox of one node (paper Sec. 4.2 "Evaluating proximal operators with
+// non-uniform node structure", eq. pgd_step_vector_form; App. B):
+//   J0 -> 0;  J1 -> u / (1 + 2 eta lambda2) clipped to [-M, M];
+//   free coordinates: keys |u| (non-free and padding -1, below every free key),
+//   descending sort, then the PAVA of App. B with weights rho on the first
+//   kbar positions and 0 after.  Violations can only start at the kbar/kbar+1
+//   boundary, so a single pooled block [a, b] forms there; positions before
+//   it keep the ridge-and-clip value, block positions get |u| - V / rho
+//   (V the block value in rho-scaled units), positions after it exactly 0.
+// The block is found in parallel.  With P the prefix sums of w = rho * key,
+// the pooled value of [a, b] is
+//   V(a, b) = prox_{c H_M}(S / cnt),  S = P[b+1] - P[a], cnt = b - a + 1,
+//                                     c = rho (kbar - a) / cnt.
+// For a fixed left end the block grows right while V(a, b) < w_{b+1}; that
+// test is monotone in b, so all (a, b) pairs are tested at once and the
+// smallest passing b, b(a), is kept per a.  The left end is the largest a
+// whose left neighbour's value prox_{rho H_M}(w_{a-1}) is not below
+// V(a, b(a)).  This is the block the one-step expansion of App. B reaches.
+// The right test is written without divisions:
+//   S <= M (cnt + wa):  V = S / (cnt + wa)      ->  S >= w (cnt + wa)
+//   otherwise:          V = (S - wa M) / cnt    ->  S - wa M >= w cnt
+// with wa = rho (kbar - a).
+// ---------------------------------------------------------------------------
+template <int PP>
+struct ProxLds {
+    double key[PP];       // free magnitudes in sorted (descending) order
+    int rank[PP];         // sorted position of each free coordinate
+    double psum[PP + 1];  // prefix sums of rho * key
+    int bmin[128];        // per left end a: smallest passing right end
+    double vblk[128];     // per left end a: block value V(a, b(a))
+};
+
+// Register bitonic sort of the wave's 64 E (key, idx) pairs; lane l holds
+// positions l E .. l E + E - 1.  Order: key descending, idx ascending on equal
+// keys (strict).  Strides below E are compare-exchanges inside a lane; larger
+// strides pair lane l with lane l ^ (stride / E) through shuffles.
+template <int PP>
+__device__ __forceinline__ void reg_bitonic_desc(double (&key)[PP / 64], int (&idx)[PP / 64])
+{
+    constexpr int E = PP / 64;
+    const int l = threadIdx.x;
+#pragma unroll
+    for (int size = 2; size <= PP; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= E) {
+                const int lm = stride / E;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const double pk = __shfl_xor(key[e], lm);
+                    const int pi = __shfl_xor(idx[e], lm);
+                    const int i = l * E + e;
+                    const bool lower = (i & stride) == 0;
+                    const bool desc = (i & size) == 0;
+                    const bool mine_first = (key[e] > pk) || (key[e] == pk && idx[e] < pi);
+                    const bool keep = (lower == desc) ? mine_first : !mine_first;
+                    if (!keep) { key[e] = pk; idx[e] = pi; }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (e & stride) continue;
+                    const int e2 = e | stride;
+                    const int i = l * E + e;
+                    const bool desc = (i & size) == 0;
+                    const bool first = (key[e] > key[e2]) || (key[e] == key[e2] && idx[e] < idx[e2]);
+                    if (desc != first) {
+                        const double tk = key[e]; key[e] = key[e2]; key[e2] = tk;
+                        const int ti = idx[e]; idx[e] = idx[e2]; idx[e2] = ti;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Descending order with index tie-break, as in the sort.
+__device__ __forceinline__ bool before(double ka, int ia, double kb, int ib)
+{
+    return (ka > kb) || (ka == kb && ia < ib);
+}
+
+// perm (nullable): the node's sorted order from its previous step (PP
+// entries, free coordinates first); when given, the new keys are gathered in
+// that order and repaired by odd-even transposition rounds, which is cheap
+// because the order of |u| changes little between steps; the full sort runs
+// only if 8 rounds leave it unsorted.  The new order is written back.
+template <int PP>
+__device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const int (&sv)[PP / 64],
+                            int p, int kbar, double eta, double lambda2, double M,
+                            double (&bet)[PP / 64], int32_t *perm, bool have_prev)
+{
+    constexpr int E = PP / 64;
+    const int l = threadIdx.x;
+    const int j0 = l * E;
+    const double rho = 1.0 / (2.0 * eta * lambda2);
+    const double shrink = 1.0 + 2.0 * eta * lambda2;
+    double key[E];
+    int idx[E];
+    int nfree = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = j0 + e;
+        const bool fr = (j < p) && sv[e] == 0;
+        key[e] = fr ? fabs(u[e]) : -1.0;
+        idx[e] = j;
+        nfree += fr ? 1 : 0;
+    }
+    const int pf = wave_sum_i(nfree);
+    bool sorted = false;
+    if (perm && have_prev) {
+        // keys by coordinate into LDS, then gathered in the previous order
+#pragma unroll
+        for (int e = 0; e < E; ++e) L.key[j0 + e] = key[e];
+        int pv[E];
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) {
+            const int4 v = *reinterpret_cast<const int4 *>(perm + j0 + 4 * q);
+            pv[4 * q] = v.x; pv[4 * q + 1] = v.y; pv[4 * q + 2] = v.z; pv[4 * q + 3] = v.w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            idx[e] = pv[e];
+            key[e] = L.key[pv[e]];
+        }
+        for (int round = 0; round < 8; ++round) {
+            int swaps = 0;
+            // even pairs (2i, 2i + 1) lie inside a lane
+#pragma unroll
+            for (int e = 0; e + 1 < E; e += 2) {
+                if (!before(key[e], idx[e], key[e + 1], idx[e + 1])) {
+                    const double tk = key[e]; key[e] = key[e + 1]; key[e + 1] = tk;
+                    const int ti = idx[e]; idx[e] = idx[e + 1]; idx[e + 1] = ti;
+                    ++swaps;
+                }
+            }
+            // odd pairs: inside a lane, plus (last of lane l, first of lane l + 1)
+#pragma unroll
+            for (int e = 1; e + 1 < E; e += 2) {
+                if (!before(key[e], idx[e], key[e + 1], idx[e + 1])) {
+                    const double tk = key[e]; key[e] = key[e + 1]; key[e + 1] = tk;
+                    const int ti = idx[e]; idx[e] = idx[e + 1]; idx[e + 1] = ti;
+                    ++swaps;
+                }
+            }
+            const double nk = __shfl_down(key[0], 1);
+            const int ni = __shfl_down(idx[0], 1);
+            const double pk = __shfl_up(key[E - 1], 1);
+            const int pi = __shfl_up(idx[E - 1], 1);
+            const bool swap_hi = (l < 63) && !before(key[E - 1], idx[E - 1], nk, ni);
+            const bool swap_lo = (l > 0) && !before(pk, pi, key[0], idx[0]);
+            if (swap_hi) { key[E - 1] = nk; idx[E - 1] = ni; ++swaps; }
+            if (swap_lo) { key[0] = pk; idx[0] = pi; ++swaps; }
+            if (__ballot(swaps != 0) == 0ull) {
+                sorted = true;
+                break;
+            }
+        }
+        __syncthreads();
+    }
+    if (sorted) {
+        // repaired in place
+    } else if constexpr (E <= 4) {
+        reg_bitonic_desc<PP>(key, idx);
+    } else {
+        // wide chunks: sort through LDS (the register network would be too
+        // large to unroll); L.psum and L.rank serve as scratch for the pairs
+        double *sk = L.psum;
+        int *si = L.rank;
+#pragma unroll
+        for (int e = 0; e < E; ++e) { sk[j0 + e] = key[e]; si[j0 + e] = idx[e]; }
+        __syncthreads();
+        bitonic_desc<PP>(sk, si);
+#pragma unroll
+        for (int e = 0; e < E; ++e) { key[e] = sk[j0 + e]; idx[e] = si[j0 + e]; }
+        __syncthreads();
+    }
+    if (perm) {
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q)
+            *reinterpret_cast<int4 *>(perm + j0 + 4 * q) =
+                make_int4(idx[4 * q], idx[4 * q + 1], idx[4 * q + 2], idx[4 * q + 3]);
+    }
+    // sorted keys, ranks and prefix sums of w = rho * key
+    double acc = 0.0, loc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int r = j0 + e;
+        L.key[r] = key[e];
+        if (r < pf) L.rank[idx[e]] = r;
+        acc += (r < pf) ? rho * key[e] : 0.0;
+        loc[e] = acc;
+    }
+    double incl = acc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double t = __shfl_up(incl, o);
+        if (l >= o) incl += t;
+    }
+    const double excl = incl - acc;
+#pragma unroll
+    for (int e = 0; e < E; ++e) L.psum[j0 + e + 1] = excl + loc[e];
+    if (l == 0) L.psum[0] = 0.0;
+    __syncthreads();
+
+    int ba = 0, bb_end = -1, top;
+    double V = 0.0;
+    if (kbar <= 0) {
+        top = 0;
+    } else if (kbar >= pf) {
+        top = pf;
+    } else {
+        top = kbar;
+        const double wl = rho * L.key[kbar - 1], wr = rho * L.key[kbar];
+        if (prox_huber(wl, rho, M) < wr) {
+            // lane a finds b(a) by binary search (the right test is monotone
+            // in b), then V(a, b(a)) and the left test; the left end is the
+            // largest a that passes
+            int found = -1;
+            for (int a0 = ((kbar - 1) / 64) * 64; a0 >= 0 && found < 0; a0 -= 64) {
+                const int a = a0 + l;
+                bool left = false;
+                if (a < kbar) {
+                    const double pa = L.psum[a];
+                    const double wa = rho * (double)(kbar - a);
+                    int lo = kbar, hi = pf - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        const double cnt = (double)(mid - a + 1);
+                        const double S = L.psum[mid + 1] - pa;
+                        const double w = rho * L.key[mid + 1];
+                        const bool pass = (S <= M * (cnt + wa)) ? (S >= w * (cnt + wa))
+                                                                : (S - wa * M >= w * cnt);
+                        if (pass) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    const double cnt = (double)(lo - a + 1);
+                    const double Va = prox_huber((L.psum[lo + 1] - pa) / cnt, wa / cnt, M);
+                    L.bmin[a] = lo;
+                    L.vblk[a] = Va;
+                    left = (a == 0) || (prox_huber(rho * L.key[a - 1], rho, M) >= Va);
+                }
+                const unsigned long long mask = __ballot(left);
+                if (mask) found = a0 + 63 - __clzll(mask);
+            }
+            __syncthreads();
+            if (found >= 0) {
+                ba = found;
+                bb_end = L.bmin[found];
+                V = L.vblk[found];
+                top = found;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = j0 + e;
+        const double au = fabs(u[e]), sg = (u[e] > 0.0) ? 1.0 : ((u[e] < 0.0) ? -1.0 : 0.0);
+        double bj = 0.0;
+        if (j < p && sv[e] >= 0) {
+            if (sv[e] > 0) {
+                bj = sg * fmin(au / shrink, M);
+            } else {
+                const int r = L.rank[j];
+                if (r < top) bj = sg * fmin(au / shrink, M);
+                else if (r >= ba && r <= bb_end) bj = sg * (au - V / rho);
+            }
+        }
+        bet[e] = bj;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Prox + FISTA momentum for every running slot (one wave per slot).  The
+// gradient is the sum of the split-K partials of X^T R, read here directly:
+// all loads of a lane's chunk are independent, so they are in flight together.
 // ---------------------------------------------------------------------------
 template <typename Ti, int PP>
 __global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int gsplit,
@@ -510,32 +806,47 @@ __global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int
                                                    Ti *__restrict__ Yi, const int8_t *__restrict__ stg,
                                                    SlotState ss, Consts c)
 {
+    constexpr int E = PP / 64, NQ = E / 4;
     __shared__ ProxLds<PP> L;
     const int b = blockIdx.x;
     const int l = threadIdx.x;
     if (ss.status[b] != SLOT_RUNNING) return;
-    const int p = c.p;
     const int64_t off = (int64_t)b * c.ldp;
-    const int64_t sstride = (int64_t)c.mpad * c.ldp;
+    const int64_t gstride = (int64_t)c.mpad * c.ldp;
+    const int j0 = l * E;
     const double th = ss.theta[b];
-    const int8_t *st = stg + off;
-    for (int j = l; j < p; j += 64) {
-        double gj = 0.0;
-        for (int s = 0; s < gsplit; ++s) gj += (double)Gp[s * sstride + off + j];
-        const double bj = B[off + j], bp = Bprev[off + j];
-        const double yj = bj + th * (bj - bp);
-        L.uu[j] = yj - c.eta * gj;
+
+    double g[E], bo[E], bp[E], u[E], y[E], bet[E];
+    int sv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) { g[e] = 0.0; bo[e] = 0.0; bp[e] = 0.0; sv[e] = -1; }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = j0 + 4 * q;
+        const bool ok = j < c.ldp;
+        const int jj = ok ? j : 0;
+        ld4(B + off + jj, &bo[4 * q]);
+        ld4(Bprev + off + jj, &bp[4 * q]);
+        ld4_i8(stg + off + jj, &sv[4 * q]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            bo[4 * q + e] = ok ? bo[4 * q + e] : 0.0;
+            bp[4 * q + e] = ok ? bp[4 * q + e] : 0.0;
+            sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
+        }
     }
-    __syncthreads();
-    masked_prox<PP>(L, st, p, ss.kbar[b], c.eta, c.lambda2, c.M);
+    sum_splits<Ti, NQ>(Gp + off + (j0 < c.ldp ? j0 : 0), gsplit, gstride, j0, c.ldp, g);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        y[e] = bo[e] + th * (bo[e] - bp[e]);
+        u[e] = y[e] - c.eta * g[e];
+    }
+    masked_prox<PP>(L, u, sv, c.p, ss.kbar[b], c.eta, c.lambda2, c.M, bet,
+                    ss.perm + (int64_t)b * c.pp, ss.iter[b] > 0);
     // restart test (y - beta+)^T (beta+ - beta) > 0, then momentum
     double dot = 0.0;
-    for (int j = l; j < p; j += 64) {
-        const double bj = B[off + j], bp = Bprev[off + j];
-        const double yj = bj + th * (bj - bp);
-        const double bn = L.bb[j];
-        dot += (yj - bn) * (bn - bj);
-    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) dot += (y[e] - bet[e]) * (bet[e] - bo[e]);
     dot = wave_sum(dot);
     const double t = ss.tmom[b];
     double tn, thn;
@@ -546,12 +857,17 @@ __global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int
         tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
         thn = (t - 1.0) / tn;
     }
-    for (int j = l; j < p; j += 64) {
-        const double bj = B[off + j];
-        const double bn = L.bb[j];
-        Bprev[off + j] = bj;
-        B[off + j] = bn;
-        Yi[off + j] = (Ti)(bn + thn * (bn - bj));
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = j0 + 4 * q;
+        if (j < c.ldp) {
+            double yn[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) yn[e] = bet[4 * q + e] + thn * (bet[4 * q + e] - bo[4 * q + e]);
+            st4(Bprev + off + j, &bo[4 * q]);
+            st4(B + off + j, &bet[4 * q]);
+            st4(Yi + off + j, yn);
+        }
     }
     if (l == 0) {
         ss.tmom[b] = tn;
@@ -566,19 +882,40 @@ __global__ __launch_bounds__(64) void k_prox_batch(const double *__restrict__ U,
                                                     const int32_t *__restrict__ kbar, double *__restrict__ Bout,
                                                     double eta, Consts c)
 {
+    constexpr int E = PP / 64, NQ = E / 4;
     __shared__ ProxLds<PP> L;
     const int b = blockIdx.x, l = threadIdx.x;
     const int64_t off = (int64_t)b * c.ldp;
-    for (int j = l; j < c.p; j += 64) L.uu[j] = U[off + j];
-    __syncthreads();
-    masked_prox<PP>(L, stg + off, c.p, kbar[b], eta, c.lambda2, c.M);
-    for (int j = l; j < c.p; j += 64) Bout[off + j] = L.bb[j];
+    const int j0 = l * E;
+    double u[E], bet[E];
+    int sv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) { u[e] = 0.0; sv[e] = -1; }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = j0 + 4 * q;
+        const bool ok = j < c.ldp;
+        const int jj = ok ? j : 0;
+        ld4(U + off + jj, &u[4 * q]);
+        ld4_i8(stg + off + jj, &sv[4 * q]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            u[4 * q + e] = ok ? u[4 * q + e] : 0.0;
+            sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
+        }
+    }
+    masked_prox<PP>(L, u, sv, c.p, kbar[b], eta, c.lambda2, c.M, bet, nullptr, false);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = j0 + 4 * q;
+        if (j < c.ldp) st4(Bout + off + j, &bet[4 * q]);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Certificate finish (one wave per slot): paper Sec. 4.4,
 // eqs. batched_primal_value_component / batched_dual_value_component.
-//   q = (sum of Q partials) / (2 lambda2)
+//   q = (sum of the split-K partials of X^T zeta) / (2 lambda2)
 //   g*(q) = sum_{J1} H_M(q_j) + TopSum_kbar{H_M(q_j)}_{free}  (kbar rounds of
 //           wave argmax; fewer free entries than kbar sums them all)
 //   g(beta) by Thm. 4.1: J1 contributes beta^2/2; on the free set with
@@ -611,17 +948,36 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
                                                      const int8_t *__restrict__ stg, SlotState ss,
                                                      Consts c, int update_state)
 {
+    constexpr int E = PP / 64, NQ = E / 4;
     __shared__ CertLds<PP> L;
     const int b = blockIdx.x, l = threadIdx.x;
     if (update_state && ss.status[b] != SLOT_RUNNING) return;
     const int p = c.p;
     const int64_t off = (int64_t)b * c.ldp;
     const int64_t qstride = (int64_t)c.mpad * c.ldp;
-    const int8_t *st = stg + off;
+    const int j0 = l * E;
     const int kbar = ss.kbar[b];
     const double inv2l = 1.0 / (2.0 * c.lambda2);
     const double slack = 1.0 + 1e-9;
 
+    double qv[E], bv[E];
+    int sv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) { qv[e] = 0.0; bv[e] = 0.0; sv[e] = -1; }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = j0 + 4 * q;
+        const bool ok = j < c.ldp;
+        const int jj = ok ? j : 0;
+        ld4(B + off + jj, &bv[4 * q]);
+        ld4_i8(stg + off + jj, &sv[4 * q]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            bv[4 * q + e] = ok ? bv[4 * q + e] : 0.0;
+            sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
+        }
+    }
+    sum_splits<double, NQ>(Qp + off + (j0 < c.ldp ? j0 : 0), qsplit, qstride, j0, c.ldp, qv);
     // smooth parts
     double fl = 0.0, fc = 0.0;
     for (int t = l; t < tiles_n; t += 64) {
@@ -631,23 +987,23 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
     fl = wave_sum(fl);
     fc = wave_sum(fc);
 
-    // per-coordinate pass
     double gin = 0.0, g1 = 0.0, sum_a = 0.0, sum_a2 = 0.0;
-    int nnz = 0, bad = 0;
-    for (int j = l; j < PP; j += 64) {
+    int nnz = 0, bad = 0, cin = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = j0 + e;
         double hj = -1.0, aj = -1.0;
         if (j < p) {
-            double q = 0.0;
-            for (int s = 0; s < qsplit; ++s) q += Qp[s * qstride + off + j];
-            q *= inv2l;
-            const double bj = B[off + j];
+            const double q = qv[e] * inv2l;
+            const double bj = bv[e];
             const double ab = fabs(bj);
-            const int s = st[j];
+            const int s = sv[e];
             if (s < 0) {
                 if (bj != 0.0) bad = 1;
             } else {
                 if (ab > c.M * slack) bad = 1;
                 if (s > 0) {
+                    ++cin;
                     gin += huber(q, c.M);
                     g1 += 0.5 * bj * bj;
                 } else {
@@ -662,6 +1018,20 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
         L.h[j] = hj;
         L.a[j] = aj;
     }
+    // J1 indices in ascending order: exclusive scan of the per-lane counts
+    {
+        int incl = cin;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (l >= o) incl += t;
+        }
+        int pos = incl - cin;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (j0 + e < p && sv[e] > 0 && pos < 256) L.sup[pos++] = j0 + e;
+    }
+    const int nin = min(256, __shfl(wave_sum_i(cin), 0));
     gin = wave_sum(gin);
     g1 = wave_sum(g1);
     sum_a = wave_sum(sum_a);
@@ -706,7 +1076,7 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
         __syncthreads();
     }
     __syncthreads();
-    // branching index: the largest free |beta| (needs at least one free entry)
+    // branching index: the largest free |beta|
     int jstar = -1;
     if (kbar > 0) {
         jstar = (ntop > 0) ? L.topi[0] : -1;
@@ -753,17 +1123,16 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
     const double phi = fl + 2.0 * c.lambda2 * (g1 + gfree);
     const double psi = -fc - 2.0 * c.lambda2 * (gin + topsum);
 
-    // rounding support: J1 plus the selected free indices, ascending
+    // rounding support: J1 (already ascending in L.sup) plus the selected free
+    // indices, merged into ascending order
     if (l == 0) {
-        int len = 0;
-        for (int j = 0; j < p && len < 256; ++j)
-            if (st[j] > 0) L.sup[len++] = j;
-        for (int r = 0; r < ntop && len < 256; ++r) L.sup[len++] = L.topi[r];
-        for (int x = 1; x < len; ++x) {
-            const int v = L.sup[x];
-            int y = x - 1;
+        int len = nin;
+        for (int r = 0; r < ntop && len < 256; ++r) {
+            const int v = L.topi[r];
+            int y = len - 1;
             while (y >= 0 && L.sup[y] > v) { L.sup[y + 1] = L.sup[y]; --y; }
             L.sup[y + 1] = v;
+            ++len;
         }
         int32_t *so = ss.sup + (int64_t)b * c.k;
         for (int r = 0; r < c.k; ++r) so[r] = (r < len) ? L.sup[r] : -1;
@@ -878,6 +1247,29 @@ __global__ __launch_bounds__(256) void k_transpose(const TA *__restrict__ X, TA 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split-K reduction: out[i] = sum_s parts[s * stride + i], in split order
+// (deterministic), four elements per thread.  Columns (nodes) that are not
+// running are skipped.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce_splits(const T *__restrict__ parts, int nsplit,
+                                                        int64_t stride, T *__restrict__ out,
+                                                        int64_t count, int ld,
+                                                        const int32_t *__restrict__ status)
+{
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i >= count) return;
+    if (status && status[i / ld] != SLOT_RUNNING) return;
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int s = 0; s < nsplit; ++s) {
+        T v[4];
+        ld4(parts + s * stride + i, v);
+        a0 += v[0]; a1 += v[1]; a2 += v[2]; a3 += v[3];
+    }
+    out[i] = a0; out[i + 1] = a1; out[i + 2] = a2; out[i + 3] = a3;
+}
+
 // ===========================================================================
 // Launchers
 // ===========================================================================
@@ -889,9 +1281,10 @@ static void gemm(hipStream_t s, const GemmArgs &g, int tiles_n, int splits)
 }
 
 void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
-                      void *R, const double *y, const Consts &c)
+                      void *R, const double *y, const Consts &c, const int32_t *status)
 {
     GemmArgs g{};
+    g.col_status = status;
     g.A = X; g.lda = c.ldp; g.B = Yi; g.ldb = c.ldp; g.C = R; g.ldc = c.npad;
     g.k_len = c.ldp; g.k_chunk = c.ldp; g.tiles_m = c.npad / GEMM_BM;
     g.n = c.n; g.loss = c.loss; g.y = y;
@@ -902,9 +1295,10 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
 }
 
 void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
-                void *Gp, int gsplit, int gchunk, const Consts &c)
+                void *Gp, int gsplit, int gchunk, const Consts &c, const int32_t *status)
 {
     GemmArgs g{};
+    g.col_status = status;
     g.A = XT; g.lda = c.npad; g.B = R; g.ldb = c.npad; g.C = Gp; g.ldc = c.ldp;
     g.split_stride = (int64_t)c.mpad * c.ldp;
     g.k_len = c.npad; g.k_chunk = gchunk; g.tiles_m = c.pm / GEMM_BM; g.rows_valid = c.ldp;
@@ -915,9 +1309,11 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
 }
 
 void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,
-                     const double *y, double *lsum, double *csum, const Consts &c)
+                     const double *y, double *lsum, double *csum, const Consts &c,
+                     const int32_t *status)
 {
     GemmArgs g{};
+    g.col_status = status;
     g.A = X; g.lda = c.ldp; g.B = B; g.ldb = c.ldp; g.C = Z; g.ldc = c.npad;
     g.k_len = c.ldp; g.k_chunk = c.ldp; g.tiles_m = c.npad / GEMM_BM;
     g.n = c.n; g.loss = c.loss; g.y = y; g.lsum = lsum; g.csum = csum; g.ldsum = c.mpad;
@@ -928,9 +1324,10 @@ void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, d
 }
 
 void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, double *Qp,
-                     int qsplit, int qchunk, const Consts &c)
+                     int qsplit, int qchunk, const Consts &c, const int32_t *status)
 {
     GemmArgs g{};
+    g.col_status = status;
     g.A = XT; g.lda = c.npad; g.B = Z; g.ldb = c.npad; g.C = Qp; g.ldc = c.ldp;
     g.split_stride = (int64_t)c.mpad * c.ldp;
     g.k_len = c.npad; g.k_chunk = qchunk; g.tiles_m = c.pm / GEMM_BM; g.rows_valid = c.ldp;
@@ -942,13 +1339,25 @@ void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, 
 
 #define KBNB_PP_DISPATCH(P, CALL)                     \
     do {                                              \
-        if ((P) <= 64) { constexpr int PP = 64; CALL; } \
-        else if ((P) <= 128) { constexpr int PP = 128; CALL; } \
-        else if ((P) <= 256) { constexpr int PP = 256; CALL; } \
+        if ((P) <= 256) { constexpr int PP = 256; CALL; } \
         else if ((P) <= 512) { constexpr int PP = 512; CALL; } \
         else if ((P) <= 1024) { constexpr int PP = 1024; CALL; } \
         else { constexpr int PP = 2048; CALL; } \
     } while (0)
+
+void launch_reduce(hipStream_t s, bool f64, const void *parts, int nsplit, void *out,
+                   const Consts &c, const int32_t *status)
+{
+    const int64_t count = (int64_t)c.mpad * c.ldp;
+    const int64_t stride = count;
+    dim3 grid((unsigned)((count / 4 + 255) / 256));
+    if (f64)
+        hipLaunchKernelGGL((k_reduce_splits<double>), grid, dim3(256), 0, s, (const double *)parts, nsplit,
+                           stride, (double *)out, count, c.ldp, status);
+    else
+        hipLaunchKernelGGL((k_reduce_splits<float>), grid, dim3(256), 0, s, (const float *)parts, nsplit,
+                           stride, (float *)out, count, c.ldp, status);
+}
 
 void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, double *B,
                       double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c)
