@@ -90,6 +90,7 @@ struct kbnb_problem {
     // sizes
     int ldp = 0, npad = 0, pm = 0, m = 0, mpad = 0, pp = 256;
     int gsplit = 1, gchunk = 0, qsplit = 1, qchunk = 0, tiles_n = 0;
+    int gsplit_pad = 1, qsplit_pad = 1;  // split buffers allocated (multiple of the load batch)
     int cert_period = 8;
     uint64_t budget = 0, bytes = 0;
     // device memory
@@ -164,8 +165,8 @@ static size_t per_slot_bytes(const kbnb_problem *P)
     size_t b = 0;
     b += (size_t)P->ldp * (ti + 8 + 8 + 1);            // Yi, B, Bprev, st
     b += (size_t)P->npad * (ti + 8);                   // R, Z
-    b += (size_t)P->gsplit * P->ldp * ti;              // Gp
-    b += (size_t)P->qsplit * P->ldp * 8;               // Qp
+    b += (size_t)P->gsplit_pad * P->ldp * ti;          // Gp
+    b += (size_t)P->qsplit_pad * P->ldp * 8;           // Qp
     b += (size_t)P->tiles_n * 16;                      // lsum, csum
     b += (size_t)P->ldp * 8 + 128 + P->k * 4;          // gather buffer, scalars, support
     b += (size_t)P->ldp * (ti + 8);                    // reduced G and Q
@@ -185,6 +186,8 @@ static void choose_splits(kbnb_problem *P)
     P->gsplit = (P->npad + chunk - 1) / chunk;
     P->qchunk = chunk;
     P->qsplit = P->gsplit;
+    P->gsplit_pad = (int)round_up(P->gsplit, split_batch(P->pp, P->ti_bytes));
+    P->qsplit_pad = (int)round_up(P->qsplit, split_batch(P->pp, 8));
 }
 
 static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
@@ -198,11 +201,11 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         (size_t)P->npad * 8,                     // y
         mp * P->ldp * ti,                        // Yi
         mp * P->npad * ti,                       // R
-        (size_t)P->gsplit * mp * P->ldp * ti,    // Gp
+        (size_t)P->gsplit_pad * mp * P->ldp * ti, // Gp
         mp * P->ldp * 8,                         // B
         mp * P->ldp * 8,                         // Bprev
         mp * P->npad * 8,                        // Z
-        (size_t)P->qsplit * mp * P->ldp * 8,     // Qp
+        (size_t)P->qsplit_pad * mp * P->ldp * 8, // Qp
         (size_t)P->tiles_n * mp * 8,             // lsum
         (size_t)P->tiles_n * mp * 8,             // csum
         mp * P->ldp,                             // st
@@ -287,11 +290,11 @@ static void enqueue_round(kbnb_problem *P)
     for (int it = 0; it < P->cert_period; ++it) {
         launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, P->c, P->ss.status);
         launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c, P->ss.status);
-        launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
+        launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit_pad, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
     }
     launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c, P->ss.status);
     launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
-    launch_cert_finish(s, P->Qp, P->qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
+    launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
 }
 
 // Kernel types for the timing instrumentation.
@@ -319,7 +322,7 @@ static int enqueue_round_timed(kbnb_problem *P, std::vector<int> &kinds)
         launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c, P->ss.status);
         HIP_TRY(hipEventRecord(P->ev[q++], s));
         HIP_TRY(hipEventRecord(mark(KT_PROX), s));
-        launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
+        launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit_pad, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
         HIP_TRY(hipEventRecord(P->ev[q++], s));
     }
     HIP_TRY(hipEventRecord(mark(KT_CFWD), s));
@@ -329,7 +332,7 @@ static int enqueue_round_timed(kbnb_problem *P, std::vector<int> &kinds)
     launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
     HIP_TRY(hipEventRecord(P->ev[q++], s));
     HIP_TRY(hipEventRecord(mark(KT_CFIN), s));
-    launch_cert_finish(s, P->Qp, P->qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
+    launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
     HIP_TRY(hipEventRecord(P->ev[q++], s));
     return 0;
 }
@@ -953,8 +956,9 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     int8_t *dst;
     int32_t *dk, *dsup, *djs, *dslen;
     const int qsplit = P->qsplit;
+    const int qsplit_pad = P->qsplit_pad;
     if ((rc = T.alloc(&dB, bh.size())) || (rc = T.alloc(&dZ, (size_t)mpad * P->npad)) ||
-        (rc = T.alloc(&dQ, (size_t)qsplit * mpad * P->ldp)) || (rc = T.alloc(&dQs, (size_t)mpad * P->ldp)) ||
+        (rc = T.alloc(&dQ, (size_t)qsplit_pad * mpad * P->ldp)) || (rc = T.alloc(&dQs, (size_t)mpad * P->ldp)) ||
         (rc = T.alloc(&dl, (size_t)P->tiles_n * mpad)) ||
         (rc = T.alloc(&dc, (size_t)P->tiles_n * mpad)) || (rc = T.alloc(&dlb, (size_t)mpad)) ||
         (rc = T.alloc(&dphi, (size_t)mpad)) || (rc = T.alloc(&dst, st.size())) || (rc = T.alloc(&dk, (size_t)mpad)) ||
@@ -964,11 +968,12 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     HIP_TRY(hipMemcpyAsync(dB, bh.data(), bh.size() * 8, hipMemcpyHostToDevice, T.s));
     HIP_TRY(hipMemcpyAsync(dst, st.data(), st.size(), hipMemcpyHostToDevice, T.s));
     HIP_TRY(hipMemcpyAsync(dk, kbar.data(), (size_t)mpad * 4, hipMemcpyHostToDevice, T.s));
+    HIP_TRY(hipMemsetAsync(dQ, 0, (size_t)qsplit_pad * mpad * P->ldp * 8, T.s));
     SlotState ss{};
     ss.lb = dlb; ss.phi = dphi; ss.kbar = dk; ss.sup = dsup; ss.jstar = djs; ss.slen = dslen;
     launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c, nullptr);
     launch_cert_bwd(T.s, P->xtype, P->XT, dZ, dQ, qsplit, P->qchunk, c, nullptr);
-    launch_cert_finish(T.s, dQ, qsplit, dl, dc, P->tiles_n, dB, dst, ss, c, 0);
+    launch_cert_finish(T.s, dQ, qsplit_pad, dl, dc, P->tiles_n, dB, dst, ss, c, 0);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(psi, dlb, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));
     HIP_TRY(hipMemcpyAsync(phi, dphi, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));

@@ -29,6 +29,15 @@ constexpr int GEMM_BK = 16;
 
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// Splits summed per load batch by the per-node kernels (sort width pp,
+// element size in bytes): the split-K partial buffers are allocated in a
+// multiple of this count, the extra ones staying zero.
+__host__ __device__ constexpr int split_batch(int pp, int elem_bytes)
+{
+    return (elem_bytes == 4) ? ((pp >= 2048) ? 4 : ((pp >= 1024) ? 8 : ((pp >= 512) ? 16 : 32)))
+                             : ((pp >= 2048) ? 2 : ((pp >= 1024) ? 4 : ((pp >= 512) ? 8 : 16)));
+}
+
 // Per-slot scalar state (struct of arrays, device memory).
 struct SlotState {
     double *theta;    // extrapolation weight for the next step

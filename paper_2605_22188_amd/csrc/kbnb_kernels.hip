@@ -221,12 +221,6 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
         const int run = (tid < BN) ? (g.col_status[col0 + tid] == SLOT_RUNNING) : 0;
         if (!__syncthreads_or(run)) return;
     }
-    // 16-row MFMA blocks wholly at or beyond row_limit hold only padding
-    const int row_limit = (MODE == EPI_STORE) ? g.rows_valid : (g.tiles_m * BM);
-    bool blk_on[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) blk_on[i] = row0 + wm * 32 + i * 16 < row_limit;
-
     const TA *A = reinterpret_cast<const TA *>(g.A);
     const TB *Bg = reinterpret_cast<const TB *>(g.B);
 
@@ -240,22 +234,19 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     // staging: thread t loads groups t, t + 256, ... of each operand tile;
     // group x covers row x / GPR, k = 4 (x % GPR) .. + 3 of the stage
     TC ra[LPT][4], rb[LPT][4];
+    bool rok[LPT];
+    // loads only: a group past kend re-reads k = kbeg (always valid); its
+    // zeroing happens at the LDS store, so no instruction consumes the loaded
+    // registers before the stage's MFMA work has been issued
     auto load_stage = [&](int k0) {
 #pragma unroll
         for (int v = 0; v < LPT; ++v) {
             const int x = tid + 256 * v;
             const int r = x / GPR, kq = 4 * (x % GPR);
-            // branch-free: a group past kend re-reads k = kbeg (always valid)
-            // and is zeroed, so all loads of the stage are in flight together
-            const bool ok = k0 + kq < kend;
-            const int kk = ok ? k0 + kq : kbeg;
+            rok[v] = k0 + kq < kend;
+            const int kk = rok[v] ? k0 + kq : kbeg;
             ld4(A + (int64_t)(row0 + r) * g.lda + kk, ra[v]);
             ld4(Bg + (int64_t)(col0 + r) * g.ldb + kk, rb[v]);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                ra[v][e] = ok ? ra[v][e] : (TC)0;
-                rb[v][e] = ok ? rb[v][e] : (TC)0;
-            }
         }
     };
     auto store_stage = [&](int bufi) {
@@ -265,46 +256,53 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
             const int r = x / GPR, kq = 4 * (x % GPR);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                As[bufi][r * LS + kq + e] = ra[v][e];
-                Bs[bufi][r * LS + kq + e] = rb[v][e];
+                As[bufi][r * LS + kq + e] = rok[v] ? ra[v][e] : (TC)0;
+                Bs[bufi][r * LS + kq + e] = rok[v] ? rb[v][e] : (TC)0;
             }
         }
     };
 
-    if (kbeg < kend) {
+    // contract sub-blocks [0, nh) of the LDS stage in buffer bi
+    auto compute = [&](int bi, int h) {
+        TC av[2][4], bv[2][4];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const TC *pa = &As[bi][(wm * 32 + f * 16 + arow) * LS + 16 * h + 4 * lg];
+            const TC *pb = &Bs[bi][(wn * 32 + f * 16 + lr) * LS + 16 * h + 4 * lg];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                av[f][s] = pa[s];
+                bv[f][s] = pb[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = mfma16(av[i][s], bv[j][s], acc[i][j]);
+    };
+
+    // full stages (no conditions inside), then a partial last stage whose
+    // depth is a multiple of 16
+    const int nfull = (kend - kbeg) / BK;
+    const int ntail = ((kend - kbeg) % BK) / 16;
+    const int nstage = nfull + (ntail > 0 ? 1 : 0);
+    if (nstage > 0) {
         load_stage(kbeg);
         store_stage(0);
     }
     __syncthreads();
     int buf = 0;
-    for (int kk = kbeg; kk < kend; kk += BK) {
-        const bool more = kk + BK < kend;
-        if (more) load_stage(kk + BK);
-        // only the k sub-blocks of 16 that hold data are contracted (the
-        // last stage may be partial; k_len is a multiple of 16)
-        const int kvalid = min(BK, kend - kk);
+    for (int st = 0; st < nstage; ++st) {
+        const bool more = st + 1 < nstage;
+        if (more) load_stage(kbeg + (st + 1) * BK);
+        if (st < nfull) {
 #pragma unroll
-        for (int h = 0; h < NH; ++h) {
-            if (16 * h >= kvalid) break;
-            TC av[2][4], bv[2][4];
-#pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                const TC *pa = &As[buf][(wm * 32 + f * 16 + arow) * LS + 16 * h + 4 * lg];
-                const TC *pb = &Bs[buf][(wn * 32 + f * 16 + lr) * LS + 16 * h + 4 * lg];
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    av[f][s] = pa[s];
-                    bv[f][s] = pb[s];
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    if (blk_on[i])
-#pragma unroll
-                        for (int j = 0; j < 2; ++j)
-                            acc[i][j] = mfma16(av[i][s], bv[j][s], acc[i][j]);
+            for (int h = 0; h < NH; ++h) compute(buf, h);
+        } else {
+            for (int h = 0; h < ntail; ++h) compute(buf, h);
         }
         if (more) store_stage(buf ^ 1);
         __syncthreads();
@@ -493,27 +491,26 @@ __device__ __forceinline__ void st4(double *p, const double v[4])
 // Sum of split-K partials for a lane's chunk: acc[e] += sum_s src[s * stride + e]
 // for e < 4 * NQ.  Loads are issued in batches of SB splits before any is
 // added, so up to SB * NQ 16-byte loads per lane are in flight at once.
+// Sum of split-K partials for a lane's chunk: acc[e] += sum_s col[s * stride + j0 + e].
+// nsplit is padded to a multiple of the batch (the padding partial buffers are
+// zero), so the batch loop has no conditions and all SB * NQ 16-byte loads of
+// a batch are in flight together.  Group addresses are clamped into the
+// column with min(): a group past ldp reads valid memory and its (unused)
+// value belongs to a padding coordinate.
 template <typename T, int NQ>
-__device__ __forceinline__ void sum_splits(const T *__restrict__ src, int nsplit, int64_t stride,
+__device__ __forceinline__ void sum_splits(const T *__restrict__ col, int nsplit, int64_t stride,
                                            int j0, int ldp, double (&acc)[4 * NQ])
 {
-    constexpr int SB = (sizeof(T) == 4) ? ((NQ >= 8) ? 4 : ((NQ >= 4) ? 8 : ((NQ >= 2) ? 16 : 32)))
-                                        : ((NQ >= 8) ? 2 : ((NQ >= 4) ? 4 : ((NQ >= 2) ? 8 : 16)));
+    constexpr int SB = split_batch(4 * NQ * 64, (int)sizeof(T));
+    int go[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) go[q] = min(j0 + 4 * q, ldp - 4);
     for (int s0 = 0; s0 < nsplit; s0 += SB) {
         T v[SB][4 * NQ];
-        // branch-free: out-of-range groups load the chunk's first element
-        // (always valid) and are zeroed by a select, so every load of the
-        // batch is issued before the first wait
 #pragma unroll
-        for (int i = 0; i < SB; ++i) {
+        for (int i = 0; i < SB; ++i)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const bool ok = (s0 + i < nsplit) && (j0 + 4 * q < ldp);
-                ld4(src + (ok ? ((int64_t)(s0 + i) * stride + 4 * q) : (int64_t)0), &v[i][4 * q]);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[i][4 * q + e] = ok ? v[i][4 * q + e] : (T)0;
-            }
-        }
+            for (int q = 0; q < NQ; ++q) ld4(col + (int64_t)(s0 + i) * stride + go[q], &v[i][4 * q]);
 #pragma unroll
         for (int i = 0; i < SB; ++i)
 #pragma unroll
@@ -835,7 +832,7 @@ __global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int
             sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
         }
     }
-    sum_splits<Ti, NQ>(Gp + off + (j0 < c.ldp ? j0 : 0), gsplit, gstride, j0, c.ldp, g);
+    sum_splits<Ti, NQ>(Gp + off, gsplit, gstride, j0, c.ldp, g);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         y[e] = bo[e] + th * (bo[e] - bp[e]);
@@ -977,7 +974,7 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
             sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
         }
     }
-    sum_splits<double, NQ>(Qp + off + (j0 < c.ldp ? j0 : 0), qsplit, qstride, j0, c.ldp, qv);
+    sum_splits<double, NQ>(Qp + off, qsplit, qstride, j0, c.ldp, qv);
     // smooth parts
     double fl = 0.0, fc = 0.0;
     for (int t = l; t < tiles_n; t += 64) {
