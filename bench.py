@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--comparator-nodes", type=int, default=32,
                     help="nodes bounded one at a time at batch width 1 (0 = skip)")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -83,6 +85,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_bytes > 0:
+        # a plain copy kernel of known size: reads and writes copy_bytes each,
+        # used to scale the FETCH_SIZE / WRITE_SIZE counters
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes}))
+        return
     import paper_2605_22188_amd as K
     import workloads as W
 

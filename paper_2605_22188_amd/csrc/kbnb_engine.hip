@@ -633,7 +633,9 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     while (P->pp < P->p) P->pp *= 2;
     P->npad = (int)round_up(P->n, 64);
     P->pm = (int)round_up(P->ldp, 64);
-    P->tiles_n = P->npad / GEMM_BM;
+    // per-row-tile loss sums of the certificate: sized for 32-row tiles (the
+    // arena is zeroed, so rows a 64-row launch does not write stay zero)
+    P->tiles_n = P->npad / 32;
     P->cert_period = d->cert_period ? d->cert_period : 8;
     P->budget = d->hbm_budget_bytes ? d->hbm_budget_bytes : (8ull << 30);
     P->own_x = (d->mem_flags != KBNB_MEM_DEVICE_BORROW);
@@ -969,6 +971,8 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     HIP_TRY(hipMemcpyAsync(dst, st.data(), st.size(), hipMemcpyHostToDevice, T.s));
     HIP_TRY(hipMemcpyAsync(dk, kbar.data(), (size_t)mpad * 4, hipMemcpyHostToDevice, T.s));
     HIP_TRY(hipMemsetAsync(dQ, 0, (size_t)qsplit_pad * mpad * P->ldp * 8, T.s));
+    HIP_TRY(hipMemsetAsync(dl, 0, (size_t)P->tiles_n * mpad * 8, T.s));
+    HIP_TRY(hipMemsetAsync(dc, 0, (size_t)P->tiles_n * mpad * 8, T.s));
     SlotState ss{};
     ss.lb = dlb; ss.phi = dphi; ss.kbar = dk; ss.sup = dsup; ss.jstar = djs; ss.slen = dslen;
     launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c, nullptr);

@@ -172,6 +172,7 @@ struct GemmArgs {
     int k_len;             // total k extent (multiple of 16)
     int k_chunk;           // k per split (multiple of 16)
     int tiles_m;
+    int tiles_n;
     const int32_t *col_status;  // nullable: skip tiles with no running column
     int rows_valid;        // store rows < rows_valid (EPI_STORE)
     int n;                 // rows with data (EPI_DLOSS / EPI_CERT)
@@ -182,10 +183,13 @@ struct GemmArgs {
     int64_t ldsum;
 };
 
-template <typename TA, typename TB, typename TC, int MODE>
+template <typename TA, typename TB, typename TC, int MODE, int BM>
 __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
 {
-    constexpr int BM = GEMM_BM, BN = GEMM_BN;
+    // tile BM x 64 (BM = 32 or 64); the 4 waves form a 2 x 2 grid of
+    // (BM / 2) x 32 wave tiles, i.e. FI x 2 MFMA blocks of 16 x 16
+    constexpr int BN = GEMM_BN;
+    constexpr int FI = BM / 32;
     // k depth of one LDS stage: 64 (float) or 32 (double) so that a stage's
     // MFMA work (64 or 32 instructions per wave) covers the next stage's
     // global-load latency.  A stage is NH sub-blocks of 16; in sub-block h
@@ -196,7 +200,8 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     constexpr int PAD = (sizeof(TC) == 8) ? 2 : 4;
     constexpr int LS = BK + PAD;                      // LDS row stride (elements)
     constexpr int GPR = BK / 4;                       // 4-element groups per row
-    constexpr int LPT = (BM * GPR) / 256;             // groups per thread per operand
+    constexpr int LPA = (BM * GPR) / 256;             // A groups per thread per stage
+    constexpr int LPB = (BN * GPR) / 256;             // B groups per thread per stage
     typedef typename V4<TC>::t acc_t;
     __shared__ TC As[2][BM * LS];
     __shared__ TC Bs[2][BN * LS];
@@ -210,7 +215,20 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     // 4 (i % 4) + i / 4 into row slot i makes both layouts "lane group g,
     // register r holds row 4g + r", so one epilogue serves both.
     const int arow = (sizeof(TC) == 8) ? ((lr & 3) * 4 + (lr >> 2)) : lr;
-    const int tm = blockIdx.x % g.tiles_m, tn = blockIdx.x / g.tiles_m;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs
+    // (blockIdx % 8), each with its own L2.  The tiles that share an A row
+    // tile (all column tiles of one row tile) go to the same XCD and are
+    // dispatched back to back, so A is fetched into one L2 and reused there.
+    int tm, tn;
+    if (g.tiles_m >= 8) {
+        const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+        tn = q % g.tiles_n;
+        tm = (q / g.tiles_n) * 8 + xcd;
+        if (tm >= g.tiles_m) return;
+    } else {
+        tm = blockIdx.x % g.tiles_m;
+        tn = blockIdx.x / g.tiles_m;
+    }
     const int split = blockIdx.y;
     const int row0 = tm * BM, col0 = tn * BN;
     const int kbeg = split * g.k_chunk;
@@ -224,61 +242,79 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     const TA *A = reinterpret_cast<const TA *>(g.A);
     const TB *Bg = reinterpret_cast<const TB *>(g.B);
 
-    acc_t acc[2][2];
+    acc_t acc[FI][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
             acc[i][j] = acc_t{0, 0, 0, 0};
+    // the epilogue's y values (rows row0 + wm*BM/2 + i*16 + lg*4 + r), loaded
+    // now so their latency is hidden behind the contraction (y has npad rows)
+    double yv[FI][4];
+    if constexpr (MODE != EPI_STORE) {
+#pragma unroll
+        for (int i = 0; i < FI; ++i) ld4(g.y + row0 + wm * (BM / 2) + i * 16 + lg * 4, yv[i]);
+    }
 
     // staging: thread t loads groups t, t + 256, ... of each operand tile;
     // group x covers row x / GPR, k = 4 (x % GPR) .. + 3 of the stage
-    TC ra[LPT][4], rb[LPT][4];
-    bool rok[LPT];
+    TC ra[LPA][4], rb[LPB][4];
+    bool rka[LPA], rkb[LPB];
     // loads only: a group past kend re-reads k = kbeg (always valid); its
     // zeroing happens at the LDS store, so no instruction consumes the loaded
     // registers before the stage's MFMA work has been issued
     auto load_stage = [&](int k0) {
 #pragma unroll
-        for (int v = 0; v < LPT; ++v) {
+        for (int v = 0; v < LPA; ++v) {
             const int x = tid + 256 * v;
             const int r = x / GPR, kq = 4 * (x % GPR);
-            rok[v] = k0 + kq < kend;
-            const int kk = rok[v] ? k0 + kq : kbeg;
-            ld4(A + (int64_t)(row0 + r) * g.lda + kk, ra[v]);
-            ld4(Bg + (int64_t)(col0 + r) * g.ldb + kk, rb[v]);
+            rka[v] = k0 + kq < kend;
+            ld4(A + (int64_t)(row0 + r) * g.lda + (rka[v] ? k0 + kq : kbeg), ra[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < LPB; ++v) {
+            const int x = tid + 256 * v;
+            const int r = x / GPR, kq = 4 * (x % GPR);
+            rkb[v] = k0 + kq < kend;
+            ld4(Bg + (int64_t)(col0 + r) * g.ldb + (rkb[v] ? k0 + kq : kbeg), rb[v]);
         }
     };
     auto store_stage = [&](int bufi) {
 #pragma unroll
-        for (int v = 0; v < LPT; ++v) {
+        for (int v = 0; v < LPA; ++v) {
             const int x = tid + 256 * v;
             const int r = x / GPR, kq = 4 * (x % GPR);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                As[bufi][r * LS + kq + e] = rok[v] ? ra[v][e] : (TC)0;
-                Bs[bufi][r * LS + kq + e] = rok[v] ? rb[v][e] : (TC)0;
-            }
+            for (int e = 0; e < 4; ++e) As[bufi][r * LS + kq + e] = rka[v] ? ra[v][e] : (TC)0;
+        }
+#pragma unroll
+        for (int v = 0; v < LPB; ++v) {
+            const int x = tid + 256 * v;
+            const int r = x / GPR, kq = 4 * (x % GPR);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[bufi][r * LS + kq + e] = rkb[v] ? rb[v][e] : (TC)0;
         }
     };
 
     // contract sub-blocks [0, nh) of the LDS stage in buffer bi
     auto compute = [&](int bi, int h) {
-        TC av[2][4], bv[2][4];
+        TC av[FI][4], bv[2][4];
+#pragma unroll
+        for (int f = 0; f < FI; ++f) {
+            const TC *pa = &As[bi][(wm * (BM / 2) + f * 16 + arow) * LS + 16 * h + 4 * lg];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) av[f][s] = pa[s];
+        }
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
-            const TC *pa = &As[bi][(wm * 32 + f * 16 + arow) * LS + 16 * h + 4 * lg];
             const TC *pb = &Bs[bi][(wn * 32 + f * 16 + lr) * LS + 16 * h + 4 * lg];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                av[f][s] = pa[s];
-                bv[f][s] = pb[s];
-            }
+            for (int s = 0; s < 4; ++s) bv[f][s] = pb[s];
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < FI; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = mfma16(av[i][s], bv[j][s], acc[i][j]);
@@ -310,7 +346,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     }
 
     // ---- epilogue ----------------------------------------------------------
-    // acc[i][j][r] holds C at row = row0 + wm*32 + i*16 + lg*4 + r,
+    // acc[i][j][r] holds C at row = row0 + wm*BM/2 + i*16 + lg*4 + r,
     //                        col = col0 + wn*32 + j*16 + lr.
     if constexpr (MODE == EPI_DLOSS) {
         TC *C = reinterpret_cast<TC *>(g.C);
@@ -318,13 +354,13 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
         for (int j = 0; j < 2; ++j) {
             const int col = col0 + wn * 32 + j * 16 + lr;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int rb0 = row0 + wm * 32 + i * 16 + lg * 4;
+            for (int i = 0; i < FI; ++i) {
+                const int rb0 = row0 + wm * (BM / 2) + i * 16 + lg * 4;
                 acc_t o;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = rb0 + r;
-                    o[r] = (row < g.n) ? dloss_t<TC>(g.loss, acc[i][j][r], (TC)g.y[row]) : (TC)0;
+                    const TC d = dloss_t<TC>(g.loss, acc[i][j][r], (TC)yv[i][r]);
+                    o[r] = (rb0 + r < g.n) ? d : (TC)0;
                 }
                 *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = o;
             }
@@ -335,8 +371,8 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
         for (int j = 0; j < 2; ++j) {
             const int col = col0 + wn * 32 + j * 16 + lr;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int rb0 = row0 + wm * 32 + i * 16 + lg * 4;
+            for (int i = 0; i < FI; ++i) {
+                const int rb0 = row0 + wm * (BM / 2) + i * 16 + lg * 4;
                 if (rb0 + 3 < g.rows_valid) {
                     *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = acc[i][j];
                 } else {
@@ -356,21 +392,18 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
             const int col = col0 + wn * 32 + j * 16 + lr;
             double sl = 0.0, sc = 0.0;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int rb0 = row0 + wm * 32 + i * 16 + lg * 4;
+            for (int i = 0; i < FI; ++i) {
+                const int rb0 = row0 + wm * (BM / 2) + i * 16 + lg * 4;
                 f64x4 o;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = rb0 + r;
-                    if (row < g.n) {
-                        double z, lv, cv;
-                        cert_terms(g.loss, acc[i][j][r], g.y[row], z, lv, cv);
-                        o[r] = z;
-                        sl += lv;
-                        sc += cv;
-                    } else {
-                        o[r] = 0.0;
-                    }
+                    double z, lv, cv;
+                    cert_terms(g.loss, acc[i][j][r], yv[i][r], z, lv, cv);
+                    const bool in = row < g.n;
+                    o[r] = in ? z : 0.0;
+                    sl += in ? lv : 0.0;
+                    sc += in ? cv : 0.0;
                 }
                 *reinterpret_cast<f64x4 *>(C + (int64_t)col * g.ldc + rb0) = o;
             }
@@ -1270,11 +1303,20 @@ __global__ __launch_bounds__(256) void k_reduce_splits(const T *__restrict__ par
 // ===========================================================================
 // Launchers
 // ===========================================================================
+// rows: the A operand's (padded) row count, a multiple of 64.  BM = 32 when
+// 64-row tiles would leave fewer than two workgroups per CU (256 CUs), so
+// that resident workgroups hide each other's load latency.
 template <typename TA, typename TB, typename TC, int MODE>
-static void gemm(hipStream_t s, const GemmArgs &g, int tiles_n, int splits)
+static void gemm(hipStream_t s, GemmArgs g, int rows, int tiles_n, int splits)
 {
-    dim3 grid(g.tiles_m * tiles_n, splits);
-    hipLaunchKernelGGL((k_gemm_tn<TA, TB, TC, MODE>), grid, dim3(256), 0, s, g);
+    g.tiles_n = tiles_n;
+    const bool small = (int64_t)(rows / 64) * tiles_n * splits < 512;
+    const int bm = small ? 32 : 64;
+    g.tiles_m = rows / bm;
+    const int tm_grid = (g.tiles_m >= 8) ? (g.tiles_m + 7) / 8 * 8 : g.tiles_m;
+    dim3 grid(tm_grid * tiles_n, splits);
+    if (small) hipLaunchKernelGGL((k_gemm_tn<TA, TB, TC, MODE, 32>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm_tn<TA, TB, TC, MODE, 64>), grid, dim3(256), 0, s, g);
 }
 
 void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
@@ -1283,12 +1325,12 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
     GemmArgs g{};
     g.col_status = status;
     g.A = X; g.lda = c.ldp; g.B = Yi; g.ldb = c.ldp; g.C = R; g.ldc = c.npad;
-    g.k_len = c.ldp; g.k_chunk = c.ldp; g.tiles_m = c.npad / GEMM_BM;
+    g.k_len = c.ldp; g.k_chunk = c.ldp;
     g.n = c.n; g.loss = c.loss; g.y = y;
     const int tn = c.mpad / GEMM_BN;
-    if (iter_f64) gemm<double, double, double, EPI_DLOSS>(s, g, tn, 1);
-    else if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS>(s, g, tn, 1);
-    else gemm<uint16_t, float, float, EPI_DLOSS>(s, g, tn, 1);
+    if (iter_f64) gemm<double, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
+    else if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
+    else gemm<uint16_t, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
 }
 
 void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
@@ -1298,11 +1340,11 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
     g.col_status = status;
     g.A = XT; g.lda = c.npad; g.B = R; g.ldb = c.npad; g.C = Gp; g.ldc = c.ldp;
     g.split_stride = (int64_t)c.mpad * c.ldp;
-    g.k_len = c.npad; g.k_chunk = gchunk; g.tiles_m = c.pm / GEMM_BM; g.rows_valid = c.ldp;
+    g.k_len = c.npad; g.k_chunk = gchunk; g.rows_valid = c.ldp;
     const int tn = c.mpad / GEMM_BN;
-    if (iter_f64) gemm<double, double, double, EPI_STORE>(s, g, tn, gsplit);
-    else if (xtype == XT_F32) gemm<float, float, float, EPI_STORE>(s, g, tn, gsplit);
-    else gemm<uint16_t, float, float, EPI_STORE>(s, g, tn, gsplit);
+    if (iter_f64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
+    else if (xtype == XT_F32) gemm<float, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
+    else gemm<uint16_t, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
 }
 
 void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,
@@ -1312,12 +1354,12 @@ void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, d
     GemmArgs g{};
     g.col_status = status;
     g.A = X; g.lda = c.ldp; g.B = B; g.ldb = c.ldp; g.C = Z; g.ldc = c.npad;
-    g.k_len = c.ldp; g.k_chunk = c.ldp; g.tiles_m = c.npad / GEMM_BM;
+    g.k_len = c.ldp; g.k_chunk = c.ldp;
     g.n = c.n; g.loss = c.loss; g.y = y; g.lsum = lsum; g.csum = csum; g.ldsum = c.mpad;
     const int tn = c.mpad / GEMM_BN;
-    if (xtype == XT_F64) gemm<double, double, double, EPI_CERT>(s, g, tn, 1);
-    else if (xtype == XT_F32) gemm<float, double, double, EPI_CERT>(s, g, tn, 1);
-    else gemm<uint16_t, double, double, EPI_CERT>(s, g, tn, 1);
+    if (xtype == XT_F64) gemm<double, double, double, EPI_CERT>(s, g, c.npad, tn, 1);
+    else if (xtype == XT_F32) gemm<float, double, double, EPI_CERT>(s, g, c.npad, tn, 1);
+    else gemm<uint16_t, double, double, EPI_CERT>(s, g, c.npad, tn, 1);
 }
 
 void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, double *Qp,
@@ -1327,11 +1369,11 @@ void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, 
     g.col_status = status;
     g.A = XT; g.lda = c.npad; g.B = Z; g.ldb = c.npad; g.C = Qp; g.ldc = c.ldp;
     g.split_stride = (int64_t)c.mpad * c.ldp;
-    g.k_len = c.npad; g.k_chunk = qchunk; g.tiles_m = c.pm / GEMM_BM; g.rows_valid = c.ldp;
+    g.k_len = c.npad; g.k_chunk = qchunk; g.rows_valid = c.ldp;
     const int tn = c.mpad / GEMM_BN;
-    if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, tn, qsplit);
-    else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, tn, qsplit);
-    else gemm<uint16_t, double, double, EPI_STORE>(s, g, tn, qsplit);
+    if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, qsplit);
+    else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, c.pm, tn, qsplit);
+    else gemm<uint16_t, double, double, EPI_STORE>(s, g, c.pm, tn, qsplit);
 }
 
 #define KBNB_PP_DISPATCH(P, CALL)                     \
