@@ -305,7 +305,7 @@ enum { KT_FWD = 0, KT_BWD = 1, KT_PROX = 2, KT_CFWD = 3, KT_CBWD = 4, KT_CFIN = 
 static int enqueue_round_timed(kbnb_problem *P, std::vector<int> &kinds)
 {
     hipStream_t s = P->stream;
-    const size_t need = 2 * (4 * (size_t)P->cert_period + 4);
+    const size_t need = 2 * (3 * (size_t)P->cert_period + 3);
     while (P->ev.size() < need) {
         hipEvent_t e;
         HIP_TRY(hipEventCreate(&e));
@@ -313,27 +313,29 @@ static int enqueue_round_timed(kbnb_problem *P, std::vector<int> &kinds)
     }
     kinds.clear();
     size_t q = 0;
-    auto mark = [&](int kind) { kinds.push_back(kind); return P->ev[q++]; };
+    // each launch carries its own start/stop events (kernel timestamps)
+    auto timed = [&](int kind) {
+        kinds.push_back(kind);
+        g_ktime.start = P->ev[q];
+        g_ktime.stop = P->ev[q + 1];
+        q += 2;
+    };
     for (int it = 0; it < P->cert_period; ++it) {
-        HIP_TRY(hipEventRecord(mark(KT_FWD), s));
+        timed(KT_FWD);
         launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, P->c, P->ss.status);
-        HIP_TRY(hipEventRecord(P->ev[q++], s));
-        HIP_TRY(hipEventRecord(mark(KT_BWD), s));
+        timed(KT_BWD);
         launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c, P->ss.status);
-        HIP_TRY(hipEventRecord(P->ev[q++], s));
-        HIP_TRY(hipEventRecord(mark(KT_PROX), s));
+        timed(KT_PROX);
         launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit_pad, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
-        HIP_TRY(hipEventRecord(P->ev[q++], s));
     }
-    HIP_TRY(hipEventRecord(mark(KT_CFWD), s));
+    timed(KT_CFWD);
     launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c, P->ss.status);
-    HIP_TRY(hipEventRecord(P->ev[q++], s));
-    HIP_TRY(hipEventRecord(mark(KT_CBWD), s));
+    timed(KT_CBWD);
     launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
-    HIP_TRY(hipEventRecord(P->ev[q++], s));
-    HIP_TRY(hipEventRecord(mark(KT_CFIN), s));
+    timed(KT_CFIN);
     launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
-    HIP_TRY(hipEventRecord(P->ev[q++], s));
+    g_ktime = KernelTiming{};
+    HIP_TRY(hipGetLastError());
     return 0;
 }
 

@@ -34,7 +34,7 @@ __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + 
 // multiple of this count, the extra ones staying zero.
 __host__ __device__ constexpr int split_batch(int pp, int elem_bytes)
 {
-    return (elem_bytes == 4) ? ((pp >= 2048) ? 4 : ((pp >= 1024) ? 8 : ((pp >= 512) ? 16 : 32)))
+    return (elem_bytes == 4) ? ((pp >= 2048) ? 4 : ((pp >= 1024) ? 8 : 16))
                              : ((pp >= 2048) ? 2 : ((pp >= 1024) ? 4 : ((pp >= 512) ? 8 : 16)));
 }
 
@@ -72,6 +72,13 @@ struct AdmitRec {
 };
 
 enum XType { XT_F64 = 0, XT_F32 = 1, XT_BF16 = 2 };
+
+// When `start` is set, the next launch of the calling thread records the
+// kernel's own start/end timestamps in (start, stop) (instrumentation).
+struct KernelTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local KernelTiming g_ktime;
 
 // ---- launchers (kbnb_kernels.hip) -----------------------------------------
 // iteration GEMMs (Ti = float for float32/bfloat16... instances, double for float64)

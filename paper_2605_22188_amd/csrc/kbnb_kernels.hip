@@ -12,12 +12,27 @@
 //   cfin  per node: g*(Q / 2 lambda2) by TopSum selection, g(B) in closed form,
 //         primal/dual values, status, rounding support and branching index.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cmath>
 #include <cstdint>
 
 #include "kbnb_internal.h"
 
 namespace kbnb {
+
+thread_local KernelTiming g_ktime;
+
+// Every launch goes through this macro: when the calling thread has set a
+// timing pair, the kernel is launched with hipExtLaunchKernelGGL so that the
+// events carry the kernel's own start and end timestamps.
+#define KBNB_LAUNCH(KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                        \
+    do {                                                                                         \
+        if (g_ktime.start)                                                                       \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, g_ktime.start, g_ktime.stop, \
+                                  0, __VA_ARGS__);                                               \
+        else                                                                                     \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                   \
+    } while (0)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -173,6 +188,7 @@ struct GemmArgs {
     int k_chunk;           // k per split (multiple of 16)
     int tiles_m;
     int tiles_n;
+    int nsplit;
     const int32_t *col_status;  // nullable: skip tiles with no running column
     int rows_valid;        // store rows < rows_valid (EPI_STORE)
     int n;                 // rows with data (EPI_DLOSS / EPI_CERT)
@@ -219,17 +235,28 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     // (blockIdx % 8), each with its own L2.  The tiles that share an A row
     // tile (all column tiles of one row tile) go to the same XCD and are
     // dispatched back to back, so A is fetched into one L2 and reused there.
-    int tm, tn;
-    if (g.tiles_m >= 8) {
+    int tm, tn, split;
+    if (g.nsplit > 1) {
+        // split-K: every tile of one k-split goes to the same XCD, so both
+        // operand chunks of the split are fetched into one L2 and read there
+        const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+        const int T = g.tiles_m * g.tiles_n;
+        split = xcd + 8 * (q / T);
+        const int t = q % T;
+        tm = t % g.tiles_m;
+        tn = t / g.tiles_m;
+        if (split >= g.nsplit) return;
+    } else if (g.tiles_m >= 8) {
+        split = 0;
         const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
         tn = q % g.tiles_n;
         tm = (q / g.tiles_n) * 8 + xcd;
         if (tm >= g.tiles_m) return;
     } else {
+        split = 0;
         tm = blockIdx.x % g.tiles_m;
         tn = blockIdx.x / g.tiles_m;
     }
-    const int split = blockIdx.y;
     const int row0 = tm * BM, col0 = tn * BN;
     const int kbeg = split * g.k_chunk;
     const int kend = min(g.k_len, kbeg + g.k_chunk);
@@ -1310,13 +1337,17 @@ template <typename TA, typename TB, typename TC, int MODE>
 static void gemm(hipStream_t s, GemmArgs g, int rows, int tiles_n, int splits)
 {
     g.tiles_n = tiles_n;
+    g.nsplit = splits;
     const bool small = (int64_t)(rows / 64) * tiles_n * splits < 512;
     const int bm = small ? 32 : 64;
     g.tiles_m = rows / bm;
-    const int tm_grid = (g.tiles_m >= 8) ? (g.tiles_m + 7) / 8 * 8 : g.tiles_m;
-    dim3 grid(tm_grid * tiles_n, splits);
-    if (small) hipLaunchKernelGGL((k_gemm_tn<TA, TB, TC, MODE, 32>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_gemm_tn<TA, TB, TC, MODE, 64>), grid, dim3(256), 0, s, g);
+    int nblocks;
+    if (splits > 1) nblocks = 8 * g.tiles_m * tiles_n * ((splits + 7) / 8);
+    else if (g.tiles_m >= 8) nblocks = (g.tiles_m + 7) / 8 * 8 * tiles_n;
+    else nblocks = g.tiles_m * tiles_n;
+    dim3 grid(nblocks, 1);
+    if (small) KBNB_LAUNCH((k_gemm_tn<TA, TB, TC, MODE, 32>), grid, dim3(256), 0, s, g);
+    else KBNB_LAUNCH((k_gemm_tn<TA, TB, TC, MODE, 64>), grid, dim3(256), 0, s, g);
 }
 
 void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
@@ -1391,10 +1422,10 @@ void launch_reduce(hipStream_t s, bool f64, const void *parts, int nsplit, void 
     const int64_t stride = count;
     dim3 grid((unsigned)((count / 4 + 255) / 256));
     if (f64)
-        hipLaunchKernelGGL((k_reduce_splits<double>), grid, dim3(256), 0, s, (const double *)parts, nsplit,
+        KBNB_LAUNCH((k_reduce_splits<double>), grid, dim3(256), 0, s, (const double *)parts, nsplit,
                            stride, (double *)out, count, c.ldp, status);
     else
-        hipLaunchKernelGGL((k_reduce_splits<float>), grid, dim3(256), 0, s, (const float *)parts, nsplit,
+        KBNB_LAUNCH((k_reduce_splits<float>), grid, dim3(256), 0, s, (const float *)parts, nsplit,
                            stride, (float *)out, count, c.ldp, status);
 }
 
@@ -1402,10 +1433,10 @@ void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, 
                       double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c)
 {
     if (iter_f64) {
-        KBNB_PP_DISPATCH(c.p, hipLaunchKernelGGL((k_prox_iter<double, PP>), dim3(c.m), dim3(64), 0, s,
+        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<double, PP>), dim3(c.m), dim3(64), 0, s,
                                                  (const double *)Gp, gsplit, B, Bprev, (double *)Yi, st, ss, c));
     } else {
-        KBNB_PP_DISPATCH(c.p, hipLaunchKernelGGL((k_prox_iter<float, PP>), dim3(c.m), dim3(64), 0, s,
+        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<float, PP>), dim3(c.m), dim3(64), 0, s,
                                                  (const float *)Gp, gsplit, B, Bprev, (float *)Yi, st, ss, c));
     }
 }
@@ -1413,7 +1444,7 @@ void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, 
 void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const int32_t *kbar,
                        double *Bout, int m, double eta, const Consts &c)
 {
-    KBNB_PP_DISPATCH(c.p, hipLaunchKernelGGL((k_prox_batch<PP>), dim3(m), dim3(64), 0, s, U, st, kbar,
+    KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_batch<PP>), dim3(m), dim3(64), 0, s, U, st, kbar,
                                              Bout, eta, c));
 }
 
@@ -1421,7 +1452,7 @@ void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const doubl
                         const double *csum, int tiles_n, const double *B, const int8_t *st,
                         SlotState ss, const Consts &c, int update_state)
 {
-    KBNB_PP_DISPATCH(c.p, hipLaunchKernelGGL((k_cert_finish<PP>), dim3(c.m), dim3(64), 0, s, Qp, qsplit,
+    KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_cert_finish<PP>), dim3(c.m), dim3(64), 0, s, Qp, qsplit,
                                              lsum, csum, tiles_n, B, st, ss, c, update_state));
 }
 
@@ -1430,10 +1461,10 @@ void launch_admit(hipStream_t s, bool iter_f64, const uint8_t *stage, int count,
 {
     if (count <= 0) return;
     if (iter_f64)
-        hipLaunchKernelGGL((k_admit<double>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
+        KBNB_LAUNCH((k_admit<double>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
                            (double *)Yi, st, ss, c);
     else
-        hipLaunchKernelGGL((k_admit<float>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
+        KBNB_LAUNCH((k_admit<float>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
                            (float *)Yi, st, ss, c);
 }
 
@@ -1442,11 +1473,11 @@ void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int
 {
     dim3 grid((rows + 3) / 4);
     if (xtype == XT_F64)
-        hipLaunchKernelGGL((k_matvec<double>), grid, dim3(256), 0, s, (const double *)A, lda, rows, cols, v, out);
+        KBNB_LAUNCH((k_matvec<double>), grid, dim3(256), 0, s, (const double *)A, lda, rows, cols, v, out);
     else if (xtype == XT_F32)
-        hipLaunchKernelGGL((k_matvec<float>), grid, dim3(256), 0, s, (const float *)A, lda, rows, cols, v, out);
+        KBNB_LAUNCH((k_matvec<float>), grid, dim3(256), 0, s, (const float *)A, lda, rows, cols, v, out);
     else
-        hipLaunchKernelGGL((k_matvec<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)A, lda, rows, cols, v, out);
+        KBNB_LAUNCH((k_matvec<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)A, lda, rows, cols, v, out);
 }
 
 void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
@@ -1455,11 +1486,11 @@ void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, 
     (void)pm;
     dim3 grid((p + 31) / 32, (n + 31) / 32);
     if (xtype == XT_F64)
-        hipLaunchKernelGGL((k_transpose<double>), grid, dim3(256), 0, s, (const double *)X, (double *)XT, n, p, ldp, npad);
+        KBNB_LAUNCH((k_transpose<double>), grid, dim3(256), 0, s, (const double *)X, (double *)XT, n, p, ldp, npad);
     else if (xtype == XT_F32)
-        hipLaunchKernelGGL((k_transpose<float>), grid, dim3(256), 0, s, (const float *)X, (float *)XT, n, p, ldp, npad);
+        KBNB_LAUNCH((k_transpose<float>), grid, dim3(256), 0, s, (const float *)X, (float *)XT, n, p, ldp, npad);
     else
-        hipLaunchKernelGGL((k_transpose<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)X, (uint16_t *)XT, n, p, ldp, npad);
+        KBNB_LAUNCH((k_transpose<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)X, (uint16_t *)XT, n, p, ldp, npad);
 }
 
 }  // namespace kbnb
