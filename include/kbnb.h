@@ -148,7 +148,10 @@ int submit_nodes(kbnb_problem *prob, const kbnb_node_desc *nodes, int32_t count)
  * not NULL it receives, for result i, the rounding support (J1 plus the kbar
  * largest free |beta_j|, ties to the lowest index; Sec. 4.3) sorted ascending
  * in supports[i*k .. i*k+support_len-1], the rest set to -1.  If `betas` is
- * not NULL it receives the float64 iterate of result i in betas[i*p .. +p-1].
+ * not NULL it receives the float64 iterate of result i in betas[i*p .. +p-1]:
+ * the certified iterate with the least primal value, i.e. primal_value is
+ * Phi_N at exactly this point, and the support and branch_index are its
+ * rounding support and largest free coordinate.
  * Returns KBNB_OK, or KBNB_TIMEOUT if nothing completed in time.
  */
 int poll_bounds(kbnb_problem *prob, kbnb_bound_result *out, int32_t cap,
@@ -160,11 +163,13 @@ typedef struct {
     double node_rel_tol;     /* per-node relative gap; 0 -> 1e-6 */
     int32_t max_fista_iters; /* per node; 0 -> 20000 */
     int64_t max_nodes;       /* 0 -> unlimited */
+    double log_every_s;      /* > 0: one progress line on stderr at this period; 0 -> silent */
 } kbnb_bnb_options;
 
 typedef struct {
     double objective;   /* incumbent value v(S) = min over supp beta in S, |beta| <= M */
-    double lower_bound; /* certified global lower bound */
+    double lower_bound; /* certified global lower bound: the least bound of any
+                           pruned, closed or unexplored node, capped at objective */
     double rel_gap;
     int64_t nodes;      /* nodes bounded */
     int32_t status;     /* 0 optimal (gap <= tol), 1 time limit, 2 node limit */
@@ -232,7 +237,7 @@ int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
  * timing; mode -1: leave the mode unchanged.  out (nullable, 18 doubles)
  * receives the counters before the mode change: out[0..7] total milliseconds
  * of the kernel types {forward X Y, backward X^T R, prox, certificate X B,
- * certificate X^T zeta, certificate finish, admission, split-K reduction},
+ * certificate X^T zeta, certificate finish, admission, (unused, 0)},
  * out[8..15] their launch counts, out[16] the sum over timed iteration
  * launches of sum_b (p - |J0_b|) over the nodes in the batch, out[17] the sum
  * over timed iteration launches of the number of nodes in the batch.

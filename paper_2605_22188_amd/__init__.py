@@ -60,7 +60,7 @@ class BoundResult(ctypes.Structure):
 class BnbOptions(ctypes.Structure):
     _fields_ = [("time_limit_s", ctypes.c_double), ("rel_gap_tol", ctypes.c_double),
                 ("node_rel_tol", ctypes.c_double), ("max_fista_iters", ctypes.c_int32),
-                ("max_nodes", ctypes.c_int64)]
+                ("max_nodes", ctypes.c_int64), ("log_every_s", ctypes.c_double)]
 
 
 class BnbResult(ctypes.Structure):
@@ -239,12 +239,12 @@ def bound_nodes(h: Handle, nodes, **kw):
 
 
 def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=0.0,
-                     max_fista_iters=0, max_nodes=0):
+                     max_fista_iters=0, max_nodes=0, log_every_s=0.0):
     sup = np.full(h.k, -1, np.int32)
     beta = np.zeros(h.p)
     o = BnbOptions(time_limit_s=time_limit_s, rel_gap_tol=rel_gap_tol,
                    node_rel_tol=node_rel_tol, max_fista_iters=max_fista_iters,
-                   max_nodes=max_nodes)
+                   max_nodes=max_nodes, log_every_s=log_every_s)
     r = BnbResult(support=_p(sup), beta=_p(beta))
     _check(load().branch_and_bound(h.ptr, ctypes.byref(o), ctypes.byref(r)))
     return dict(objective=r.objective, lower_bound=r.lower_bound, rel_gap=r.rel_gap,

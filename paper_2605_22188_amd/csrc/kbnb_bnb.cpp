@@ -16,7 +16,10 @@
 //     children, both warm-started from the parent iterate (z_j = 0 zeroes
 //     beta_j).
 // Pruning: bound >= UB - 1e-6 |UB|.  Termination: no open or in-flight node,
-// or (UB - global bound) <= rel_gap_tol * |UB|.
+// or (UB - global bound) <= rel_gap_tol * |UB|.  The reported lower bound is
+// the least bound over every leaf of the explored tree (pruned nodes, closed
+// nodes) and every node left open, so it is certified even when pruning used
+// the relative slack.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -102,6 +105,8 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     std::vector<int32_t> full_out;
     std::vector<std::vector<int32_t>> outs_store;
     double global_lb = -INFINITY;
+    double leaf_lb = INFINITY;  // least bound of the discarded subtrees
+    double last_log = 0.0;
 
     auto prunable = [&](double lb) { return lb >= UB - prune_rel * std::fabs(UB); };
 
@@ -110,6 +115,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         while (!open.empty() && prunable(open.top()->lb)) {
             Open *o = open.top();
             open.pop();
+            leaf_lb = std::min(leaf_lb, o->lb);
             delete o;
             // every remaining node has a bound at least as large
             while (!open.empty()) {
@@ -127,6 +133,13 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         if (std::isfinite(UB) && !reopt_pending && global_lb >= UB - gap_tol * std::fabs(UB)) break;
         if (opt->time_limit_s > 0 && elapsed() > opt->time_limit_s) { status = 1; break; }
         if (opt->max_nodes > 0 && nodes >= opt->max_nodes) { status = 2; break; }
+        if (opt->log_every_s > 0 && elapsed() - last_log >= opt->log_every_s) {
+            last_log = elapsed();
+            fprintf(stderr, "[bnb] %.1fs nodes %lld open %zu in flight %zu UB %.10g LB %.10g\n",
+                    last_log, (long long)nodes, open.size(), flight.size(), UB,
+                    std::min(global_lb, leaf_lb));
+            fflush(stderr);
+        }
 
         // fill the device
         batch.clear();
@@ -197,6 +210,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             ++nodes;
             const double lb = std::max(br.lower_bound, o->lb);
             if (prunable(lb)) {
+                leaf_lb = std::min(leaf_lb, lb);
                 delete o;
                 continue;
             }
@@ -215,6 +229,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             const int pf = p - (int)o->in.size() - (int)o->out.size();
             const int j = br.branch_index;
             if (kbar <= 0 || pf <= kbar || j < 0) {
+                leaf_lb = std::min(leaf_lb, lb);
                 delete o;
                 continue;
             }
@@ -278,6 +293,8 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                     ++updates;
                 }
             } else {
+                // unexplored: its parent's bound still holds for its subtree
+                global_lb = std::min(global_lb, it->second.node->lb);
                 delete it->second.node;
             }
             flight.erase(it);
@@ -292,9 +309,8 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         delete open.top();
         open.pop();
     }
-    if (status == 0) global_lb = UB;
     res->objective = UB;
-    res->lower_bound = std::min(global_lb, UB);
+    res->lower_bound = std::min(std::min(global_lb, leaf_lb), UB);
     res->rel_gap = std::isfinite(UB) ? (UB - res->lower_bound) / std::max(std::fabs(UB), 1e-12) : INFINITY;
     res->nodes = nodes;
     res->status = status;

@@ -99,8 +99,7 @@ struct kbnb_problem {
     void *X = nullptr, *XT = nullptr, *Yi = nullptr, *R = nullptr, *Gp = nullptr;
     double *y = nullptr, *B = nullptr, *Bprev = nullptr, *Z = nullptr, *Qp = nullptr;
     double *lsum = nullptr, *csum = nullptr, *gbuf = nullptr;
-    void *Gsum = nullptr;      // reduced gradient [mpad][ldp], iteration type
-    double *Qsum = nullptr;    // reduced X^T zeta [mpad][ldp]
+    double *Bbest = nullptr;   // iterate of the best certified primal value [mpad][ldp]
     int8_t *st = nullptr;
     uint8_t *stage_d = nullptr;
     int32_t *gslots_d = nullptr;
@@ -163,13 +162,12 @@ static size_t per_slot_bytes(const kbnb_problem *P)
 {
     const size_t ti = P->ti_bytes;
     size_t b = 0;
-    b += (size_t)P->ldp * (ti + 8 + 8 + 1);            // Yi, B, Bprev, st
+    b += (size_t)P->ldp * (ti + 8 + 8 + 8 + 1);        // Yi, B, Bprev, Bbest, st
     b += (size_t)P->npad * (ti + 8);                   // R, Z
     b += (size_t)P->gsplit_pad * P->ldp * ti;          // Gp
     b += (size_t)P->qsplit_pad * P->ldp * 8;           // Qp
     b += (size_t)P->tiles_n * 16;                      // lsum, csum
     b += (size_t)P->ldp * 8 + 128 + P->k * 4;          // gather buffer, scalars, support
-    b += (size_t)P->ldp * (ti + 8);                    // reduced G and Q
     b += (size_t)P->pp * 4;                            // sort permutation
     return b;
 }
@@ -186,8 +184,8 @@ static void choose_splits(kbnb_problem *P)
     P->gsplit = (P->npad + chunk - 1) / chunk;
     P->qchunk = chunk;
     P->qsplit = P->gsplit;
-    P->gsplit_pad = (int)round_up(P->gsplit, split_batch(P->pp, P->ti_bytes));
-    P->qsplit_pad = (int)round_up(P->qsplit, split_batch(P->pp, 8));
+    P->gsplit_pad = (int)round_up(P->gsplit, split_batch(node_wave_cols(P->pp), P->ti_bytes));
+    P->qsplit_pad = (int)round_up(P->qsplit, split_batch(node_wave_cols(P->pp), 8));
 }
 
 static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
@@ -215,8 +213,7 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         mp * 8 * 7,                              // double slot arrays
         mp * 4 * 7,                              // int slot arrays
         mp * P->k * 4,                           // supports
-        mp * P->ldp * ti,                        // G (reduced)
-        mp * P->ldp * 8,                         // Q (reduced)
+        mp * P->ldp * 8,                         // Bbest
         mp * (size_t)P->pp * 4,                  // sort permutations
     };
     const int nitems = sizeof(sizes) / sizeof(sizes[0]);
@@ -273,9 +270,8 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
     P->ss.jstar = ii + 4 * mp;
     P->ss.slen = ii + 5 * mp;
     P->ss.sup = (int32_t *)(base + off[18]);
-    P->ss.perm = (int32_t *)(base + off[21]);
-    P->Gsum = base + off[19];
-    P->Qsum = (double *)(base + off[20]);
+    P->Bbest = (double *)(base + off[19]);
+    P->ss.perm = (int32_t *)(base + off[20]);
     P->slot_dev = base + off[16];
     P->slot_bytes = off[18] + sizes[18] - off[16];
     return 0;
@@ -294,7 +290,7 @@ static void enqueue_round(kbnb_problem *P)
     }
     launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c, P->ss.status);
     launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
-    launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
+    launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, P->c, 1);
 }
 
 // Kernel types for the timing instrumentation.
@@ -333,7 +329,7 @@ static int enqueue_round_timed(kbnb_problem *P, std::vector<int> &kinds)
     timed(KT_CBWD);
     launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
     timed(KT_CFIN);
-    launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->st, P->ss, P->c, 1);
+    launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, P->c, 1);
     g_ktime = KernelTiming{};
     HIP_TRY(hipGetLastError());
     return 0;
@@ -418,7 +414,7 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
     do {
         if (nadm) {
             HIP_TRY(hipMemcpyAsync(P->stage_d, P->stage_h, (size_t)nadm * P->rec_bytes, hipMemcpyHostToDevice, s));
-            launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
+            launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Bbest, P->Yi, P->st, P->ss, P->c);
         }
         std::vector<int> kinds;
         const bool timed = P->timing;
@@ -450,7 +446,7 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
         }
         if (nfin) {
             HIP_TRY(hipMemcpyAsync(P->gslots_d, P->h_gslots, (size_t)nfin * 4, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_gather_cols, dim3(nfin), dim3(256), 0, s, P->B, P->ldp, P->p, P->gslots_d, P->gbuf);
+            hipLaunchKernelGGL(k_gather_cols, dim3(nfin), dim3(256), 0, s, P->Bbest, P->ldp, P->p, P->gslots_d, P->gbuf);
             HIP_TRY(hipMemcpyAsync(P->h_gbuf, P->gbuf, (size_t)nfin * P->p * 8, hipMemcpyDeviceToHost, s));
             // retired slots must not iterate again
             hipLaunchKernelGGL(k_retire, dim3((nfin + 255) / 256), dim3(256), 0, s, P->gslots_d, nfin, P->ss.status);
@@ -602,7 +598,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     *out = nullptr;
     if (d->n <= 0 || d->p <= 0 || d->k <= 0 || d->k > d->p)
         return fail(KBNB_E_INVALID_ARGUMENT, "need n > 0, 0 < k <= p (n=%d p=%d k=%d)", d->n, d->p, d->k);
-    if (d->p > 2048) return fail(KBNB_E_INVALID_ARGUMENT, "p=%d exceeds the supported maximum 2048", d->p);
+    if (d->p > 8192) return fail(KBNB_E_INVALID_ARGUMENT, "p=%d exceeds the supported maximum 8192", d->p);
     if (d->k > 128) return fail(KBNB_E_INVALID_ARGUMENT, "k=%d exceeds the supported maximum 128", d->k);
     if (d->loss != KBNB_LOSS_SQUARED && d->loss != KBNB_LOSS_LOGISTIC)
         return fail(KBNB_E_INVALID_ARGUMENT, "unknown loss %d", d->loss);
@@ -979,7 +975,7 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     ss.lb = dlb; ss.phi = dphi; ss.kbar = dk; ss.sup = dsup; ss.jstar = djs; ss.slen = dslen;
     launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c, nullptr);
     launch_cert_bwd(T.s, P->xtype, P->XT, dZ, dQ, qsplit, P->qchunk, c, nullptr);
-    launch_cert_finish(T.s, dQ, qsplit_pad, dl, dc, P->tiles_n, dB, dst, ss, c, 0);
+    launch_cert_finish(T.s, dQ, qsplit_pad, dl, dc, P->tiles_n, dB, nullptr, dst, ss, c, 0);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(psi, dlb, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));
     HIP_TRY(hipMemcpyAsync(phi, dphi, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));

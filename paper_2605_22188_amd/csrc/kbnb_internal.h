@@ -32,6 +32,12 @@ __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + 
 // Splits summed per load batch by the per-node kernels (sort width pp,
 // element size in bytes): the split-K partial buffers are allocated in a
 // multiple of this count, the extra ones staying zero.
+// Padded column length of the per-node kernels: the power of two >= p, at
+// least 256, at most 8192.  Up to 2048 a node runs on one wave; above, on
+// pp / 1024 waves, so every thread holds 16 coordinates.
+__host__ __device__ constexpr int node_waves(int pp) { return pp <= 2048 ? 1 : pp / 1024; }
+// coordinates a wave of the per-node kernels holds (64 threads x E)
+__host__ __device__ constexpr int node_wave_cols(int pp) { return pp / node_waves(pp); }
 __host__ __device__ constexpr int split_batch(int pp, int elem_bytes)
 {
     return (elem_bytes == 4) ? ((pp >= 2048) ? 4 : ((pp >= 1024) ? 8 : 16))
@@ -88,8 +94,6 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
 void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
                 void *Gp, int gsplit, int gchunk, const Consts &c, const int32_t *status);
 // G = sum of split-K partials (float, or double when f64), running columns only
-void launch_reduce(hipStream_t s, bool f64, const void *parts, int nsplit, void *out,
-                   const Consts &c, const int32_t *status);
 // the per-node kernels sum the split-K partials themselves
 void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, double *B,
                       double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c);
@@ -99,12 +103,15 @@ void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, d
                      const int32_t *status);
 void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, double *Qp,
                      int qsplit, int qchunk, const Consts &c, const int32_t *status);
+// Bbest (engine only, nullable when update_state is 0): receives B of a
+// certificate that improves the slot's best primal value
 void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const double *lsum,
-                        const double *csum, int tiles_n, const double *B, const int8_t *st,
-                        SlotState ss, const Consts &c, int update_state);
+                        const double *csum, int tiles_n, const double *B, double *Bbest,
+                        const int8_t *st, SlotState ss, const Consts &c, int update_state);
 // admission of staged nodes into slots
 void launch_admit(hipStream_t s, bool iter_f64, const uint8_t *stage, int count, int rec_bytes,
-                  double *B, double *Bprev, void *Yi, int8_t *st, SlotState ss, const Consts &c);
+                  double *B, double *Bprev, double *Bbest, void *Yi, int8_t *st, SlotState ss,
+                  const Consts &c);
 // standalone prox over a batch (u given), for the step-level entry point
 void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const int32_t *kbar,
                        double *Bout, int m, double eta, const Consts &c);

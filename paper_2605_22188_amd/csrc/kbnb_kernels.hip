@@ -454,8 +454,13 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront helpers.
+// Wavefront and workgroup helpers.  A per-node workgroup has W waves; with
+// W = 1 the block-level helpers are the plain wave operations.  Every block
+// helper must be reached by all threads of the workgroup.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -466,12 +471,6 @@ __device__ __forceinline__ int wave_sum_i(int v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
 // argmax with ties to the lowest index; (v, i) pairs, i = INT_MAX for none
@@ -487,6 +486,119 @@ __device__ __forceinline__ void wave_argmax(double &v, int &i)
         }
     }
 }
+// inclusive prefix sum over the lanes of a wave
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int ln = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T t = __shfl_up(v, o);
+        if (ln >= o) v += t;
+    }
+    return v;
+}
+
+// Sums reduce the per-wave totals in wave order, so every thread gets the
+// same bits.
+template <int W>
+__device__ __forceinline__ double blk_sum(double v)
+{
+    v = wave_sum(v);
+    if constexpr (W == 1) {
+        return v;
+    } else {
+        __shared__ double red[W];
+        __syncthreads();
+        if (lane_id() == 0) red[wave_id()] = v;
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) s += red[q];
+        return s;
+    }
+}
+template <int W>
+__device__ __forceinline__ int blk_sum_i(int v)
+{
+    v = wave_sum_i(v);
+    if constexpr (W == 1) {
+        return v;
+    } else {
+        __shared__ int red[W];
+        __syncthreads();
+        if (lane_id() == 0) red[wave_id()] = v;
+        __syncthreads();
+        int s = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) s += red[q];
+        return s;
+    }
+}
+template <int W>
+__device__ __forceinline__ int blk_max_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    if constexpr (W == 1) {
+        return v;
+    } else {
+        __shared__ int red[W];
+        __syncthreads();
+        if (lane_id() == 0) red[wave_id()] = v;
+        __syncthreads();
+        int s = red[0];
+#pragma unroll
+        for (int q = 1; q < W; ++q) s = max(s, red[q]);
+        return s;
+    }
+}
+template <int W>
+__device__ __forceinline__ bool blk_any(bool pred)
+{
+    if constexpr (W == 1) return __ballot(pred) != 0ull;
+    else return __syncthreads_or(pred) != 0;
+}
+template <int W>
+__device__ __forceinline__ void blk_argmax(double &v, int &i)
+{
+    wave_argmax(v, i);
+    if constexpr (W > 1) {
+        __shared__ double rv[W];
+        __shared__ int ri[W];
+        __syncthreads();
+        if (lane_id() == 0) {
+            rv[wave_id()] = v;
+            ri[wave_id()] = i;
+        }
+        __syncthreads();
+        v = rv[0];
+        i = ri[0];
+#pragma unroll
+        for (int q = 1; q < W; ++q)
+            if (rv[q] > v || (rv[q] == v && ri[q] < i)) {
+                v = rv[q];
+                i = ri[q];
+            }
+    }
+}
+// exclusive prefix sum over the workgroup's threads (in thread order)
+template <int W, typename T>
+__device__ __forceinline__ T blk_excl_scan(T v)
+{
+    const T incl = wave_incl_scan(v);
+    if constexpr (W == 1) {
+        return incl - v;
+    } else {
+        __shared__ T tot[W];
+        __syncthreads();
+        if (lane_id() == 63) tot[wave_id()] = incl;
+        __syncthreads();
+        T off = 0;
+        for (int q = 0; q < wave_id(); ++q) off += tot[q];
+        return off + incl - v;
+    }
+}
 
 // Huber prox: argmin_v 1/2 (v - x)^2 + c H_M(v)
 __device__ __forceinline__ double prox_huber(double x, double c, double M)
@@ -500,19 +612,18 @@ __device__ __forceinline__ double huber(double q, double M)
     return (a <= M) ? 0.5 * q * q : M * a - 0.5 * M * M;
 }
 
-// Bitonic sort of PP (key, idx) pairs in LDS by one 64-lane wave:
+// Bitonic sort of PP (key, idx) pairs in LDS by the whole workgroup:
 // key descending, idx ascending on equal keys (a strict total order).
-template <int PP>
-__device__ void bitonic_desc(double *key, int *idx)
+template <int PP, typename TI>
+__device__ void bitonic_desc(double *key, TI *idx)
 {
-    const int l = threadIdx.x;
     for (int size = 2; size <= PP; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = l; t < PP / 2; t += 64) {
+            for (int t = threadIdx.x; t < PP / 2; t += blockDim.x) {
                 const int i = 2 * t - (t & (stride - 1));
                 const int j = i + stride;
                 const double ki = key[i], kj = key[j];
-                const int ii = idx[i], ij = idx[j];
+                const TI ii = idx[i], ij = idx[j];
                 const bool i_first = (ki > kj) || (ki == kj && ii < ij);
                 const bool want_desc = ((i & size) == 0);
                 if (want_desc != i_first) {
@@ -526,11 +637,12 @@ __device__ void bitonic_desc(double *key, int *idx)
 }
 
 // ---------------------------------------------------------------------------
-// Per-node kernels run one 64-lane wave per node.  Lane l owns the contiguous
-// coordinates j = E l .. E l + E - 1 (E = PP / 64 with PP >= 256 a power of
-// two >= p), i.e. E / 4 whole groups of four, so a node's column is read and
-// written with 16-byte vector accesses.  Groups at or beyond ldp (the padded
-// column length, a multiple of 16) are not touched.
+// Per-node kernels run one workgroup of W waves per node (W = 1 up to
+// PP = 2048, more above).  Thread t owns the contiguous coordinates
+// j = E t .. E t + E - 1 (E = PP / (64 W); PP >= 256 a power of two >= p),
+// i.e. E / 4 whole groups of four, so a node's column is read and written
+// with 16-byte vector accesses.  Groups at or beyond ldp (the padded column
+// length, a multiple of 16) are not touched.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void ld4_i8(const int8_t *p, int o[4])
 {
@@ -547,11 +659,7 @@ __device__ __forceinline__ void st4(double *p, const double v[4])
     *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
 }
 
-
-// Sum of split-K partials for a lane's chunk: acc[e] += sum_s src[s * stride + e]
-// for e < 4 * NQ.  Loads are issued in batches of SB splits before any is
-// added, so up to SB * NQ 16-byte loads per lane are in flight at once.
-// Sum of split-K partials for a lane's chunk: acc[e] += sum_s col[s * stride + j0 + e].
+// Sum of split-K partials for a thread's chunk: acc[e] += sum_s col[s * stride + j0 + e].
 // nsplit is padded to a multiple of the batch (the padding partial buffers are
 // zero), so the batch loop has no conditions and all SB * NQ 16-byte loads of
 // a batch are in flight together.  Group addresses are clamped into the
@@ -577,6 +685,9 @@ __device__ __forceinline__ void sum_splits(const T *__restrict__ col, int nsplit
             for (int e = 0; e < 4 * NQ; ++e) acc[e] += (double)v[i][e];
     }
 }
+
+// Waves per node workgroup for a padded column length PP.
+template <int PP> struct NodeWaves { static constexpr int W = node_waves(PP); };
 
 // ---------------------------------------------------------------------------
 // Masked prox of one node (paper Sec. 4.2 "Evaluating proximal operators with
@@ -605,13 +716,13 @@ __device__ __forceinline__ void sum_splits(const T *__restrict__ col, int nsplit
 template <int PP>
 struct ProxLds {
     double key[PP];       // free magnitudes in sorted (descending) order
-    int rank[PP];         // sorted position of each free coordinate
+    uint16_t rank[PP];    // sorted position of each free coordinate
     double psum[PP + 1];  // prefix sums of rho * key
     int bmin[128];        // per left end a: smallest passing right end
     double vblk[128];     // per left end a: block value V(a, b(a))
 };
 
-// Register bitonic sort of the wave's 64 E (key, idx) pairs; lane l holds
+// Register bitonic sort of one wave's 64 E (key, idx) pairs; lane l holds
 // positions l E .. l E + E - 1.  Order: key descending, idx ascending on equal
 // keys (strict).  Strides below E are compare-exchanges inside a lane; larger
 // strides pair lane l with lane l ^ (stride / E) through shuffles.
@@ -619,7 +730,7 @@ template <int PP>
 __device__ __forceinline__ void reg_bitonic_desc(double (&key)[PP / 64], int (&idx)[PP / 64])
 {
     constexpr int E = PP / 64;
-    const int l = threadIdx.x;
+    const int l = lane_id();
 #pragma unroll
     for (int size = 2; size <= PP; size <<= 1) {
 #pragma unroll
@@ -666,14 +777,17 @@ __device__ __forceinline__ bool before(double ka, int ia, double kb, int ib)
 // that order and repaired by odd-even transposition rounds, which is cheap
 // because the order of |u| changes little between steps; the full sort runs
 // only if 8 rounds leave it unsorted.  The new order is written back.
-template <int PP>
-__device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const int (&sv)[PP / 64],
-                            int p, int kbar, double eta, double lambda2, double M,
-                            double (&bet)[PP / 64], int32_t *perm, bool have_prev)
+template <int PP, int W>
+__device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / (64 * W)],
+                            const int (&sv)[PP / (64 * W)], int p, int kbar, double eta,
+                            double lambda2, double M, double (&bet)[PP / (64 * W)],
+                            int32_t *perm, bool have_prev)
 {
-    constexpr int E = PP / 64;
-    const int l = threadIdx.x;
-    const int j0 = l * E;
+    constexpr int E = PP / (64 * W);
+    constexpr int T = 64 * W;
+    const int t = threadIdx.x;
+    const int ln = lane_id();
+    const int j0 = t * E;
     const double rho = 1.0 / (2.0 * eta * lambda2);
     const double shrink = 1.0 + 2.0 * eta * lambda2;
     double key[E];
@@ -687,7 +801,7 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
         idx[e] = j;
         nfree += fr ? 1 : 0;
     }
-    const int pf = wave_sum_i(nfree);
+    const int pf = blk_sum_i<W>(nfree);
     bool sorted = false;
     if (perm && have_prev) {
         // keys by coordinate into LDS, then gathered in the previous order
@@ -707,7 +821,7 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
         }
         for (int round = 0; round < 8; ++round) {
             int swaps = 0;
-            // even pairs (2i, 2i + 1) lie inside a lane
+            // even pairs (2i, 2i + 1) lie inside a thread
 #pragma unroll
             for (int e = 0; e + 1 < E; e += 2) {
                 if (!before(key[e], idx[e], key[e + 1], idx[e + 1])) {
@@ -716,7 +830,7 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
                     ++swaps;
                 }
             }
-            // odd pairs: inside a lane, plus (last of lane l, first of lane l + 1)
+            // odd pairs: inside a thread, plus (last of thread t, first of t + 1)
 #pragma unroll
             for (int e = 1; e + 1 < E; e += 2) {
                 if (!before(key[e], idx[e], key[e + 1], idx[e + 1])) {
@@ -725,15 +839,28 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
                     ++swaps;
                 }
             }
-            const double nk = __shfl_down(key[0], 1);
-            const int ni = __shfl_down(idx[0], 1);
-            const double pk = __shfl_up(key[E - 1], 1);
-            const int pi = __shfl_up(idx[E - 1], 1);
-            const bool swap_hi = (l < 63) && !before(key[E - 1], idx[E - 1], nk, ni);
-            const bool swap_lo = (l > 0) && !before(pk, pi, key[0], idx[0]);
+            double nk = __shfl_down(key[0], 1);
+            int ni = __shfl_down(idx[0], 1);
+            double pk = __shfl_up(key[E - 1], 1);
+            int pi = __shfl_up(idx[E - 1], 1);
+            if constexpr (W > 1) {
+                // neighbours across a wave boundary go through LDS; the
+                // barrier of blk_any below orders these reads before the
+                // next round's writes
+                __shared__ double xk_first[W], xk_last[W];
+                __shared__ int xi_first[W], xi_last[W];
+                const int w = wave_id();
+                if (ln == 0) { xk_first[w] = key[0]; xi_first[w] = idx[0]; }
+                if (ln == 63) { xk_last[w] = key[E - 1]; xi_last[w] = idx[E - 1]; }
+                __syncthreads();
+                if (ln == 63 && w + 1 < W) { nk = xk_first[w + 1]; ni = xi_first[w + 1]; }
+                if (ln == 0 && w > 0) { pk = xk_last[w - 1]; pi = xi_last[w - 1]; }
+            }
+            const bool swap_hi = (t < T - 1) && !before(key[E - 1], idx[E - 1], nk, ni);
+            const bool swap_lo = (t > 0) && !before(pk, pi, key[0], idx[0]);
             if (swap_hi) { key[E - 1] = nk; idx[E - 1] = ni; ++swaps; }
             if (swap_lo) { key[0] = pk; idx[0] = pi; ++swaps; }
-            if (__ballot(swaps != 0) == 0ull) {
+            if (!blk_any<W>(swaps != 0)) {
                 sorted = true;
                 break;
             }
@@ -742,17 +869,17 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
     }
     if (sorted) {
         // repaired in place
-    } else if constexpr (E <= 4) {
+    } else if constexpr (W == 1 && E <= 4) {
         reg_bitonic_desc<PP>(key, idx);
     } else {
         // wide chunks: sort through LDS (the register network would be too
-        // large to unroll); L.psum and L.rank serve as scratch for the pairs
-        double *sk = L.psum;
-        int *si = L.rank;
+        // large to unroll); L.key and L.rank serve as the pair arrays
+        double *sk = L.key;
+        uint16_t *si = L.rank;
 #pragma unroll
-        for (int e = 0; e < E; ++e) { sk[j0 + e] = key[e]; si[j0 + e] = idx[e]; }
+        for (int e = 0; e < E; ++e) { sk[j0 + e] = key[e]; si[j0 + e] = (uint16_t)idx[e]; }
         __syncthreads();
-        bitonic_desc<PP>(sk, si);
+        bitonic_desc<PP, uint16_t>(sk, si);
 #pragma unroll
         for (int e = 0; e < E; ++e) { key[e] = sk[j0 + e]; idx[e] = si[j0 + e]; }
         __syncthreads();
@@ -769,20 +896,14 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
     for (int e = 0; e < E; ++e) {
         const int r = j0 + e;
         L.key[r] = key[e];
-        if (r < pf) L.rank[idx[e]] = r;
+        if (r < pf) L.rank[idx[e]] = (uint16_t)r;
         acc += (r < pf) ? rho * key[e] : 0.0;
         loc[e] = acc;
     }
-    double incl = acc;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const double t = __shfl_up(incl, o);
-        if (l >= o) incl += t;
-    }
-    const double excl = incl - acc;
+    const double excl = blk_excl_scan<W, double>(acc);
 #pragma unroll
     for (int e = 0; e < E; ++e) L.psum[j0 + e + 1] = excl + loc[e];
-    if (l == 0) L.psum[0] = 0.0;
+    if (t == 0) L.psum[0] = 0.0;
     __syncthreads();
 
     int ba = 0, bb_end = -1, top;
@@ -795,12 +916,12 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
         top = kbar;
         const double wl = rho * L.key[kbar - 1], wr = rho * L.key[kbar];
         if (prox_huber(wl, rho, M) < wr) {
-            // lane a finds b(a) by binary search (the right test is monotone
-            // in b), then V(a, b(a)) and the left test; the left end is the
-            // largest a that passes
+            // thread a finds b(a) by binary search (the right test is
+            // monotone in b), then V(a, b(a)) and the left test; the left end
+            // is the largest a that passes
             int found = -1;
-            for (int a0 = ((kbar - 1) / 64) * 64; a0 >= 0 && found < 0; a0 -= 64) {
-                const int a = a0 + l;
+            for (int a0 = ((kbar - 1) / T) * T; a0 >= 0 && found < 0; a0 -= T) {
+                const int a = a0 + t;
                 bool left = false;
                 if (a < kbar) {
                     const double pa = L.psum[a];
@@ -822,8 +943,7 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
                     L.vblk[a] = Va;
                     left = (a == 0) || (prox_huber(rho * L.key[a - 1], rho, M) >= Va);
                 }
-                const unsigned long long mask = __ballot(left);
-                if (mask) found = a0 + 63 - __clzll(mask);
+                found = blk_max_i<W>(left ? a : -1);
             }
             __syncthreads();
             if (found >= 0) {
@@ -853,24 +973,24 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / 64], const in
 }
 
 // ---------------------------------------------------------------------------
-// Prox + FISTA momentum for every running slot (one wave per slot).  The
+// Prox + FISTA momentum for every running slot (one workgroup per slot).  The
 // gradient is the sum of the split-K partials of X^T R, read here directly:
-// all loads of a lane's chunk are independent, so they are in flight together.
+// all loads of a thread's chunk are independent, so they are in flight together.
 // ---------------------------------------------------------------------------
-template <typename Ti, int PP>
-__global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int gsplit,
-                                                   double *__restrict__ B, double *__restrict__ Bprev,
-                                                   Ti *__restrict__ Yi, const int8_t *__restrict__ stg,
-                                                   SlotState ss, Consts c)
+template <typename Ti, int PP, int W>
+__global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp, int gsplit,
+                                                       double *__restrict__ B, double *__restrict__ Bprev,
+                                                       Ti *__restrict__ Yi, const int8_t *__restrict__ stg,
+                                                       SlotState ss, Consts c)
 {
-    constexpr int E = PP / 64, NQ = E / 4;
+    constexpr int E = PP / (64 * W), NQ = E / 4;
     __shared__ ProxLds<PP> L;
     const int b = blockIdx.x;
-    const int l = threadIdx.x;
+    const int t = threadIdx.x;
     if (ss.status[b] != SLOT_RUNNING) return;
     const int64_t off = (int64_t)b * c.ldp;
     const int64_t gstride = (int64_t)c.mpad * c.ldp;
-    const int j0 = l * E;
+    const int j0 = t * E;
     const double th = ss.theta[b];
 
     double g[E], bo[E], bp[E], u[E], y[E], bet[E];
@@ -898,21 +1018,21 @@ __global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int
         y[e] = bo[e] + th * (bo[e] - bp[e]);
         u[e] = y[e] - c.eta * g[e];
     }
-    masked_prox<PP>(L, u, sv, c.p, ss.kbar[b], c.eta, c.lambda2, c.M, bet,
-                    ss.perm + (int64_t)b * c.pp, ss.iter[b] > 0);
+    masked_prox<PP, W>(L, u, sv, c.p, ss.kbar[b], c.eta, c.lambda2, c.M, bet,
+                       ss.perm + (int64_t)b * c.pp, ss.iter[b] > 0);
     // restart test (y - beta+)^T (beta+ - beta) > 0, then momentum
     double dot = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) dot += (y[e] - bet[e]) * (bet[e] - bo[e]);
-    dot = wave_sum(dot);
-    const double t = ss.tmom[b];
+    dot = blk_sum<W>(dot);
+    const double tm = ss.tmom[b];
     double tn, thn;
     if (dot > 0.0) {
         tn = 1.0;
         thn = 0.0;
     } else {
-        tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-        thn = (t - 1.0) / tn;
+        tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tm * tm));
+        thn = (tm - 1.0) / tn;
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -926,7 +1046,7 @@ __global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int
             st4(Yi + off + j, yn);
         }
     }
-    if (l == 0) {
+    if (t == 0) {
         ss.tmom[b] = tn;
         ss.theta[b] = thn;
         ss.iter[b] = ss.iter[b] + 1;
@@ -934,16 +1054,16 @@ __global__ __launch_bounds__(64) void k_prox_iter(const Ti *__restrict__ Gp, int
 }
 
 // Standalone prox over a batch (step-level entry point).
-template <int PP>
-__global__ __launch_bounds__(64) void k_prox_batch(const double *__restrict__ U, const int8_t *__restrict__ stg,
-                                                    const int32_t *__restrict__ kbar, double *__restrict__ Bout,
-                                                    double eta, Consts c)
+template <int PP, int W>
+__global__ __launch_bounds__(64 * W) void k_prox_batch(const double *__restrict__ U, const int8_t *__restrict__ stg,
+                                                        const int32_t *__restrict__ kbar, double *__restrict__ Bout,
+                                                        double eta, Consts c)
 {
-    constexpr int E = PP / 64, NQ = E / 4;
+    constexpr int E = PP / (64 * W), NQ = E / 4;
     __shared__ ProxLds<PP> L;
-    const int b = blockIdx.x, l = threadIdx.x;
+    const int b = blockIdx.x, t = threadIdx.x;
     const int64_t off = (int64_t)b * c.ldp;
-    const int j0 = l * E;
+    const int j0 = t * E;
     double u[E], bet[E];
     int sv[E];
 #pragma unroll
@@ -961,7 +1081,7 @@ __global__ __launch_bounds__(64) void k_prox_batch(const double *__restrict__ U,
             sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
         }
     }
-    masked_prox<PP>(L, u, sv, c.p, kbar[b], eta, c.lambda2, c.M, bet, nullptr, false);
+    masked_prox<PP, W>(L, u, sv, c.p, kbar[b], eta, c.lambda2, c.M, bet, nullptr, false);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int j = j0 + 4 * q;
@@ -970,11 +1090,11 @@ __global__ __launch_bounds__(64) void k_prox_batch(const double *__restrict__ U,
 }
 
 // ---------------------------------------------------------------------------
-// Certificate finish (one wave per slot): paper Sec. 4.4,
+// Certificate finish (one workgroup per slot): paper Sec. 4.4,
 // eqs. batched_primal_value_component / batched_dual_value_component.
 //   q = (sum of the split-K partials of X^T zeta) / (2 lambda2)
 //   g*(q) = sum_{J1} H_M(q_j) + TopSum_kbar{H_M(q_j)}_{free}  (kbar rounds of
-//           wave argmax; fewer free entries than kbar sums them all)
+//           argmax; fewer free entries than kbar sums them all)
 //   g(beta) by Thm. 4.1: J1 contributes beta^2/2; on the free set with
 //           a = |beta| sorted descending (top kbar by the same selection),
 //           at most kbar nonzeros -> sum a^2/2; otherwise the first s in
@@ -997,25 +1117,28 @@ struct CertLds {
     int sup[256];
 };
 
-template <int PP>
-__global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Qp, int qsplit,
-                                                     const double *__restrict__ lsum,
-                                                     const double *__restrict__ csum, int tiles_n,
-                                                     const double *__restrict__ B,
-                                                     const int8_t *__restrict__ stg, SlotState ss,
-                                                     Consts c, int update_state)
+template <int PP, int W>
+__global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict__ Qp, int qsplit,
+                                                         const double *__restrict__ lsum,
+                                                         const double *__restrict__ csum, int tiles_n,
+                                                         const double *__restrict__ B,
+                                                         double *__restrict__ Bbest,
+                                                         const int8_t *__restrict__ stg, SlotState ss,
+                                                         Consts c, int update_state)
 {
-    constexpr int E = PP / 64, NQ = E / 4;
+    constexpr int E = PP / (64 * W), NQ = E / 4;
+    constexpr int T = 64 * W;
     __shared__ CertLds<PP> L;
-    const int b = blockIdx.x, l = threadIdx.x;
+    const int b = blockIdx.x, t = threadIdx.x;
     if (update_state && ss.status[b] != SLOT_RUNNING) return;
     const int p = c.p;
     const int64_t off = (int64_t)b * c.ldp;
     const int64_t qstride = (int64_t)c.mpad * c.ldp;
-    const int j0 = l * E;
+    const int j0 = t * E;
     const int kbar = ss.kbar[b];
     const double inv2l = 1.0 / (2.0 * c.lambda2);
     const double slack = 1.0 + 1e-9;
+    const double phi_prev = update_state ? ss.phi[b] : INFINITY;
 
     double qv[E], bv[E];
     int sv[E];
@@ -1037,12 +1160,12 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
     sum_splits<double, NQ>(Qp + off, qsplit, qstride, j0, c.ldp, qv);
     // smooth parts
     double fl = 0.0, fc = 0.0;
-    for (int t = l; t < tiles_n; t += 64) {
-        fl += lsum[(int64_t)t * c.mpad + b];
-        fc += csum[(int64_t)t * c.mpad + b];
+    for (int q = t; q < tiles_n; q += T) {
+        fl += lsum[(int64_t)q * c.mpad + b];
+        fc += csum[(int64_t)q * c.mpad + b];
     }
-    fl = wave_sum(fl);
-    fc = wave_sum(fc);
+    fl = blk_sum<W>(fl);
+    fc = blk_sum<W>(fc);
 
     double gin = 0.0, g1 = 0.0, sum_a = 0.0, sum_a2 = 0.0;
     int nnz = 0, bad = 0, cin = 0;
@@ -1075,26 +1198,20 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
         L.h[j] = hj;
         L.a[j] = aj;
     }
-    // J1 indices in ascending order: exclusive scan of the per-lane counts
+    // J1 indices in ascending order: exclusive scan of the per-thread counts
     {
-        int incl = cin;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(incl, o);
-            if (l >= o) incl += t;
-        }
-        int pos = incl - cin;
+        int pos = blk_excl_scan<W, int>(cin);
 #pragma unroll
         for (int e = 0; e < E; ++e)
             if (j0 + e < p && sv[e] > 0 && pos < 256) L.sup[pos++] = j0 + e;
     }
-    const int nin = min(256, __shfl(wave_sum_i(cin), 0));
-    gin = wave_sum(gin);
-    g1 = wave_sum(g1);
-    sum_a = wave_sum(sum_a);
-    sum_a2 = wave_sum(sum_a2);
-    nnz = wave_sum_i(nnz);
-    bad = wave_sum_i(bad);
+    const int nin = min(256, blk_sum_i<W>(cin));
+    gin = blk_sum<W>(gin);
+    g1 = blk_sum<W>(g1);
+    sum_a = blk_sum<W>(sum_a);
+    sum_a2 = blk_sum<W>(sum_a2);
+    nnz = blk_sum_i<W>(nnz);
+    bad = blk_sum_i<W>(bad);
     __syncthreads();
 
     // TopSum_kbar of H over the free set
@@ -1102,14 +1219,14 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
     for (int r = 0; r < kbar; ++r) {
         double v = -1.0;
         int vi = 0x7fffffff;
-        for (int j = l; j < PP; j += 64) {
+        for (int j = t; j < PP; j += T) {
             const double hv = L.h[j];
             if (hv > v) { v = hv; vi = j; }
         }
-        wave_argmax(v, vi);
+        blk_argmax<W>(v, vi);
         if (v < 0.0) break;
         topsum += v;
-        if (l == 0) L.h[vi] = -1.0;
+        if (t == 0) L.h[vi] = -1.0;
         __syncthreads();
     }
     // kbar largest |beta| over the free set (ties to the lowest index)
@@ -1118,13 +1235,13 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
     for (int r = 0; r < kcap; ++r) {
         double v = -1.0;
         int vi = 0x7fffffff;
-        for (int j = l; j < PP; j += 64) {
+        for (int j = t; j < PP; j += T) {
             const double av = L.a[j];
             if (av > v) { v = av; vi = j; }
         }
-        wave_argmax(v, vi);
+        blk_argmax<W>(v, vi);
         if (v < 0.0) break;
-        if (l == 0) {
+        if (t == 0) {
             L.topa[r] = v;
             L.topi[r] = vi;
             L.a[vi] = -1.0;
@@ -1140,11 +1257,11 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
     } else {
         double v = -1.0;
         int vi = 0x7fffffff;
-        for (int j = l; j < PP; j += 64) {
+        for (int j = t; j < PP; j += T) {
             const double av = L.a[j];
             if (av > v) { v = av; vi = j; }
         }
-        wave_argmax(v, vi);
+        blk_argmax<W>(v, vi);
         jstar = (v >= 0.0) ? vi : -1;
     }
 
@@ -1179,10 +1296,22 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
     }
     const double phi = fl + 2.0 * c.lambda2 * (g1 + gfree);
     const double psi = -fc - 2.0 * c.lambda2 * (gin + topsum);
+    // In the engine the node's reported iterate is the one with the best
+    // primal value, with its rounding support and branching index: they are
+    // replaced only when this certificate improves that value.
+    const bool nan = (psi != psi) || (phi != phi);
+    const bool improved = !update_state || (!nan && phi < phi_prev);
+    if (update_state && improved) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = j0 + 4 * q;
+            if (j < c.ldp) st4(Bbest + off + j, &bv[4 * q]);
+        }
+    }
 
     // rounding support: J1 (already ascending in L.sup) plus the selected free
     // indices, merged into ascending order
-    if (l == 0) {
+    if (t == 0 && improved) {
         int len = nin;
         for (int r = 0; r < ntop && len < 256; ++r) {
             const int v = L.topi[r];
@@ -1195,11 +1324,12 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
         for (int r = 0; r < c.k; ++r) so[r] = (r < len) ? L.sup[r] : -1;
         ss.slen[b] = len < c.k ? len : c.k;
         ss.jstar[b] = jstar;
+    }
+    if (t == 0) {
         if (update_state) {
             // a NaN value means the iterate broke down: the node keeps its last
             // certified bound and stops with status ERROR
-            const bool nan = (psi != psi) || (phi != phi);
-            double LB = ss.lb[b], PH = ss.phi[b];
+            double LB = ss.lb[b], PH = phi_prev;
             if (!nan && psi > LB) LB = psi;
             if (!nan && phi < PH) PH = phi;
             const double gap = (PH < INFINITY && LB > -INFINITY) ? (PH - LB) / fmax(fabs(PH), 1e-12) : INFINITY;
@@ -1226,8 +1356,8 @@ __global__ __launch_bounds__(64) void k_cert_finish(const double *__restrict__ Q
 // ---------------------------------------------------------------------------
 template <typename Ti>
 __global__ __launch_bounds__(64) void k_admit(const uint8_t *__restrict__ stage, int rec_bytes,
-                                               double *B, double *Bprev, Ti *Yi, int8_t *stg,
-                                               SlotState ss, Consts c)
+                                               double *B, double *Bprev, double *Bbest, Ti *Yi,
+                                               int8_t *stg, SlotState ss, Consts c)
 {
     const uint8_t *rec = stage + (int64_t)blockIdx.x * rec_bytes;
     const AdmitRec h = *reinterpret_cast<const AdmitRec *>(rec);
@@ -1242,6 +1372,7 @@ __global__ __launch_bounds__(64) void k_admit(const uint8_t *__restrict__ stage,
         stg[off + j] = s;
         B[off + j] = w;
         Bprev[off + j] = w;
+        Bbest[off + j] = w;
         Yi[off + j] = (Ti)w;
     }
     if (threadIdx.x == 0) {
@@ -1304,28 +1435,6 @@ __global__ __launch_bounds__(256) void k_transpose(const TA *__restrict__ X, TA 
     }
 }
 
-// ---------------------------------------------------------------------------
-// Split-K reduction: out[i] = sum_s parts[s * stride + i], in split order
-// (deterministic), four elements per thread.  Columns (nodes) that are not
-// running are skipped.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_reduce_splits(const T *__restrict__ parts, int nsplit,
-                                                        int64_t stride, T *__restrict__ out,
-                                                        int64_t count, int ld,
-                                                        const int32_t *__restrict__ status)
-{
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (i >= count) return;
-    if (status && status[i / ld] != SLOT_RUNNING) return;
-    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    for (int s = 0; s < nsplit; ++s) {
-        T v[4];
-        ld4(parts + s * stride + i, v);
-        a0 += v[0]; a1 += v[1]; a2 += v[2]; a3 += v[3];
-    }
-    out[i] = a0; out[i + 1] = a1; out[i + 2] = a2; out[i + 3] = a3;
-}
 
 // ===========================================================================
 // Launchers
@@ -1407,36 +1516,25 @@ void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, 
     else gemm<uint16_t, double, double, EPI_STORE>(s, g, c.pm, tn, qsplit);
 }
 
-#define KBNB_PP_DISPATCH(P, CALL)                     \
-    do {                                              \
-        if ((P) <= 256) { constexpr int PP = 256; CALL; } \
-        else if ((P) <= 512) { constexpr int PP = 512; CALL; } \
-        else if ((P) <= 1024) { constexpr int PP = 1024; CALL; } \
-        else { constexpr int PP = 2048; CALL; } \
+// PP: padded column length of the per-node kernels; W: waves per node.
+#define KBNB_PP_DISPATCH(P, CALL)                                                  \
+    do {                                                                           \
+        if ((P) <= 256) { constexpr int PP = 256, W = NodeWaves<PP>::W; CALL; }    \
+        else if ((P) <= 512) { constexpr int PP = 512, W = NodeWaves<PP>::W; CALL; } \
+        else if ((P) <= 1024) { constexpr int PP = 1024, W = NodeWaves<PP>::W; CALL; } \
+        else if ((P) <= 2048) { constexpr int PP = 2048, W = NodeWaves<PP>::W; CALL; } \
+        else if ((P) <= 4096) { constexpr int PP = 4096, W = NodeWaves<PP>::W; CALL; } \
+        else { constexpr int PP = 8192, W = NodeWaves<PP>::W; CALL; }              \
     } while (0)
-
-void launch_reduce(hipStream_t s, bool f64, const void *parts, int nsplit, void *out,
-                   const Consts &c, const int32_t *status)
-{
-    const int64_t count = (int64_t)c.mpad * c.ldp;
-    const int64_t stride = count;
-    dim3 grid((unsigned)((count / 4 + 255) / 256));
-    if (f64)
-        KBNB_LAUNCH((k_reduce_splits<double>), grid, dim3(256), 0, s, (const double *)parts, nsplit,
-                           stride, (double *)out, count, c.ldp, status);
-    else
-        KBNB_LAUNCH((k_reduce_splits<float>), grid, dim3(256), 0, s, (const float *)parts, nsplit,
-                           stride, (float *)out, count, c.ldp, status);
-}
 
 void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, double *B,
                       double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c)
 {
     if (iter_f64) {
-        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<double, PP>), dim3(c.m), dim3(64), 0, s,
+        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<double, PP, W>), dim3(c.m), dim3(64 * W), 0, s,
                                                  (const double *)Gp, gsplit, B, Bprev, (double *)Yi, st, ss, c));
     } else {
-        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<float, PP>), dim3(c.m), dim3(64), 0, s,
+        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<float, PP, W>), dim3(c.m), dim3(64 * W), 0, s,
                                                  (const float *)Gp, gsplit, B, Bprev, (float *)Yi, st, ss, c));
     }
 }
@@ -1444,28 +1542,29 @@ void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, 
 void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const int32_t *kbar,
                        double *Bout, int m, double eta, const Consts &c)
 {
-    KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_batch<PP>), dim3(m), dim3(64), 0, s, U, st, kbar,
+    KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_batch<PP, W>), dim3(m), dim3(64 * W), 0, s, U, st, kbar,
                                              Bout, eta, c));
 }
 
 void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const double *lsum,
-                        const double *csum, int tiles_n, const double *B, const int8_t *st,
-                        SlotState ss, const Consts &c, int update_state)
+                        const double *csum, int tiles_n, const double *B, double *Bbest,
+                        const int8_t *st, SlotState ss, const Consts &c, int update_state)
 {
-    KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_cert_finish<PP>), dim3(c.m), dim3(64), 0, s, Qp, qsplit,
-                                             lsum, csum, tiles_n, B, st, ss, c, update_state));
+    KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_cert_finish<PP, W>), dim3(c.m), dim3(64 * W), 0, s, Qp, qsplit,
+                                             lsum, csum, tiles_n, B, Bbest, st, ss, c, update_state));
 }
 
 void launch_admit(hipStream_t s, bool iter_f64, const uint8_t *stage, int count, int rec_bytes,
-                  double *B, double *Bprev, void *Yi, int8_t *st, SlotState ss, const Consts &c)
+                  double *B, double *Bprev, double *Bbest, void *Yi, int8_t *st, SlotState ss,
+                  const Consts &c)
 {
     if (count <= 0) return;
     if (iter_f64)
         KBNB_LAUNCH((k_admit<double>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
-                           (double *)Yi, st, ss, c);
+                           Bbest, (double *)Yi, st, ss, c);
     else
         KBNB_LAUNCH((k_admit<float>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
-                           (float *)Yi, st, ss, c);
+                           Bbest, (float *)Yi, st, ss, c);
 }
 
 void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int rows, int cols,
