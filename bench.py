@@ -78,6 +78,152 @@ def run_batch(K, h, nodes, tol):
     return [got[i] for i in range(len(nodes))], lat
 
 
+def bnb_leg(K, W, torch, args):
+    """Time-to-zero-gap of the full GPU branch and bound on the 10000 x 1000
+    bfloat16 squared-loss workload (rho 0.9, k 10, SNR 5, lambda2 1e-3), batch
+    width and certificate period chosen by the autotuner."""
+    inst = W.bnb_squared_10000x1000_bf16()
+    X = torch.from_numpy(inst.X_store).cuda()
+    y = torch.from_numpy(inst.y).cuda()
+    t = time.perf_counter()
+    tune = K.autotune(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
+                      widths=[64, 128, 256, 512, 1024, 2048], periods=[8, 16],
+                      max_iters=args.tune_iters, rel_tol=1e-6, time_limit_s=90.0, seed=2000)
+    t_tune = time.perf_counter() - t
+    log(f"autotune {t_tune:.1f}s -> width {tune['batch_width']} period {tune['cert_period']}; "
+        f"rates {np.round(tune['rates'], 1).tolist()}")
+    h = K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
+                         batch_width=tune["batch_width"], cert_period=tune["cert_period"])
+    torch.cuda.synchronize()
+    out = K.branch_and_bound(h, time_limit_s=args.bnb_time_limit, log_every_s=10.0)
+    K.destroy_problem(h)
+    log(f"bnb: {out['seconds']:.2f}s nodes {out['nodes']} gap {out['rel_gap']:.3g}")
+    return {"workload": "squared_10000x1000_bf16_rho0.9_k10", "seconds": round(out["seconds"], 3),
+            "status": ["zero gap", "time limit", "node limit"][out["status"]],
+            "rel_gap": out["rel_gap"], "objective": out["objective"],
+            "lower_bound": out["lower_bound"], "nodes": int(out["nodes"]),
+            "support": [int(v) for v in out["support"]],
+            "incumbent_updates": int(out["incumbent_updates"]),
+            "autotune": {"batch_width": tune["batch_width"], "cert_period": tune["cert_period"],
+                         "seconds": round(t_tune, 2), "widths": tune["widths"],
+                         "periods": tune["periods"],
+                         "rates": np.round(tune["rates"], 2).tolist(),
+                         "sample": f"{tune['sample_nodes']} generated nodes, "
+                                   f"max {args.tune_iters} iterations each"}}
+
+
+def _make_mix_instance(q):
+    import workloads as W
+    return W.make_instance(q["name"], q["n"], q["p"], q["rho"], q["k"], q["loss"], q["lambda2"],
+                           q["M"], q["dtype"], q["seed"])
+
+
+def serving_leg(K, W, torch, args):
+    """Serving mix: 32 concurrent problems (n ~ U{1000..20000}, p ~ U{100..3000},
+    k ~ U{5..20}, squared/logistic 50/50, rho in {0.3, 0.6, 0.9}, float32 X),
+    each with 2 GiB of the 64 GiB workspace budget.  A saturation burst sets
+    the offered load; then node requests (|J1| ~ U{0..k/2}, |J0| ~ U{0..0.3 p})
+    arrive per problem as a Poisson stream at `serve_load` times the
+    saturated rate, and each request's latency is the time from its arrival
+    to its result at poll."""
+    import threading
+    from concurrent.futures import ProcessPoolExecutor
+    specs = W.serving_mix_problems(32)
+    t = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        insts = list(ex.map(_make_mix_instance, specs))
+    log(f"serving: 32 instances drawn in {time.perf_counter() - t:.1f}s")
+    handles = []
+    for inst in insts:
+        X = torch.from_numpy(inst.X_store).cuda()
+        y = torch.from_numpy(inst.y).cuda()
+        handles.append(K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M,
+                                        dtype=inst.dtype, hbm_budget_bytes=2 << 30,
+                                        cert_period=8))
+        del X, y
+    torch.cuda.synchronize()
+    widths = [K.problem_info(h)["batch_width"] for h in handles]
+    rng = np.random.Generator(np.random.PCG64(777))
+
+    def requests(i, count):
+        inst = insts[i]
+        return W.random_nodes(inst.p, count, inst.k // 2, int(0.3 * inst.p),
+                              seed=int(rng.integers(1 << 30)))
+
+    it_cap = args.serve_iters
+    # saturation: a burst of nodes on every problem at once
+    burst = 64
+    bursts = [requests(i, burst) for i in range(32)]
+    t0 = time.perf_counter()
+    threads = [threading.Thread(target=K.bound_nodes, args=(handles[i], bursts[i]),
+                                kwargs=dict(rel_tol=1e-6, max_iters=it_cap)) for i in range(32)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    t_sat = time.perf_counter() - t0
+    sat_rate = 32 * burst / t_sat
+    log(f"serving: saturated {sat_rate:.0f} node bounds/s")
+    # Poisson stream
+    lam = args.serve_load * sat_rate / 32
+    dur = args.serve_seconds
+    lat, converged, done = [], [0], [0]
+    lock = threading.Lock()
+
+    def run(i):
+        h = handles[i]
+        arr = np.cumsum(rng_i[i].exponential(1.0 / lam, size=int(lam * dur * 2) + 16))
+        arr = arr[arr < dur]
+        nodes = requests_i[i][:len(arr)]
+        start = t_start[0]
+        sub, nxt = {}, 0
+        while nxt < len(arr) or sub:
+            now = time.perf_counter() - start
+            due = []
+            while nxt < len(arr) and arr[nxt] <= now:
+                due.append(nxt)
+                nxt += 1
+            if due:
+                K.submit_nodes(h, [nodes[j] for j in due], tags=due, rel_tol=1e-6,
+                               max_iters=it_cap)
+                for j in due:
+                    sub[j] = arr[j]
+            wait = (arr[nxt] - now) if nxt < len(arr) else 0.05
+            res, _ = K.poll_bounds(h, cap=1024, timeout_us=max(0, int(wait * 1e6)),
+                                   supports=False, betas=False)
+            tnow = time.perf_counter() - start
+            with lock:
+                for r in res:
+                    a = sub.pop(r["tag"])
+                    lat.append(tnow - a)
+                    done[0] += 1
+                    converged[0] += r["status"] == K.CONVERGED
+
+    rng_i = [np.random.Generator(np.random.PCG64(900 + i)) for i in range(32)]
+    requests_i = [requests(i, int(lam * dur * 2) + 16) for i in range(32)]
+    t_start = [time.perf_counter()]
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(32)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    wall = time.perf_counter() - t_start[0]
+    for h in handles:
+        K.destroy_problem(h)
+    lat_ms = np.array(lat) * 1e3
+    log(f"serving: {done[0]} requests in {wall:.1f}s, p50 {np.percentile(lat_ms, 50):.2f} ms, "
+        f"p99 {np.percentile(lat_ms, 99):.2f} ms")
+    return {"workload": "serving_mix_32_problems_f32", "problems": 32,
+            "offered_load": args.serve_load, "saturated_rate": round(sat_rate, 1),
+            "requests": int(done[0]), "seconds": round(wall, 2),
+            "bounds_per_s": round(done[0] / wall, 1),
+            "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                           "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+            "converged_fraction": round(converged[0] / max(1, done[0]), 4),
+            "max_iters": it_cap, "batch_widths": widths,
+            "budget_bytes_per_problem": 2 << 30}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +237,13 @@ def main():
     ap.add_argument("--comparator-nodes", type=int, default=32,
                     help="nodes bounded one at a time at batch width 1 (0 = skip)")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--bnb", type=int, default=1, help="run the time-to-zero-gap leg")
+    ap.add_argument("--bnb-time-limit", type=float, default=150.0)
+    ap.add_argument("--tune-iters", type=int, default=200)
+    ap.add_argument("--serving", type=int, default=1, help="run the serving-mix latency leg")
+    ap.add_argument("--serve-load", type=float, default=0.5)
+    ap.add_argument("--serve-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-iters", type=int, default=2000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -234,6 +387,9 @@ def main():
                           f"{tcpu:.1f}s")}
         log(f"cpu oracle: {cpu['value']} node bounds/s")
 
+    ttz = bnb_leg(K, W, torch, args) if args.bnb else None
+    serving = serving_leg(K, W, torch, args) if args.serving else None
+
     lat_ms = np.array(lat_all) * 1e3
     out = {
         "metric": METRIC,
@@ -264,6 +420,8 @@ def main():
         "kernels": kern,
         "cpu_baseline": cpu,
         "comparator": comparator,
+        "time_to_zero_gap": ttz,
+        "serving": serving,
         "setup_s": round(t_setup, 3),
     }
     K.destroy_problem(h)

@@ -193,6 +193,45 @@ typedef struct {
 int branch_and_bound(kbnb_problem *prob, const kbnb_bnb_options *opts,
                      kbnb_bnb_result *result);
 
+typedef struct {
+    const int32_t *widths;  /* candidate batch widths; NULL -> 64, 128, ..., 2048 */
+    int32_t n_widths;
+    const int32_t *periods; /* candidate certificate periods; NULL -> 4, 8, 16 */
+    int32_t n_periods;
+    int32_t sample_nodes;   /* nodes generated when none are given; 0 -> 2 x largest width */
+    int32_t max_iters;      /* per sample node; 0 -> 2000 */
+    double rel_tol;         /* per sample node; 0 -> 1e-6 */
+    double time_limit_s;    /* no further candidate is started after this; 0 -> 60 */
+    double tie_frac;        /* rates within this fraction of the best tie; 0 -> 0.03 */
+    uint64_t seed;          /* generator seed of the sample nodes */
+} kbnb_tune_options;
+
+typedef struct {
+    int32_t batch_width;    /* the choice */
+    int32_t cert_period;
+    double rate;            /* node bounds per second of the choice on the sample */
+    int32_t trials;         /* candidates measured */
+    int32_t sample_nodes;   /* nodes bounded per candidate */
+    double seconds;         /* total tuning time */
+} kbnb_tune_result;
+
+/*
+ * autotune -- choose the batch width and certificate period for a problem
+ * by measurement (the batch-size sweep of App. E.4, replaced by a timed
+ * search on this device).  For each candidate (width, period) a problem is
+ * created from `desc` with those values, the same sample of nodes is bounded
+ * (the given `nodes`, tags ignored, or `sample_nodes` generated ones with
+ * |J1| ~ U{0..k/2} and |J0| ~ U{0..p/10}, disjoint uniform subsets), and the
+ * rate is sample size / wall time from the first submit to the last result.
+ * Candidates that exceed the budget are skipped (rate 0).  The choice is the
+ * smallest width whose best rate is within tie_frac of the overall best, at
+ * its fastest period.  rates (nullable) receives n_widths x n_periods rates,
+ * row-major by width (0 where skipped or not reached).  desc->batch_width and
+ * desc->cert_period are ignored.
+ */
+int autotune(const kbnb_problem_desc *desc, const kbnb_node_desc *nodes, int32_t count,
+             const kbnb_tune_options *opts, kbnb_tune_result *result, double *rates);
+
 /* last_error -- thread-local description of the last failing call. */
 const char *last_error(void);
 

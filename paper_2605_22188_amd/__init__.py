@@ -71,9 +71,23 @@ class BnbResult(ctypes.Structure):
                 ("incumbent_updates", ctypes.c_int64), ("seconds", ctypes.c_double)]
 
 
+class TuneOptions(ctypes.Structure):
+    _fields_ = [("widths", ctypes.c_void_p), ("n_widths", ctypes.c_int32),
+                ("periods", ctypes.c_void_p), ("n_periods", ctypes.c_int32),
+                ("sample_nodes", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("rel_tol", ctypes.c_double), ("time_limit_s", ctypes.c_double),
+                ("tie_frac", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("batch_width", ctypes.c_int32), ("cert_period", ctypes.c_int32),
+                ("rate", ctypes.c_double), ("trials", ctypes.c_int32),
+                ("sample_nodes", ctypes.c_int32), ("seconds", ctypes.c_double)]
+
+
 EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
-           "branch_and_bound", "last_error", "prox_batch", "certify_batch", "problem_info",
-           "kernel_stats"]
+           "branch_and_bound", "autotune", "last_error", "prox_batch", "certify_batch",
+           "problem_info", "kernel_stats"]
 
 _lib = None
 
@@ -136,11 +150,8 @@ class Handle:
                 pass
 
 
-def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_period=0,
-                   hbm_budget_bytes=0):
-    """X: host array holding the stored entries (float64 / float32 / uint16
-    bfloat16 bits), or a torch CUDA tensor (copied on the device)."""
-    lib = load()
+def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hbm_budget_bytes):
+    """Marshal a problem description; returns (desc, arrays to keep alive, mem flag)."""
     xd = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     keep = []
     if hasattr(X, "is_cuda") and X.is_cuda:
@@ -162,9 +173,46 @@ def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_p
                     x_dtype=xd, mem_flags=mem, X=xptr, ldx=ldx, y=yptr, hip_stream=None,
                     hbm_budget_bytes=int(hbm_budget_bytes), batch_width=int(batch_width),
                     cert_period=int(cert_period))
+    return d, keep, mem
+
+
+def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_period=0,
+                   hbm_budget_bytes=0):
+    """X: host array holding the stored entries (float64 / float32 / uint16
+    bfloat16 bits), or a torch CUDA tensor (copied on the device)."""
+    lib = load()
+    d, keep, mem = _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period,
+                                 hbm_budget_bytes)
     out = ctypes.c_void_p()
     _check(lib.create_problem(ctypes.byref(d), ctypes.byref(out)))
-    return Handle(out, n, p, int(k), keep if mem != MEM_HOST_COPY else [])
+    return Handle(out, d.n, d.p, int(k), keep if mem != MEM_HOST_COPY else [])
+
+
+def autotune(X, y, k, loss, lambda2, M, dtype="f32", nodes=None, widths=None, periods=None,
+             sample_nodes=0, max_iters=0, rel_tol=0.0, time_limit_s=0.0, tie_frac=0.0, seed=0,
+             hbm_budget_bytes=0):
+    """Measure every (batch width, certificate period) candidate on a node
+    sample and return the choice plus the table of rates (node bounds/s)."""
+    lib = load()
+    d, keep, _ = _problem_desc(X, y, k, loss, lambda2, M, dtype, 0, 0, hbm_budget_bytes)
+    w = np.ascontiguousarray(widths if widths is not None else [64, 128, 256, 512, 1024, 2048],
+                             dtype=np.int32)
+    pr = np.ascontiguousarray(periods if periods is not None else [4, 8, 16], dtype=np.int32)
+    o = TuneOptions(widths=_p(w), n_widths=len(w), periods=_p(pr), n_periods=len(pr),
+                    sample_nodes=int(sample_nodes), max_iters=int(max_iters),
+                    rel_tol=float(rel_tol), time_limit_s=float(time_limit_s),
+                    tie_frac=float(tie_frac), seed=int(seed))
+    arr, count = None, 0
+    if nodes is not None:
+        arr, nkeep = _node_array(nodes, math.inf, 0.0, 0, None, None)
+        keep += nkeep
+        count = len(nodes)
+    r = TuneResult()
+    rates = np.zeros((len(w), len(pr)))
+    _check(lib.autotune(ctypes.byref(d), arr, count, ctypes.byref(o), ctypes.byref(r), _p(rates)))
+    return dict(batch_width=r.batch_width, cert_period=r.cert_period, rate=r.rate,
+                trials=r.trials, sample_nodes=r.sample_nodes, seconds=r.seconds,
+                widths=w.tolist(), periods=pr.tolist(), rates=rates)
 
 
 def destroy_problem(h: Handle):
@@ -173,11 +221,8 @@ def destroy_problem(h: Handle):
         _check(load().destroy_problem(ptr))
 
 
-def submit_nodes(h: Handle, nodes, upper_bound=math.inf, rel_tol=0.0, max_iters=0, tags=None,
-                 warm_starts=None):
-    """nodes: sequence of (fixed_in, fixed_out) index arrays (or objects with
-    .fixed_in / .fixed_out).  Per-node upper_bound / rel_tol / max_iters may be
-    scalars or sequences."""
+def _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts):
+    """Marshal node descriptors; returns (ctypes array, arrays to keep alive)."""
     count = len(nodes)
     arr = (NodeDesc * max(count, 1))()
     keep = []
@@ -199,7 +244,17 @@ def submit_nodes(h: Handle, nodes, upper_bound=math.inf, rel_tol=0.0, max_iters=
                           warm_start=_p(w) if w is not None else None,
                           upper_bound=float(pick(upper_bound, i)),
                           rel_tol=float(pick(rel_tol, i)), max_iters=int(pick(max_iters, i)))
-    _check(load().submit_nodes(h.ptr, arr, count))
+    return arr, keep
+
+
+def submit_nodes(h: Handle, nodes, upper_bound=math.inf, rel_tol=0.0, max_iters=0, tags=None,
+                 warm_starts=None):
+    """nodes: sequence of (fixed_in, fixed_out) index arrays (or objects with
+    .fixed_in / .fixed_out).  Per-node upper_bound / rel_tol / max_iters may be
+    scalars or sequences."""
+    arr, keep = _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts)
+    _check(load().submit_nodes(h.ptr, arr, len(nodes)))
+    del keep
 
 
 def poll_bounds(h: Handle, cap=1024, timeout_us=-1, supports=True, betas=True):

@@ -62,11 +62,15 @@ struct Flight {
 }  // namespace
 
 extern "C" int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
+namespace kbnb {
+int set_error(int code, const char *fmt, ...);
+}
 
 extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kbnb_bnb_result *res)
 {
-    if (!P) return KBNB_E_BAD_HANDLE;
-    if (!opt || !res || !res->support) return KBNB_E_INVALID_ARGUMENT;
+    if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (!opt || !res || !res->support)
+        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "options, result and result->support are required");
     int64_t info[8];
     double dinfo[4];
     int rc = problem_info(P, info, dinfo);

@@ -63,6 +63,20 @@ static int fail(int code, const char *fmt, ...)
 
 extern "C" const char *last_error(void) { return g_last_error.c_str(); }
 
+namespace kbnb {
+// error reporting for the host-side drivers built on the C ABI
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+}  // namespace kbnb
+
 // ---------------------------------------------------------------------------
 // problem object
 // ---------------------------------------------------------------------------
@@ -81,6 +95,17 @@ struct DoneNode {
     std::vector<double> beta;
 };
 
+// One launch configuration of a round: the launches cover the first `mact`
+// slot columns, with split-K counts chosen for that many column tiles.  Each
+// has its own captured graph, built on first use.
+struct Variant {
+    int mact = 0;
+    int gsplit = 1, gchunk = 0;
+    int qsplit = 1, qchunk = 0;
+    hipGraphExec_t graph = nullptr;
+    bool captured = false;
+};
+
 struct kbnb_problem {
     // instance
     int n = 0, p = 0, k = 0, loss = 0, xtype = 0;
@@ -89,8 +114,10 @@ struct kbnb_problem {
     int ti_bytes = 4;
     // sizes
     int ldp = 0, npad = 0, pm = 0, m = 0, mpad = 0, pp = 256;
-    int gsplit = 1, gchunk = 0, qsplit = 1, qchunk = 0, tiles_n = 0;
-    int gsplit_pad = 1, qsplit_pad = 1;  // split buffers allocated (multiple of the load batch)
+    int tiles_n = 0;
+    // split-K buffers are allocated for the largest split count of any launch
+    // width (the narrowest width has the most splits)
+    int gsplit_alloc = 1, qsplit_alloc = 1;
     int cert_period = 8;
     uint64_t budget = 0, bytes = 0;
     // device memory
@@ -115,7 +142,7 @@ struct kbnb_problem {
     char *slot_host = nullptr;  // pinned mirror of that block
     size_t slot_bytes = 0;
     hipStream_t stream = nullptr;
-    hipGraphExec_t graph = nullptr;
+    bool use_graphs = true;
     Consts c{};
     // engine
     std::thread worker;
@@ -124,7 +151,9 @@ struct kbnb_problem {
     std::deque<PendingNode> pending;
     std::deque<DoneNode> done;
     std::vector<uint64_t> slot_tag;
-    std::vector<int> free_slots;
+    std::set<int> free_slots;        // lowest index first, so running slots stay packed
+    std::vector<char> occupied;      // slot holds an admitted, unretired node
+    std::vector<Variant> var;        // launch widths 64, 128, ..., mpad
     int active = 0;
     bool shutdown = false;
     bool busy = false;  // a round is in flight
@@ -164,28 +193,46 @@ static size_t per_slot_bytes(const kbnb_problem *P)
     size_t b = 0;
     b += (size_t)P->ldp * (ti + 8 + 8 + 8 + 1);        // Yi, B, Bprev, Bbest, st
     b += (size_t)P->npad * (ti + 8);                   // R, Z
-    b += (size_t)P->gsplit_pad * P->ldp * ti;          // Gp
-    b += (size_t)P->qsplit_pad * P->ldp * 8;           // Qp
+    b += (size_t)P->gsplit_alloc * P->ldp * ti;        // Gp
+    b += (size_t)P->qsplit_alloc * P->ldp * 8;         // Qp
     b += (size_t)P->tiles_n * 16;                      // lsum, csum
     b += (size_t)P->ldp * 8 + 128 + P->k * 4;          // gather buffer, scalars, support
     b += (size_t)P->pp * 4;                            // sort permutation
     return b;
 }
 
-static void choose_splits(kbnb_problem *P)
+// Split-K for a launch covering `mact` columns: enough workgroups to cover
+// the 256 CUs a few times, at most 32 splits (the per-node kernels add the
+// partials, exactly the splits the same round's launch wrote).
+static void splits_for(const kbnb_problem *P, int mact, Variant &v)
 {
-    // backward products: enough workgroups to cover the 256 CUs a few times
-    const int tiles = (P->pm / GEMM_BM) * (P->mpad / GEMM_BN);
+    const int tiles = (P->pm / GEMM_BM) * (mact / GEMM_BN);
     const int kt = P->npad / GEMM_BK;  // 16-wide k chunks
     int want = std::max(1, (256 + tiles - 1) / tiles);
     want = std::min(want, std::max(1, kt / 4));
-    int chunk = (int)round_up((P->npad + want - 1) / want, GEMM_BK);
-    P->gchunk = chunk;
-    P->gsplit = (P->npad + chunk - 1) / chunk;
-    P->qchunk = chunk;
-    P->qsplit = P->gsplit;
-    P->gsplit_pad = (int)round_up(P->gsplit, split_batch(node_wave_cols(P->pp), P->ti_bytes));
-    P->qsplit_pad = (int)round_up(P->qsplit, split_batch(node_wave_cols(P->pp), 8));
+    want = std::min(want, 32);
+    const int chunk = (int)round_up((P->npad + want - 1) / want, GEMM_BK);
+    v.mact = mact;
+    v.gchunk = chunk;
+    v.gsplit = (P->npad + chunk - 1) / chunk;
+    v.qchunk = chunk;
+    v.qsplit = v.gsplit;
+}
+
+static void choose_splits(kbnb_problem *P)
+{
+    P->var.clear();
+    for (int w = GEMM_BN; ; w *= 2) {
+        Variant v;
+        splits_for(P, std::min(w, P->mpad), v);
+        P->var.push_back(v);
+        if (w >= P->mpad) break;
+    }
+    P->gsplit_alloc = P->qsplit_alloc = 1;
+    for (const Variant &v : P->var) {
+        P->gsplit_alloc = std::max(P->gsplit_alloc, v.gsplit);
+        P->qsplit_alloc = std::max(P->qsplit_alloc, v.qsplit);
+    }
 }
 
 static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
@@ -199,11 +246,11 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         (size_t)P->npad * 8,                     // y
         mp * P->ldp * ti,                        // Yi
         mp * P->npad * ti,                       // R
-        (size_t)P->gsplit_pad * mp * P->ldp * ti, // Gp
+        (size_t)P->gsplit_alloc * mp * P->ldp * ti, // Gp
         mp * P->ldp * 8,                         // B
         mp * P->ldp * 8,                         // Bprev
         mp * P->npad * 8,                        // Z
-        (size_t)P->qsplit_pad * mp * P->ldp * 8, // Qp
+        (size_t)P->qsplit_alloc * mp * P->ldp * 8, // Qp
         (size_t)P->tiles_n * mp * 8,             // lsum
         (size_t)P->tiles_n * mp * 8,             // csum
         mp * P->ldp,                             // st
@@ -280,17 +327,25 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
 // ---------------------------------------------------------------------------
 // graph of one engine round
 // ---------------------------------------------------------------------------
-static void enqueue_round(kbnb_problem *P)
+static Consts consts_for(const kbnb_problem *P, const Variant &v)
+{
+    Consts c = P->c;
+    c.mact = v.mact;
+    return c;
+}
+
+static void enqueue_round(kbnb_problem *P, const Variant &v)
 {
     hipStream_t s = P->stream;
+    const Consts c = consts_for(P, v);
     for (int it = 0; it < P->cert_period; ++it) {
-        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, P->c, P->ss.status);
-        launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c, P->ss.status);
-        launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit_pad, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
+        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, c, P->ss.status);
+        launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, v.gsplit, v.gchunk, c, P->ss.status);
+        launch_prox_iter(s, P->iter_f64, P->Gp, v.gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, c);
     }
-    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c, P->ss.status);
-    launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
-    launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, P->c, 1);
+    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, c, P->ss.status);
+    launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, v.qsplit, v.qchunk, c, P->ss.status);
+    launch_cert_finish(s, P->Qp, v.qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, c, 1);
 }
 
 // Kernel types for the timing instrumentation.
@@ -298,9 +353,10 @@ enum { KT_FWD = 0, KT_BWD = 1, KT_PROX = 2, KT_CFWD = 3, KT_CBWD = 4, KT_CFIN = 
 
 // Same launches as enqueue_round, each bracketed by a hipEvent pair on the
 // engine stream; the elapsed times are read after the round synchronises.
-static int enqueue_round_timed(kbnb_problem *P, std::vector<int> &kinds)
+static int enqueue_round_timed(kbnb_problem *P, const Variant &v, std::vector<int> &kinds)
 {
     hipStream_t s = P->stream;
+    const Consts c = consts_for(P, v);
     const size_t need = 2 * (3 * (size_t)P->cert_period + 3);
     while (P->ev.size() < need) {
         hipEvent_t e;
@@ -318,35 +374,46 @@ static int enqueue_round_timed(kbnb_problem *P, std::vector<int> &kinds)
     };
     for (int it = 0; it < P->cert_period; ++it) {
         timed(KT_FWD);
-        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, P->c, P->ss.status);
+        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, c, P->ss.status);
         timed(KT_BWD);
-        launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, P->gsplit, P->gchunk, P->c, P->ss.status);
+        launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, v.gsplit, v.gchunk, c, P->ss.status);
         timed(KT_PROX);
-        launch_prox_iter(s, P->iter_f64, P->Gp, P->gsplit_pad, P->B, P->Bprev, P->Yi, P->st, P->ss, P->c);
+        launch_prox_iter(s, P->iter_f64, P->Gp, v.gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, c);
     }
     timed(KT_CFWD);
-    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, P->c, P->ss.status);
+    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, c, P->ss.status);
     timed(KT_CBWD);
-    launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, P->qsplit, P->qchunk, P->c, P->ss.status);
+    launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, v.qsplit, v.qchunk, c, P->ss.status);
     timed(KT_CFIN);
-    launch_cert_finish(s, P->Qp, P->qsplit_pad, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, P->c, 1);
+    launch_cert_finish(s, P->Qp, v.qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, c, 1);
     g_ktime = KernelTiming{};
     HIP_TRY(hipGetLastError());
     return 0;
 }
 
-static int build_graph(kbnb_problem *P)
+// capture one round of variant v into a graph (once); on failure the round
+// is issued as direct launches
+static void build_graph(kbnb_problem *P, Variant &v)
 {
+    v.captured = true;
     hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return -1;
-    enqueue_round(P);
-    if (hipStreamEndCapture(P->stream, &g) != hipSuccess || !g) return -1;
+    if (hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    enqueue_round(P, v);
+    if (hipStreamEndCapture(P->stream, &g) != hipSuccess || !g) {
+        (void)hipGetLastError();
+        return;
+    }
     hipGraphExec_t ge = nullptr;
     hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return -1;
-    P->graph = ge;
-    return 0;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    v.graph = ge;
 }
 
 __global__ void k_retire(const int32_t *__restrict__ slots, int count, int32_t *__restrict__ status)
@@ -374,8 +441,9 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
     while (!P->pending.empty() && !P->free_slots.empty()) {
         PendingNode nd = std::move(P->pending.front());
         P->pending.pop_front();
-        const int slot = P->free_slots.back();
-        P->free_slots.pop_back();
+        const int slot = *P->free_slots.begin();
+        P->free_slots.erase(P->free_slots.begin());
+        P->occupied[slot] = 1;
         uint8_t *rec = P->stage_h + (size_t)nadm * P->rec_bytes;
         AdmitRec h{};
         h.slot = slot;
@@ -407,6 +475,13 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
                 run_slots += 1;
             }
     }
+    // launch width: the narrowest variant covering every occupied slot
+    int hi = 0;
+    for (int b = P->m - 1; b >= 0; --b)
+        if (P->occupied[b]) { hi = b + 1; break; }
+    Variant *var = &P->var.back();
+    for (Variant &v : P->var)
+        if (v.mact >= hi) { var = &v; break; }
     P->busy = true;
     lk.unlock();
     hipStream_t s = P->stream;
@@ -418,13 +493,14 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
         }
         std::vector<int> kinds;
         const bool timed = P->timing;
+        if (!timed && P->use_graphs && !var->captured) build_graph(P, *var);
         if (timed) {
-            int trc = enqueue_round_timed(P, kinds);
+            int trc = enqueue_round_timed(P, *var, kinds);
             if (trc) return trc;
-        } else if (P->graph) {
-            HIP_TRY(hipGraphLaunch(P->graph, s));
+        } else if (var->graph) {
+            HIP_TRY(hipGraphLaunch(var->graph, s));
         } else {
-            enqueue_round(P);
+            enqueue_round(P, *var);
         }
         HIP_TRY(hipMemcpyAsync(P->slot_host, P->slot_dev, P->slot_bytes, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -467,7 +543,8 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
             d.sup.assign(P->h_sup + (size_t)b * P->k, P->h_sup + (size_t)(b + 1) * P->k);
             d.beta.assign(P->h_gbuf + (size_t)r * P->p, P->h_gbuf + (size_t)(r + 1) * P->p);
             P->done.push_back(std::move(d));
-            P->free_slots.push_back(b);
+            P->free_slots.insert(b);
+            P->occupied[b] = 0;
             --P->active;
         }
         P->busy = false;
@@ -582,7 +659,8 @@ static void free_problem(kbnb_problem *P)
         P->worker.join();
     }
     if (P->stream) (void)hipStreamSynchronize(P->stream);
-    if (P->graph) (void)hipGraphExecDestroy(P->graph);
+    for (Variant &v : P->var)
+        if (v.graph) (void)hipGraphExecDestroy(v.graph);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     if (P->arena) (void)hipFree(P->arena);
     void *pins[] = {P->stage_h, P->slot_host, P->h_gslots, P->h_gbuf};
@@ -664,7 +742,8 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     choose_splits(P);
     P->slot_tag.assign(P->m, 0);
     P->slot_n0.assign(P->m, 0);
-    for (int b = P->m - 1; b >= 0; --b) P->free_slots.push_back(b);
+    for (int b = 0; b < P->m; ++b) P->free_slots.insert(b);
+    P->occupied.assign(P->m, 0);
 
     rc = alloc_arena(P, xbytes, xel);
     if (rc) { free_problem(P); return rc; }
@@ -723,10 +802,8 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->c.ldp = P->ldp; P->c.npad = P->npad; P->c.pm = P->pm; P->c.mpad = P->mpad; P->c.m = P->m;
     P->c.pp = P->pp;
     P->c.lambda2 = P->lambda2; P->c.M = P->M; P->c.eta = P->eta;
-    if (build_graph(P) != 0) {
-        (void)hipGetLastError();
-        P->graph = nullptr;  // direct launches each round
-    }
+    P->c.mact = P->mpad;
+    for (Variant &v : P->var) build_graph(P, v);
     if (hipStreamSynchronize(P->stream) != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "setup failed"); }
     P->worker = std::thread(engine_main, P);
     *out = P;
@@ -845,7 +922,7 @@ extern "C" int problem_info(kbnb_problem *P, int64_t *i_out, double *d_out)
     if (i_out) {
         i_out[0] = P->n; i_out[1] = P->p; i_out[2] = P->k; i_out[3] = P->m;
         i_out[4] = P->cert_period; i_out[5] = P->loss;
-        i_out[6] = P->gsplit; i_out[7] = P->rounds.load();
+        i_out[6] = P->var.back().gsplit; i_out[7] = P->rounds.load();
     }
     if (d_out) {
         d_out[0] = P->L; d_out[1] = P->lambda2; d_out[2] = P->M; d_out[3] = (double)P->bytes;
@@ -952,13 +1029,15 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     Consts c = P->c;
     c.mpad = mpad;
     c.m = m;
+    c.mact = mpad;
+    Variant v;
+    splits_for(P, mpad, v);
     double *dB, *dZ, *dQ, *dQs, *dl, *dc, *dlb, *dphi;
     int8_t *dst;
     int32_t *dk, *dsup, *djs, *dslen;
-    const int qsplit = P->qsplit;
-    const int qsplit_pad = P->qsplit_pad;
+    const int qsplit = v.qsplit;
     if ((rc = T.alloc(&dB, bh.size())) || (rc = T.alloc(&dZ, (size_t)mpad * P->npad)) ||
-        (rc = T.alloc(&dQ, (size_t)qsplit_pad * mpad * P->ldp)) || (rc = T.alloc(&dQs, (size_t)mpad * P->ldp)) ||
+        (rc = T.alloc(&dQ, (size_t)qsplit * mpad * P->ldp)) || (rc = T.alloc(&dQs, (size_t)mpad * P->ldp)) ||
         (rc = T.alloc(&dl, (size_t)P->tiles_n * mpad)) ||
         (rc = T.alloc(&dc, (size_t)P->tiles_n * mpad)) || (rc = T.alloc(&dlb, (size_t)mpad)) ||
         (rc = T.alloc(&dphi, (size_t)mpad)) || (rc = T.alloc(&dst, st.size())) || (rc = T.alloc(&dk, (size_t)mpad)) ||
@@ -968,14 +1047,14 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     HIP_TRY(hipMemcpyAsync(dB, bh.data(), bh.size() * 8, hipMemcpyHostToDevice, T.s));
     HIP_TRY(hipMemcpyAsync(dst, st.data(), st.size(), hipMemcpyHostToDevice, T.s));
     HIP_TRY(hipMemcpyAsync(dk, kbar.data(), (size_t)mpad * 4, hipMemcpyHostToDevice, T.s));
-    HIP_TRY(hipMemsetAsync(dQ, 0, (size_t)qsplit_pad * mpad * P->ldp * 8, T.s));
+    HIP_TRY(hipMemsetAsync(dQ, 0, (size_t)qsplit * mpad * P->ldp * 8, T.s));
     HIP_TRY(hipMemsetAsync(dl, 0, (size_t)P->tiles_n * mpad * 8, T.s));
     HIP_TRY(hipMemsetAsync(dc, 0, (size_t)P->tiles_n * mpad * 8, T.s));
     SlotState ss{};
     ss.lb = dlb; ss.phi = dphi; ss.kbar = dk; ss.sup = dsup; ss.jstar = djs; ss.slen = dslen;
     launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c, nullptr);
-    launch_cert_bwd(T.s, P->xtype, P->XT, dZ, dQ, qsplit, P->qchunk, c, nullptr);
-    launch_cert_finish(T.s, dQ, qsplit_pad, dl, dc, P->tiles_n, dB, nullptr, dst, ss, c, 0);
+    launch_cert_bwd(T.s, P->xtype, P->XT, dZ, dQ, qsplit, v.qchunk, c, nullptr);
+    launch_cert_finish(T.s, dQ, qsplit, dl, dc, P->tiles_n, dB, nullptr, dst, ss, c, 0);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(psi, dlb, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));
     HIP_TRY(hipMemcpyAsync(phi, dphi, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));

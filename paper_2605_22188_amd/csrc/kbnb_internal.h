@@ -29,15 +29,13 @@ constexpr int GEMM_BK = 16;
 
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
-// Splits summed per load batch by the per-node kernels (sort width pp,
-// element size in bytes): the split-K partial buffers are allocated in a
-// multiple of this count, the extra ones staying zero.
 // Padded column length of the per-node kernels: the power of two >= p, at
 // least 256, at most 8192.  Up to 2048 a node runs on one wave; above, on
 // pp / 1024 waves, so every thread holds 16 coordinates.
 __host__ __device__ constexpr int node_waves(int pp) { return pp <= 2048 ? 1 : pp / 1024; }
-// coordinates a wave of the per-node kernels holds (64 threads x E)
-__host__ __device__ constexpr int node_wave_cols(int pp) { return pp / node_waves(pp); }
+// Split-K partials summed per load batch by the per-node kernels (pp: the
+// coordinates one wave holds; element size in bytes), sized so a batch's
+// loads fit in registers.
 __host__ __device__ constexpr int split_batch(int pp, int elem_bytes)
 {
     return (elem_bytes == 4) ? ((pp >= 2048) ? 4 : ((pp >= 1024) ? 8 : 16))
@@ -67,6 +65,7 @@ struct SlotState {
 struct Consts {
     int n, p, k, loss;
     int ldp, npad, pm, mpad, m;
+    int mact;  // columns the launches cover (multiple of 64, <= mpad); slots beyond are empty
     int pp;  // per-node sort width: next power of two >= max(p, 256)
     double lambda2, M, eta;
 };

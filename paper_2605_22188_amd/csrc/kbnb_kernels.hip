@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     }
     const int row0 = tm * BM, col0 = tn * BN;
     const int kbeg = split * g.k_chunk;
-    const int kend = min(g.k_len, kbeg + g.k_chunk);
+    const int kend = max(kbeg, min(g.k_len, kbeg + g.k_chunk));  // an empty split stores zeros
     if (g.col_status) {
         // nodes that finished keep their columns, but a tile whose 64 nodes
         // are all finished (or empty) has nothing to compute
@@ -445,10 +445,17 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
             }
         }
         __syncthreads();
+        // the sums are indexed in 32-row units whatever the tile height, so
+        // launches with either height leave no stale entry behind
         if (tid < 64) {
             const int col = col0 + tid;
-            g.lsum[(int64_t)tm * g.ldsum + col] = red_l[0][tid] + red_l[1][tid];
-            g.csum[(int64_t)tm * g.ldsum + col] = red_c[0][tid] + red_c[1][tid];
+            const int64_t t32 = (int64_t)tm * (BM / 32);
+            g.lsum[t32 * g.ldsum + col] = red_l[0][tid] + red_l[1][tid];
+            g.csum[t32 * g.ldsum + col] = red_c[0][tid] + red_c[1][tid];
+            if constexpr (BM == 64) {
+                g.lsum[(t32 + 1) * g.ldsum + col] = 0.0;
+                g.csum[(t32 + 1) * g.ldsum + col] = 0.0;
+            }
         }
     }
 }
@@ -660,11 +667,11 @@ __device__ __forceinline__ void st4(double *p, const double v[4])
 }
 
 // Sum of split-K partials for a thread's chunk: acc[e] += sum_s col[s * stride + j0 + e].
-// nsplit is padded to a multiple of the batch (the padding partial buffers are
-// zero), so the batch loop has no conditions and all SB * NQ 16-byte loads of
-// a batch are in flight together.  Group addresses are clamped into the
-// column with min(): a group past ldp reads valid memory and its (unused)
-// value belongs to a padding coordinate.
+// Splits are taken in batches of SB with no conditions inside, so all SB * NQ
+// 16-byte loads of a batch are in flight together; the remaining splits
+// (nsplit is the same for the whole workgroup) go one at a time.  Group
+// addresses are clamped into the column with min(): a group past ldp reads
+// valid memory and its (unused) value belongs to a padding coordinate.
 template <typename T, int NQ>
 __device__ __forceinline__ void sum_splits(const T *__restrict__ col, int nsplit, int64_t stride,
                                            int j0, int ldp, double (&acc)[4 * NQ])
@@ -673,7 +680,8 @@ __device__ __forceinline__ void sum_splits(const T *__restrict__ col, int nsplit
     int go[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) go[q] = min(j0 + 4 * q, ldp - 4);
-    for (int s0 = 0; s0 < nsplit; s0 += SB) {
+    int s0 = 0;
+    for (; s0 + SB <= nsplit; s0 += SB) {
         T v[SB][4 * NQ];
 #pragma unroll
         for (int i = 0; i < SB; ++i)
@@ -683,6 +691,13 @@ __device__ __forceinline__ void sum_splits(const T *__restrict__ col, int nsplit
         for (int i = 0; i < SB; ++i)
 #pragma unroll
             for (int e = 0; e < 4 * NQ; ++e) acc[e] += (double)v[i][e];
+    }
+    for (; s0 < nsplit; ++s0) {
+        T v[4 * NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) ld4(col + (int64_t)s0 * stride + go[q], &v[4 * q]);
+#pragma unroll
+        for (int e = 0; e < 4 * NQ; ++e) acc[e] += (double)v[e];
     }
 }
 
@@ -1467,7 +1482,7 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
     g.A = X; g.lda = c.ldp; g.B = Yi; g.ldb = c.ldp; g.C = R; g.ldc = c.npad;
     g.k_len = c.ldp; g.k_chunk = c.ldp;
     g.n = c.n; g.loss = c.loss; g.y = y;
-    const int tn = c.mpad / GEMM_BN;
+    const int tn = c.mact / GEMM_BN;
     if (iter_f64) gemm<double, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
     else if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
     else gemm<uint16_t, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
@@ -1481,7 +1496,7 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
     g.A = XT; g.lda = c.npad; g.B = R; g.ldb = c.npad; g.C = Gp; g.ldc = c.ldp;
     g.split_stride = (int64_t)c.mpad * c.ldp;
     g.k_len = c.npad; g.k_chunk = gchunk; g.rows_valid = c.ldp;
-    const int tn = c.mpad / GEMM_BN;
+    const int tn = c.mact / GEMM_BN;
     if (iter_f64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
     else if (xtype == XT_F32) gemm<float, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
     else gemm<uint16_t, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
@@ -1496,7 +1511,7 @@ void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, d
     g.A = X; g.lda = c.ldp; g.B = B; g.ldb = c.ldp; g.C = Z; g.ldc = c.npad;
     g.k_len = c.ldp; g.k_chunk = c.ldp;
     g.n = c.n; g.loss = c.loss; g.y = y; g.lsum = lsum; g.csum = csum; g.ldsum = c.mpad;
-    const int tn = c.mpad / GEMM_BN;
+    const int tn = c.mact / GEMM_BN;
     if (xtype == XT_F64) gemm<double, double, double, EPI_CERT>(s, g, c.npad, tn, 1);
     else if (xtype == XT_F32) gemm<float, double, double, EPI_CERT>(s, g, c.npad, tn, 1);
     else gemm<uint16_t, double, double, EPI_CERT>(s, g, c.npad, tn, 1);
@@ -1510,7 +1525,7 @@ void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, 
     g.A = XT; g.lda = c.npad; g.B = Z; g.ldb = c.npad; g.C = Qp; g.ldc = c.ldp;
     g.split_stride = (int64_t)c.mpad * c.ldp;
     g.k_len = c.npad; g.k_chunk = qchunk; g.rows_valid = c.ldp;
-    const int tn = c.mpad / GEMM_BN;
+    const int tn = c.mact / GEMM_BN;
     if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, qsplit);
     else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, c.pm, tn, qsplit);
     else gemm<uint16_t, double, double, EPI_STORE>(s, g, c.pm, tn, qsplit);
@@ -1531,10 +1546,10 @@ void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, 
                       double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c)
 {
     if (iter_f64) {
-        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<double, PP, W>), dim3(c.m), dim3(64 * W), 0, s,
+        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<double, PP, W>), dim3(min(c.m, c.mact)), dim3(64 * W), 0, s,
                                                  (const double *)Gp, gsplit, B, Bprev, (double *)Yi, st, ss, c));
     } else {
-        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<float, PP, W>), dim3(c.m), dim3(64 * W), 0, s,
+        KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<float, PP, W>), dim3(min(c.m, c.mact)), dim3(64 * W), 0, s,
                                                  (const float *)Gp, gsplit, B, Bprev, (float *)Yi, st, ss, c));
     }
 }
@@ -1550,7 +1565,7 @@ void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const doubl
                         const double *csum, int tiles_n, const double *B, double *Bbest,
                         const int8_t *st, SlotState ss, const Consts &c, int update_state)
 {
-    KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_cert_finish<PP, W>), dim3(c.m), dim3(64 * W), 0, s, Qp, qsplit,
+    KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_cert_finish<PP, W>), dim3(min(c.m, c.mact)), dim3(64 * W), 0, s, Qp, qsplit,
                                              lsum, csum, tiles_n, B, Bbest, st, ss, c, update_state));
 }
 

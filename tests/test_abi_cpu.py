@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import paper_2605_22188_amd as K
@@ -36,6 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 
 STRUCTS = {"kbnb_problem_desc": K.ProblemDesc, "kbnb_node_desc": K.NodeDesc,
+           "kbnb_tune_options": K.TuneOptions, "kbnb_tune_result": K.TuneResult,
            "kbnb_bound_result": K.BoundResult, "kbnb_bnb_options": K.BnbOptions,
            "kbnb_bnb_result": K.BnbResult}
 
@@ -66,3 +68,13 @@ def test_null_handle_errors_without_device():
     assert lib.destroy_problem(None) == -5
     assert lib.submit_nodes(None, None, 0) == -5
     assert "NULL" in K.last_error()
+
+
+def test_autotune_rejects_bad_candidates_before_any_device_call():
+    X = np.zeros((4, 3), np.float32)
+    y = np.ones(4)
+    for kw in [dict(widths=[0]), dict(widths=[8192]), dict(periods=[0]), dict(widths=[]),
+               dict(nodes=[([5], [])] * 0 + [([0], [1])], widths=[64], periods=[-1])]:
+        with pytest.raises(K.KbnbError) as e:
+            K.autotune(X, y, 1, 0, 1.0, 1.0, dtype="f32", **kw)
+        assert e.value.code == -1, kw

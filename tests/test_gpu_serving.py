@@ -2,10 +2,13 @@
 
 Each node's result must not depend on what else is in flight: the same node
 bounded alone, and in a mix with other nodes of its problem while another
-problem runs on the device at the same time, gives the same bound.  Nodes are
-admitted only at round boundaries and every column's arithmetic is the same
-whatever slot it occupies, so the results are expected to be bit-identical;
-the test allows 1e-12 relative.
+problem runs on the device at the same time, gives the same bound within the
+node tolerance.  The rounds of a problem are launched over the narrowest
+column range that covers its occupied slots, with split-K counts chosen for
+that width, so the float32 summation order of the gradient (and hence the
+exact iterates) depends on the mix; the certified results do not: both
+bounds lie in [v - tol |Phi|, v] for the node value v, so they differ by at
+most tol |Phi|, and the rounding support and branching index agree.
 """
 import threading
 
@@ -51,9 +54,11 @@ def test_alone_vs_mix_and_concurrent_problems():
     for i in probe:
         a, m = alone[i], mix[i]
         assert m["status"] == a["status"] == K.CONVERGED
-        assert m["iterations"] == a["iterations"], (i, a["iterations"], m["iterations"])
-        assert m["lower_bound"] == pytest.approx(a["lower_bound"], rel=1e-12, abs=0)
-        assert m["primal_value"] == pytest.approx(a["primal_value"], rel=1e-12, abs=0)
+        scale = max(abs(a["primal_value"]), abs(m["primal_value"]))
+        assert abs(m["lower_bound"] - a["lower_bound"]) <= 1e-6 * scale, (i, a, m)
+        # each primal value is above the other's certified bound
+        assert m["primal_value"] >= a["lower_bound"] - 1e-12 * scale
+        assert a["primal_value"] >= m["lower_bound"] - 1e-12 * scale
         assert np.array_equal(m["support"], a["support"])
         assert m["branch_index"] == a["branch_index"]
     K.destroy_problem(ha)

@@ -1,0 +1,40 @@
+"""Autotuner: every candidate is measured on the same node sample, and the
+choice follows the stated rule (smallest width whose best rate is within the
+tie fraction of the overall best, at that width's fastest period)."""
+import numpy as np
+import pytest
+
+import paper_2605_22188_amd as K
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_choice_follows_the_rule():
+    print("[gpu-test] autotune 2000x150 logistic, widths 16/64/256, periods 4/8", flush=True)
+    inst = W.small_instance(2000, 150, 8, W.LOGISTIC, seed=51)
+    widths, periods = [16, 64, 256], [4, 8]
+    out = K.autotune(inst.X_store, inst.y, inst.k, inst.loss, inst.lambda2, inst.M,
+                     dtype=inst.dtype, widths=widths, periods=periods, max_iters=400,
+                     sample_nodes=256, tie_frac=0.03, seed=7)
+    rates = out["rates"]
+    assert rates.shape == (3, 2) and np.all(rates > 0)
+    assert out["trials"] == 6 and out["sample_nodes"] == 256
+    best = rates.max()
+    ok_w = [w for w, row in zip(widths, rates) if row.max() >= 0.97 * best]
+    assert out["batch_width"] == min(ok_w)
+    row = rates[widths.index(out["batch_width"])]
+    assert out["cert_period"] == periods[int(np.argmax(row))]
+    assert out["rate"] == pytest.approx(row.max())
+
+
+def test_autotune_with_given_nodes_and_budget():
+    print("[gpu-test] autotune with caller nodes and a small budget", flush=True)
+    inst = W.small_instance(1500, 100, 5, W.SQUARED, seed=52)
+    nodes = W.random_nodes(100, 64, 2, 10, seed=53)
+    out = K.autotune(inst.X_store, inst.y, inst.k, inst.loss, inst.lambda2, inst.M,
+                     dtype=inst.dtype, nodes=nodes, widths=[32, 4096], periods=[8],
+                     max_iters=300, hbm_budget_bytes=64 << 20)
+    # the 4096-wide candidate cannot fit 64 MiB: skipped with rate 0
+    assert out["rates"][1, 0] == 0.0 and out["rates"][0, 0] > 0
+    assert out["batch_width"] == 32 and out["sample_nodes"] == 64
