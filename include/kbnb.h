@@ -59,6 +59,14 @@ extern "C" {
 #define KBNB_DTYPE_F32 1
 #define KBNB_DTYPE_BF16 2 /* uint16 bfloat16 bit patterns */
 
+/* precision of the iteration's products (certificates are float64 always) */
+#define KBNB_ITER_AUTO 0 /* float64 for float64 X or the squared loss, else float32.
+                            With the squared loss the natural dual point zeta = -l'(X beta)
+                            is first-order sensitive to rounding in the iterate, and
+                            float32 iterations can stall near a 1e-6 relative gap. */
+#define KBNB_ITER_F32 1  /* float32 (bfloat16 MFMA for bfloat16 X); needs F32 or BF16 X */
+#define KBNB_ITER_F64 2  /* float64 products on any X */
+
 /* where X and y live */
 #define KBNB_MEM_HOST_COPY 0      /* host arrays, copied at create_problem */
 #define KBNB_MEM_DEVICE_COPY 1    /* device arrays, copied at create_problem */
@@ -87,6 +95,7 @@ typedef struct {
     uint64_t hbm_budget_bytes; /* device-memory budget of this problem; 0 = 8 GiB */
     int32_t batch_width;       /* node slots; 0 = chosen from the budget (max 1024) */
     int32_t cert_period;       /* iterations between float64 certificates; 0 = 8 */
+    int32_t iter_dtype;        /* KBNB_ITER_*: precision of the iteration's products */
 } kbnb_problem_desc;
 
 typedef struct {

@@ -25,6 +25,8 @@ DTYPE_F64, DTYPE_F32, DTYPE_BF16 = 0, 1, 2
 MEM_HOST_COPY, MEM_DEVICE_COPY, MEM_DEVICE_BORROW = 0, 1, 2
 CONVERGED, PRUNED, MAXITER, ERROR = 0, 1, 2, 3
 _DTYPES = {"f64": DTYPE_F64, "f32": DTYPE_F32, "bf16": DTYPE_BF16}
+ITER_AUTO, ITER_F32, ITER_F64 = 0, 1, 2
+_ITERS = {0: ITER_AUTO, "auto": ITER_AUTO, "f32": ITER_F32, "f64": ITER_F64}
 
 
 class KbnbError(RuntimeError):
@@ -39,7 +41,8 @@ class ProblemDesc(ctypes.Structure):
                 ("x_dtype", ctypes.c_int32), ("mem_flags", ctypes.c_int32),
                 ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p),
                 ("hip_stream", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_uint64),
-                ("batch_width", ctypes.c_int32), ("cert_period", ctypes.c_int32)]
+                ("batch_width", ctypes.c_int32), ("cert_period", ctypes.c_int32),
+                ("iter_dtype", ctypes.c_int32)]
 
 
 class NodeDesc(ctypes.Structure):
@@ -150,7 +153,8 @@ class Handle:
                 pass
 
 
-def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hbm_budget_bytes):
+def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hbm_budget_bytes,
+                  iter_dtype=0):
     """Marshal a problem description; returns (desc, arrays to keep alive, mem flag)."""
     xd = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     keep = []
@@ -172,17 +176,19 @@ def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hb
     d = ProblemDesc(n=n, p=p, k=int(k), loss=int(loss), lambda2=float(lambda2), M=float(M),
                     x_dtype=xd, mem_flags=mem, X=xptr, ldx=ldx, y=yptr, hip_stream=None,
                     hbm_budget_bytes=int(hbm_budget_bytes), batch_width=int(batch_width),
-                    cert_period=int(cert_period))
+                    cert_period=int(cert_period),
+                    iter_dtype=_ITERS[iter_dtype] if iter_dtype in _ITERS else int(iter_dtype))
     return d, keep, mem
 
 
 def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_period=0,
-                   hbm_budget_bytes=0):
+                   hbm_budget_bytes=0, iter_dtype=0):
     """X: host array holding the stored entries (float64 / float32 / uint16
-    bfloat16 bits), or a torch CUDA tensor (copied on the device)."""
+    bfloat16 bits), or a torch CUDA tensor (copied on the device).
+    iter_dtype: "auto" (0), "f32" or "f64" (precision of the iteration)."""
     lib = load()
     d, keep, mem = _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period,
-                                 hbm_budget_bytes)
+                                 hbm_budget_bytes, iter_dtype)
     out = ctypes.c_void_p()
     _check(lib.create_problem(ctypes.byref(d), ctypes.byref(out)))
     return Handle(out, d.n, d.p, int(k), keep if mem != MEM_HOST_COPY else [])
@@ -190,11 +196,12 @@ def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_p
 
 def autotune(X, y, k, loss, lambda2, M, dtype="f32", nodes=None, widths=None, periods=None,
              sample_nodes=0, max_iters=0, rel_tol=0.0, time_limit_s=0.0, tie_frac=0.0, seed=0,
-             hbm_budget_bytes=0):
+             hbm_budget_bytes=0, iter_dtype=0):
     """Measure every (batch width, certificate period) candidate on a node
     sample and return the choice plus the table of rates (node bounds/s)."""
     lib = load()
-    d, keep, _ = _problem_desc(X, y, k, loss, lambda2, M, dtype, 0, 0, hbm_budget_bytes)
+    d, keep, _ = _problem_desc(X, y, k, loss, lambda2, M, dtype, 0, 0, hbm_budget_bytes,
+                               iter_dtype)
     w = np.ascontiguousarray(widths if widths is not None else [64, 128, 256, 512, 1024, 2048],
                              dtype=np.int32)
     pr = np.ascontiguousarray(periods if periods is not None else [4, 8, 16], dtype=np.int32)

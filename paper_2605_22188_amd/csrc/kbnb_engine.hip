@@ -688,6 +688,10 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     if (d->ldx < d->p) return fail(KBNB_E_INVALID_ARGUMENT, "ldx=%lld < p", (long long)d->ldx);
     if (d->batch_width < 0 || d->batch_width > 4096) return fail(KBNB_E_INVALID_ARGUMENT, "batch_width out of range");
     if (d->cert_period < 0 || d->cert_period > 1000) return fail(KBNB_E_INVALID_ARGUMENT, "cert_period out of range");
+    if (d->iter_dtype < KBNB_ITER_AUTO || d->iter_dtype > KBNB_ITER_F64)
+        return fail(KBNB_E_INVALID_ARGUMENT, "unknown iter_dtype %d", d->iter_dtype);
+    if (d->iter_dtype == KBNB_ITER_F32 && d->x_dtype == KBNB_DTYPE_F64)
+        return fail(KBNB_E_INVALID_ARGUMENT, "a float32 iteration needs float32 or bfloat16 X");
     int rc = device_ok();
     if (rc) return rc;
     if (d->mem_flags == KBNB_MEM_HOST_COPY) {
@@ -703,7 +707,8 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->n = d->n; P->p = d->p; P->k = d->k; P->loss = d->loss;
     P->lambda2 = d->lambda2; P->M = d->M;
     P->xtype = d->x_dtype;
-    P->iter_f64 = (d->x_dtype == KBNB_DTYPE_F64);
+    P->iter_f64 = (d->x_dtype == KBNB_DTYPE_F64) || (d->iter_dtype == KBNB_ITER_F64) ||
+                  (d->iter_dtype == KBNB_ITER_AUTO && d->loss == KBNB_LOSS_SQUARED);
     P->ti_bytes = P->iter_f64 ? 8 : 4;
     P->ldp = (int)round_up(P->p, 16);
     while (P->pp < P->p) P->pp *= 2;

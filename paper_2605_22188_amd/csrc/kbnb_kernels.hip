@@ -199,6 +199,85 @@ struct GemmArgs {
     int64_t ldsum;
 };
 
+// XCD-aware tile order shared by the contraction kernels: workgroups are
+// dealt round-robin to the 8 XCDs (blockIdx % 8), each with its own L2.
+//  - split-K: every tile of one k-split goes to the same XCD, so both operand
+//    chunks of the split are fetched into one L2 and read there;
+//  - otherwise, with >= 8 row tiles, the column tiles of one row tile go to
+//    the same XCD back to back, so the A row tile is reused from one L2.
+// Returns false for a workgroup past the end of the grid.
+__device__ __forceinline__ bool map_tile(const GemmArgs &g, int &tm, int &tn, int &split)
+{
+    if (g.nsplit > 1) {
+        const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+        const int T = g.tiles_m * g.tiles_n;
+        split = xcd + 8 * (q / T);
+        const int t = q % T;
+        tm = t % g.tiles_m;
+        tn = t / g.tiles_m;
+        return split < g.nsplit;
+    }
+    split = 0;
+    if (g.tiles_m >= 8) {
+        const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+        tn = q % g.tiles_n;
+        tm = (q / g.tiles_n) * 8 + xcd;
+        return tm < g.tiles_m;
+    }
+    tm = blockIdx.x % g.tiles_m;
+    tn = blockIdx.x / g.tiles_m;
+    return true;
+}
+
+// Epilogues EPI_DLOSS and EPI_STORE of a BM x 64 tile whose accumulators
+// acc[i][j][r] hold C at row = row0 + wm*BM/2 + i*16 + lg*4 + r,
+// col = col0 + wn*32 + j*16 + lr (the layout of both the f32 and the bf16
+// 16x16 MFMA, and of the f64 one after the A-row permutation).
+template <typename TC, int MODE, int FI>
+__device__ __forceinline__ void epi_store(const GemmArgs &g, const typename V4<TC>::t (&acc)[FI][2],
+                                          const double (&yv)[FI][4], int row0, int col0, int wm,
+                                          int wn, int lg, int lr, int split)
+{
+    typedef typename V4<TC>::t acc_t;
+    constexpr int BM = FI * 32;
+    if constexpr (MODE == EPI_DLOSS) {
+        TC *C = reinterpret_cast<TC *>(g.C);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = col0 + wn * 32 + j * 16 + lr;
+#pragma unroll
+            for (int i = 0; i < FI; ++i) {
+                const int rb0 = row0 + wm * (BM / 2) + i * 16 + lg * 4;
+                acc_t o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const TC d = dloss_t<TC>(g.loss, acc[i][j][r], (TC)yv[i][r]);
+                    o[r] = (rb0 + r < g.n) ? d : (TC)0;
+                }
+                *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = o;
+            }
+        }
+    } else {
+        TC *C = reinterpret_cast<TC *>(g.C) + (int64_t)split * g.split_stride;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = col0 + wn * 32 + j * 16 + lr;
+#pragma unroll
+            for (int i = 0; i < FI; ++i) {
+                const int rb0 = row0 + wm * (BM / 2) + i * 16 + lg * 4;
+                if (rb0 + 3 < g.rows_valid) {
+                    *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = acc[i][j];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (rb0 + r < g.rows_valid)
+                            C[(int64_t)col * g.ldc + rb0 + r] = acc[i][j][r];
+                }
+            }
+        }
+    }
+}
+
 template <typename TA, typename TB, typename TC, int MODE, int BM>
 __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
 {
@@ -231,32 +310,8 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     // 4 (i % 4) + i / 4 into row slot i makes both layouts "lane group g,
     // register r holds row 4g + r", so one epilogue serves both.
     const int arow = (sizeof(TC) == 8) ? ((lr & 3) * 4 + (lr >> 2)) : lr;
-    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs
-    // (blockIdx % 8), each with its own L2.  The tiles that share an A row
-    // tile (all column tiles of one row tile) go to the same XCD and are
-    // dispatched back to back, so A is fetched into one L2 and reused there.
     int tm, tn, split;
-    if (g.nsplit > 1) {
-        // split-K: every tile of one k-split goes to the same XCD, so both
-        // operand chunks of the split are fetched into one L2 and read there
-        const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
-        const int T = g.tiles_m * g.tiles_n;
-        split = xcd + 8 * (q / T);
-        const int t = q % T;
-        tm = t % g.tiles_m;
-        tn = t / g.tiles_m;
-        if (split >= g.nsplit) return;
-    } else if (g.tiles_m >= 8) {
-        split = 0;
-        const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
-        tn = q % g.tiles_n;
-        tm = (q / g.tiles_n) * 8 + xcd;
-        if (tm >= g.tiles_m) return;
-    } else {
-        split = 0;
-        tm = blockIdx.x % g.tiles_m;
-        tn = blockIdx.x / g.tiles_m;
-    }
+    if (!map_tile(g, tm, tn, split)) return;
     const int row0 = tm * BM, col0 = tn * BN;
     const int kbeg = split * g.k_chunk;
     const int kend = max(kbeg, min(g.k_len, kbeg + g.k_chunk));  // an empty split stores zeros
@@ -375,41 +430,8 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     // ---- epilogue ----------------------------------------------------------
     // acc[i][j][r] holds C at row = row0 + wm*BM/2 + i*16 + lg*4 + r,
     //                        col = col0 + wn*32 + j*16 + lr.
-    if constexpr (MODE == EPI_DLOSS) {
-        TC *C = reinterpret_cast<TC *>(g.C);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = col0 + wn * 32 + j * 16 + lr;
-#pragma unroll
-            for (int i = 0; i < FI; ++i) {
-                const int rb0 = row0 + wm * (BM / 2) + i * 16 + lg * 4;
-                acc_t o;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const TC d = dloss_t<TC>(g.loss, acc[i][j][r], (TC)yv[i][r]);
-                    o[r] = (rb0 + r < g.n) ? d : (TC)0;
-                }
-                *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = o;
-            }
-        }
-    } else if constexpr (MODE == EPI_STORE) {
-        TC *C = reinterpret_cast<TC *>(g.C) + (int64_t)split * g.split_stride;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = col0 + wn * 32 + j * 16 + lr;
-#pragma unroll
-            for (int i = 0; i < FI; ++i) {
-                const int rb0 = row0 + wm * (BM / 2) + i * 16 + lg * 4;
-                if (rb0 + 3 < g.rows_valid) {
-                    *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = acc[i][j];
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (rb0 + r < g.rows_valid)
-                            C[(int64_t)col * g.ldc + rb0 + r] = acc[i][j][r];
-                }
-            }
-        }
+    if constexpr (MODE != EPI_CERT) {
+        epi_store<TC, MODE, FI>(g, acc, yv, row0, col0, wm, wn, lg, lr, split);
     } else {  // EPI_CERT (TC is double)
         double *C = reinterpret_cast<double *>(g.C);
         __shared__ double red_l[2][64];
@@ -458,6 +480,170 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// bfloat16 MFMA contraction for bfloat16-stored X in the float32 iteration:
+// C[col][row] = sum_k A[row][k] * Bm[col][k], A bfloat16 (exact instance
+// values), Bm float32.  Each Bm value b is split into three bfloat16 terms,
+// hi = bf16(b), mid = bf16(b - hi), lo = bf16(b - hi - mid) (round to nearest
+// even; both differences are exact in float32), so hi + mid + lo carries
+// b's 24-bit significand up to the last bit and three 16x16x32 bf16 MFMAs
+// into a float32 accumulator give float32-level accuracy at about 5x the
+// float32 MFMA rate.  Tile BM x 64, k stage 64 (two MFMA k-steps of 32);
+// lane l holds A row l % 16 / Bm column l % 16 at k = 8 (l / 16) .. + 7,
+// one 16-byte LDS read per operand.  Epilogues EPI_DLOSS / EPI_STORE.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+// b -> three bfloat16 bit patterns (hi, mid, lo) with hi + mid + lo ~= b
+__device__ __forceinline__ void split3(float b, uint16_t &h, uint16_t &m, uint16_t &l)
+{
+    const uint32_t hb = bf16_rne_bits(b);
+    const float r1 = b - __uint_as_float(hb << 16);
+    const uint32_t mb = bf16_rne_bits(r1);
+    const float r2 = r1 - __uint_as_float(mb << 16);
+    h = (uint16_t)hb;
+    m = (uint16_t)mb;
+    l = (uint16_t)bf16_rne_bits(r2);
+}
+
+template <int MODE, int BM>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
+{
+    constexpr int BN = GEMM_BN;
+    constexpr int FI = BM / 32;
+    constexpr int BK = 64;
+    constexpr int LS = BK + 8;              // LDS row stride (bf16 elements, 144 bytes)
+    constexpr int LPA = (BM * BK / 8) / 256;  // 8-element A groups per thread per stage
+    constexpr int LPB = (BN * BK / 4) / 256;  // 4-element Bm groups per thread per stage
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LS];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][3][BN * LS];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lg = lane >> 4;
+    int tm, tn, split;
+    if (!map_tile(g, tm, tn, split)) return;
+    const int row0 = tm * BM, col0 = tn * BN;
+    const int kbeg = split * g.k_chunk;
+    const int kend = max(kbeg, min(g.k_len, kbeg + g.k_chunk));
+    if (g.col_status) {
+        const int run = (tid < BN) ? (g.col_status[col0 + tid] == SLOT_RUNNING) : 0;
+        if (!__syncthreads_or(run)) return;
+    }
+    const uint16_t *A = reinterpret_cast<const uint16_t *>(g.A);
+    const float *Bg = reinterpret_cast<const float *>(g.B);
+
+    f32x4 acc[FI][2];
+#pragma unroll
+    for (int i = 0; i < FI; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    double yv[FI][4];
+    if constexpr (MODE == EPI_DLOSS) {
+#pragma unroll
+        for (int i = 0; i < FI; ++i) ld4(g.y + row0 + wm * (BM / 2) + i * 16 + lg * 4, yv[i]);
+    }
+
+    // staging registers; a group at or past kend re-reads k = kbeg (valid
+    // memory) and is zeroed at the LDS store
+    uint4 ra[LPA];
+    float4 rb[LPB];
+    bool rka[LPA], rkb[LPB];
+    auto load_stage = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < LPA; ++v) {
+            const int x = tid + 256 * v;
+            const int r = x / (BK / 8), kq = 8 * (x % (BK / 8));
+            rka[v] = k0 + kq < kend;
+            ra[v] = *reinterpret_cast<const uint4 *>(A + (int64_t)(row0 + r) * g.lda + (rka[v] ? k0 + kq : kbeg));
+        }
+#pragma unroll
+        for (int v = 0; v < LPB; ++v) {
+            const int x = tid + 256 * v;
+            const int r = x / (BK / 4), kq = 4 * (x % (BK / 4));
+            rkb[v] = k0 + kq < kend;
+            rb[v] = *reinterpret_cast<const float4 *>(Bg + (int64_t)(col0 + r) * g.ldb + (rkb[v] ? k0 + kq : kbeg));
+        }
+    };
+    auto store_stage = [&](int bufi) {
+#pragma unroll
+        for (int v = 0; v < LPA; ++v) {
+            const int x = tid + 256 * v;
+            const int r = x / (BK / 8), kq = 8 * (x % (BK / 8));
+            *reinterpret_cast<uint4 *>(&As[bufi][r * LS + kq]) = rka[v] ? ra[v] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < LPB; ++v) {
+            const int x = tid + 256 * v;
+            const int r = x / (BK / 4), kq = 4 * (x % (BK / 4));
+            const float bv[4] = {rb[v].x, rb[v].y, rb[v].z, rb[v].w};
+            uint16_t h[4], m[4], l[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                split3(rkb[v] ? bv[e] : 0.0f, h[e], m[e], l[e]);
+            }
+            const int o = r * LS + kq;
+            *reinterpret_cast<uint2 *>(&Bs[bufi][0][o]) =
+                make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+            *reinterpret_cast<uint2 *>(&Bs[bufi][1][o]) =
+                make_uint2(m[0] | ((uint32_t)m[1] << 16), m[2] | ((uint32_t)m[3] << 16));
+            *reinterpret_cast<uint2 *>(&Bs[bufi][2][o]) =
+                make_uint2(l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16));
+        }
+    };
+    // MFMA k-step h (k = 32 h .. 32 h + 31 of the stage)
+    auto compute = [&](int bi, int h) {
+        bf16x8 av[FI], bv[3][2];
+#pragma unroll
+        for (int f = 0; f < FI; ++f)
+            av[f] = *reinterpret_cast<const bf16x8 *>(&As[bi][(wm * (BM / 2) + f * 16 + lr) * LS + 32 * h + 8 * lg]);
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+                bv[t][f] = *reinterpret_cast<const bf16x8 *>(&Bs[bi][t][(wn * 32 + f * 16 + lr) * LS + 32 * h + 8 * lg]);
+#pragma unroll
+        for (int t = 2; t >= 0; --t)  // small terms first
+#pragma unroll
+            for (int i = 0; i < FI; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[t][j], acc[i][j], 0, 0, 0);
+    };
+
+    // full stages, then a partial last stage of 1 or 2 k-steps (a k-step
+    // whose second half lies past kend reads zeros there)
+    const int nfull = (kend - kbeg) / BK;
+    const int ntail = (((kend - kbeg) % BK) + 31) / 32;
+    const int nstage = nfull + (ntail > 0 ? 1 : 0);
+    if (nstage > 0) {
+        load_stage(kbeg);
+        store_stage(0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int st = 0; st < nstage; ++st) {
+        const bool more = st + 1 < nstage;
+        if (more) load_stage(kbeg + (st + 1) * BK);
+        if (st < nfull) {
+            compute(buf, 0);
+            compute(buf, 1);
+        } else {
+            for (int h = 0; h < ntail; ++h) compute(buf, h);
+        }
+        if (more) store_stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    epi_store<float, MODE, FI>(g, acc, yv, row0, col0, wm, wn, lg, lr, split);
 }
 
 // ---------------------------------------------------------------------------
@@ -1474,6 +1660,23 @@ static void gemm(hipStream_t s, GemmArgs g, int rows, int tiles_n, int splits)
     else KBNB_LAUNCH((k_gemm_tn<TA, TB, TC, MODE, 64>), grid, dim3(256), 0, s, g);
 }
 
+template <int MODE>
+static void gemm_bf16(hipStream_t s, GemmArgs g, int rows, int tiles_n, int splits)
+{
+    g.tiles_n = tiles_n;
+    g.nsplit = splits;
+    const bool small = (int64_t)(rows / 64) * tiles_n * splits < 512;
+    const int bm = small ? 32 : 64;
+    g.tiles_m = rows / bm;
+    int nblocks;
+    if (splits > 1) nblocks = 8 * g.tiles_m * tiles_n * ((splits + 7) / 8);
+    else if (g.tiles_m >= 8) nblocks = (g.tiles_m + 7) / 8 * 8 * tiles_n;
+    else nblocks = g.tiles_m * tiles_n;
+    dim3 grid(nblocks, 1);
+    if (small) KBNB_LAUNCH((k_gemm_bf16<MODE, 32>), grid, dim3(256), 0, s, g);
+    else KBNB_LAUNCH((k_gemm_bf16<MODE, 64>), grid, dim3(256), 0, s, g);
+}
+
 void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
                       void *R, const double *y, const Consts &c, const int32_t *status)
 {
@@ -1483,9 +1686,12 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
     g.k_len = c.ldp; g.k_chunk = c.ldp;
     g.n = c.n; g.loss = c.loss; g.y = y;
     const int tn = c.mact / GEMM_BN;
-    if (iter_f64) gemm<double, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
-    else if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
-    else gemm<uint16_t, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
+    if (iter_f64) {
+        if (xtype == XT_F64) gemm<double, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
+        else if (xtype == XT_F32) gemm<float, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
+        else gemm<uint16_t, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
+    } else if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
+    else gemm_bf16<EPI_DLOSS>(s, g, c.npad, tn, 1);
 }
 
 void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
@@ -1497,9 +1703,12 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
     g.split_stride = (int64_t)c.mpad * c.ldp;
     g.k_len = c.npad; g.k_chunk = gchunk; g.rows_valid = c.ldp;
     const int tn = c.mact / GEMM_BN;
-    if (iter_f64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
-    else if (xtype == XT_F32) gemm<float, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
-    else gemm<uint16_t, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
+    if (iter_f64) {
+        if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
+        else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
+        else gemm<uint16_t, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
+    } else if (xtype == XT_F32) gemm<float, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
+    else gemm_bf16<EPI_STORE>(s, g, c.pm, tn, gsplit);
 }
 
 void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,

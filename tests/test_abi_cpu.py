@@ -78,3 +78,16 @@ def test_autotune_rejects_bad_candidates_before_any_device_call():
         with pytest.raises(K.KbnbError) as e:
             K.autotune(X, y, 1, 0, 1.0, 1.0, dtype="f32", **kw)
         assert e.value.code == -1, kw
+
+
+def test_header_constants_match_binding():
+    text = open(os.path.join(ROOT, "include", "kbnb.h")).read()
+    defs = dict((m.group(1), int(m.group(2))) for m in
+                re.finditer(r"#define KBNB_(\w+) \(?(-?\d+)\)?", text))
+    pairs = {"OK": "OK", "TIMEOUT": "TIMEOUT", "CONVERGED": "CONVERGED", "PRUNED": "PRUNED",
+             "MAXITER": "MAXITER", "DTYPE_F64": "DTYPE_F64", "DTYPE_F32": "DTYPE_F32",
+             "DTYPE_BF16": "DTYPE_BF16", "ITER_AUTO": "ITER_AUTO", "ITER_F32": "ITER_F32",
+             "ITER_F64": "ITER_F64", "MEM_HOST_COPY": "MEM_HOST_COPY",
+             "MEM_DEVICE_COPY": "MEM_DEVICE_COPY"}
+    for hname, pname in pairs.items():
+        assert defs[hname] == getattr(K, pname), hname

@@ -136,8 +136,9 @@ def test_certify_batch_wide_nodes(n, p, k, loss):
     _certify_case(W.small_instance(n, p, k, loss, seed=p, lambda2=1.0), 24, 13)
 
 
-def _bound_parity(inst, nodes, batch_width, cert_period, warm=None, sample=None):
-    h = K.create_from_instance(inst, batch_width=batch_width, cert_period=cert_period)
+def _bound_parity(inst, nodes, batch_width, cert_period, warm=None, sample=None, iter_dtype=0):
+    h = K.create_from_instance(inst, batch_width=batch_width, cert_period=cert_period,
+                               iter_dtype=iter_dtype)
     P = oracle.Problem.from_instance(inst)
     res = K.bound_nodes(h, nodes, rel_tol=1e-6, warm_starts=warm)
     idx = range(len(nodes)) if sample is None else sample
@@ -157,12 +158,19 @@ def _bound_parity(inst, nodes, batch_width, cert_period, warm=None, sample=None)
     return res
 
 
-@pytest.mark.parametrize("loss", [W.SQUARED, W.LOGISTIC])
-def test_node_bounds_small_all_nodes(loss):
-    announce(f"node bounds 700x50 loss={loss}, 100 nodes on 64 slots")
-    inst = W.small_instance(700, 50, 6, loss, seed=5 + loss, rho=0.6)
+@pytest.mark.parametrize("loss,dtype,it", [(W.SQUARED, "f64", 0), (W.LOGISTIC, "f64", 0),
+                                            (W.SQUARED, "f32", 0), (W.LOGISTIC, "f32", 0),
+                                            (W.SQUARED, "bf16", 0), (W.LOGISTIC, "bf16", 0),
+                                            (W.LOGISTIC, "f32", "f64")])
+def test_node_bounds_small_all_nodes(loss, dtype, it):
+    """Iteration precision "auto" (0): float64 for the squared loss on any X,
+    float32 for the logistic loss on float32 / bfloat16 X (bfloat16 X: the
+    products run on bfloat16 MFMA with a three-term split of the float32
+    operand).  "f64": float64 iteration forced on float32 X."""
+    announce(f"node bounds 700x50 loss={loss} X {dtype} iteration {it}, 100 nodes on 64 slots")
+    inst = W.small_instance(700, 50, 6, loss, seed=5 + loss, rho=0.6, dtype=dtype)
     nodes = W.random_nodes(50, 100, 3, 15, seed=77)
-    _bound_parity(inst, nodes, batch_width=64, cert_period=4)
+    _bound_parity(inst, nodes, batch_width=64, cert_period=4, iter_dtype=it)
 
 
 def test_node_bounds_logistic_5000x200_launch():
@@ -242,8 +250,9 @@ def test_bnb_plain_squared_500x30_on_gpu():
     K.destroy_problem(h)
 
 
-@pytest.mark.parametrize("n,p,k,loss", [(1500, 3000, 10, W.LOGISTIC), (2500, 5000, 15, W.SQUARED)])
-def test_node_bounds_wide_nodes(n, p, k, loss):
+@pytest.mark.parametrize("n,p,k,loss,dtype,it", [(1500, 3000, 10, W.LOGISTIC, "bf16", 0),
+                                                  (2500, 5000, 15, W.SQUARED, "bf16", 0)])
+def test_node_bounds_wide_nodes(n, p, k, loss, dtype, it):
     """Node bounds at p above 2048, checked by the duality bracket the oracle
     evaluates at the returned iterate: the certified bound LB must satisfy
     LB <= Phi_oracle(beta) (validity, up to 1e-12 rounding) and
@@ -251,11 +260,11 @@ def test_node_bounds_wide_nodes(n, p, k, loss):
     tolerance of the node value, which lies in between).  The oracle's own
     solve to 1e-10 is too slow at these sizes; its certificate arithmetic at
     the same sizes is compared element by element in the certify_batch test."""
-    announce(f"node bounds {n}x{p} k={k} loss={loss}")
-    inst = W.small_instance(n, p, k, loss, seed=p + 1, lambda2=1.0)
+    announce(f"node bounds {n}x{p} k={k} loss={loss} X {dtype} iteration {it}")
+    inst = W.small_instance(n, p, k, loss, seed=p + 1, lambda2=1.0, dtype=dtype)
     P = oracle.Problem.from_instance(inst)
     nodes = W.random_nodes(p, 12, k // 2, p // 10, seed=p + 2)
-    h = K.create_from_instance(inst, batch_width=8, cert_period=8)
+    h = K.create_from_instance(inst, batch_width=8, cert_period=8, iter_dtype=it)
     res = K.bound_nodes(h, nodes, rel_tol=1e-6)
     for i, (nd, g) in enumerate(zip(nodes, res)):
         st = W.node_state(p, nd)
