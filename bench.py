@@ -112,10 +112,75 @@ def bnb_leg(K, W, torch, args):
                                    f"max {args.tune_iters} iterations each"}}
 
 
-def _make_mix_instance(q):
+def _draw(kind, q=None):
+    """Draw an instance; returns only what the device needs (the stored X,
+    y and the scalars)."""
     import workloads as W
-    return W.make_instance(q["name"], q["n"], q["p"], q["rho"], q["k"], q["loss"], q["lambda2"],
-                           q["M"], q["dtype"], q["seed"])
+    if kind == "mix":
+        inst = W.make_instance(q["name"], q["n"], q["p"], q["rho"], q["k"], q["loss"],
+                               q["lambda2"], q["M"], q["dtype"], q["seed"])
+    else:
+        inst = W.large_logistic_100000x5000_bf16()
+    return dict(X_store=inst.X_store, y=inst.y, k=inst.k, loss=inst.loss, lambda2=inst.lambda2,
+                M=inst.M, dtype=inst.dtype, n=inst.n, p=inst.p)
+
+
+def large_leg(K, W, torch, args):
+    """Node bounds on the 100000 x 5000 bfloat16 logistic workload (rho 0.7,
+    k 15, |beta*_j| ~ U[0.5, 2], lambda2 1, M 4): one batch of nodes with
+    |J1| ~ U{0..7}, |J0| ~ U{0..500}, through the bfloat16 MFMA path."""
+    t = time.perf_counter()
+    log("large: drawing the 100000 x 5000 instance")
+    d = _draw("large")
+    log(f"large: drawn in {time.perf_counter() - t:.1f}s")
+    X = torch.from_numpy(d["X_store"]).cuda()
+    y = torch.from_numpy(d["y"]).cuda()
+    del d["X_store"]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    h = K.create_problem(X, y, d["k"], d["loss"], d["lambda2"], d["M"], dtype=d["dtype"],
+                         batch_width=args.large_batch, cert_period=16)
+    t_setup = time.perf_counter() - t
+    log(f"large: problem ready in {t_setup:.1f}s: {K.problem_info(h)}")
+    del X, y
+    nodes = W.random_nodes(d["p"], args.large_batch + 72, 7, 500, seed=3000)
+    K.bound_nodes(h, nodes[:8], rel_tol=1e-6)
+    torch.cuda.synchronize()
+    log("large: warm-up done")
+    t = time.perf_counter()
+    res = K.bound_nodes(h, nodes[8:8 + args.large_batch], rel_tol=1e-6)
+    dt = time.perf_counter() - t
+    rate = len(res) / dt
+    log(f"large: timed batch done in {dt:.2f}s")
+    # kernel-timed pass on 64 further nodes
+    K.kernel_stats(h, 1)
+    K.bound_nodes(h, nodes[8 + args.large_batch:], rel_tol=1e-6)
+    ks = K.kernel_stats(h, 0)
+    K.destroy_problem(h)
+    n = d["n"]
+    iters = [r["iterations"] for r in res]
+    useful = ks["useful_cols"] / max(1, ks["launches"]["fwd_xy"])
+    kern = {}
+    for name in ("fwd_xy", "bwd_xtr", "prox", "cert_xb", "cert_xtz", "cert_finish"):
+        nl = ks["launches"][name]
+        if nl:
+            us = ks["total_ms"][name] / nl * 1e3
+            kern[name] = {"avg_us": round(us, 2), "launches": int(nl)}
+            if name in ("fwd_xy", "bwd_xtr", "cert_xb", "cert_xtz"):
+                tf = 2.0 * n * useful / (us * 1e-6) / 1e12
+                pk = PEAK_TFLOPS["bf16"] if name in ("fwd_xy", "bwd_xtr") else PEAK_TFLOPS["f64"]
+                kern[name]["alg_tflops"] = round(tf, 2)
+                kern[name]["frac_of_peak"] = round(tf / pk, 4)
+    log(f"large: {len(res)} nodes in {dt:.2f}s -> {rate:.1f} node bounds/s; kernels {kern}")
+    return {"workload": "logistic_100000x5000_bf16_rho0.7_k15", "value": round(rate, 2),
+            "unit": "node bounds/s", "nodes": len(res), "batch_width": args.large_batch,
+            "seconds": round(dt, 3), "setup_s": round(t_setup, 2),
+            "iterations": {"mean": round(float(np.mean(iters)), 1), "max": int(np.max(iters))},
+            "not_converged": int(sum(r["status"] != K.CONVERGED for r in res)),
+            "max_rel_gap": float(max(r["rel_gap"] for r in res)),
+            "iteration_products": "bfloat16 MFMA (three-term split of the float32 operand) of "
+                                  "the change since each node's last float64 certificate",
+            "kernels": kern}
 
 
 def serving_leg(K, W, torch, args):
@@ -127,12 +192,13 @@ def serving_leg(K, W, torch, args):
     saturated rate, and each request's latency is the time from its arrival
     to its result at poll."""
     import threading
-    from concurrent.futures import ProcessPoolExecutor
-    specs = W.serving_mix_problems(32)
+    from types import SimpleNamespace
     t = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=8) as ex:
-        insts = list(ex.map(_make_mix_instance, specs))
-    log(f"serving: 32 instances drawn in {time.perf_counter() - t:.1f}s")
+    insts = []
+    for i, q in enumerate(W.serving_mix_problems(32)):
+        insts.append(SimpleNamespace(**_draw("mix", q)))
+        if i % 8 == 7:
+            log(f"serving: {i + 1} instances drawn ({time.perf_counter() - t:.1f}s)")
     handles = []
     for inst in insts:
         X = torch.from_numpy(inst.X_store).cuda()
@@ -141,6 +207,7 @@ def serving_leg(K, W, torch, args):
                                         dtype=inst.dtype, hbm_budget_bytes=2 << 30,
                                         cert_period=8))
         del X, y
+        inst.X_store = None
     torch.cuda.synchronize()
     widths = [K.problem_info(h)["batch_width"] for h in handles]
     rng = np.random.Generator(np.random.PCG64(777))
@@ -244,6 +311,9 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.5)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--serve-iters", type=int, default=2000)
+    ap.add_argument("--large", type=int, default=1,
+                    help="run the 100000 x 5000 bfloat16 logistic node-bound leg")
+    ap.add_argument("--large-batch", type=int, default=256)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -389,6 +459,7 @@ def main():
 
     ttz = bnb_leg(K, W, torch, args) if args.bnb else None
     serving = serving_leg(K, W, torch, args) if args.serving else None
+    large = large_leg(K, W, torch, args) if args.large else None
 
     lat_ms = np.array(lat_all) * 1e3
     out = {
@@ -422,6 +493,7 @@ def main():
         "comparator": comparator,
         "time_to_zero_gap": ttz,
         "serving": serving,
+        "large_logistic": large,
         "setup_s": round(t_setup, 3),
     }
     K.destroy_problem(h)

@@ -60,12 +60,18 @@ extern "C" {
 #define KBNB_DTYPE_BF16 2 /* uint16 bfloat16 bit patterns */
 
 /* precision of the iteration's products (certificates are float64 always) */
-#define KBNB_ITER_AUTO 0 /* float64 for float64 X or the squared loss, else float32.
-                            With the squared loss the natural dual point zeta = -l'(X beta)
-                            is first-order sensitive to rounding in the iterate, and
-                            float32 iterations can stall near a 1e-6 relative gap. */
+#define KBNB_ITER_AUTO 0 /* F64 for float64 X or the squared loss; else ANCHORED when
+                            n > 10000, F32 otherwise.  Plain float32 iterations can stall
+                            near a 1e-6 relative gap: with the squared loss the natural
+                            dual point zeta = -l'(X beta) is first-order sensitive to
+                            rounding in the iterate, and float32 gradient sums over many
+                            rows lose the accuracy the gap needs. */
 #define KBNB_ITER_F32 1  /* float32 (bfloat16 MFMA for bfloat16 X); needs F32 or BF16 X */
 #define KBNB_ITER_F64 2  /* float64 products on any X */
+#define KBNB_ITER_ANCHORED 3 /* float32 (bfloat16 MFMA for bfloat16 X) products of the change
+                                since the node's last certificate, added to that certificate's
+                                float64 gradient: rounding shrinks as the iterate settles, so
+                                the iteration reaches float64-level gaps; needs F32 or BF16 X */
 
 /* where X and y live */
 #define KBNB_MEM_HOST_COPY 0      /* host arrays, copied at create_problem */
@@ -273,8 +279,10 @@ int certify_batch(kbnb_problem *prob, int32_t m, const int8_t *states,
                   const double *betas, double *phi, double *psi,
                   int32_t *supports, int32_t *branch);
 
-/* Problem facts: p_out[0..5] = n, p, k, batch width, cert period, loss;
- * d_out[0..3] = smoothness constant L, lambda2, M, device bytes in use. */
+/* Problem facts: i_out[0..8] = n, p, k, batch width, cert period, loss,
+ * split-K count at full width, engine rounds so far, iteration precision
+ * (KBNB_ITER_F32 / F64 / ANCHORED as resolved); d_out[0..3] = smoothness
+ * constant L, lambda2, M, device bytes in use. */
 int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
 
 /*

@@ -25,8 +25,9 @@ DTYPE_F64, DTYPE_F32, DTYPE_BF16 = 0, 1, 2
 MEM_HOST_COPY, MEM_DEVICE_COPY, MEM_DEVICE_BORROW = 0, 1, 2
 CONVERGED, PRUNED, MAXITER, ERROR = 0, 1, 2, 3
 _DTYPES = {"f64": DTYPE_F64, "f32": DTYPE_F32, "bf16": DTYPE_BF16}
-ITER_AUTO, ITER_F32, ITER_F64 = 0, 1, 2
-_ITERS = {0: ITER_AUTO, "auto": ITER_AUTO, "f32": ITER_F32, "f64": ITER_F64}
+ITER_AUTO, ITER_F32, ITER_F64, ITER_ANCHORED = 0, 1, 2, 3
+_ITERS = {0: ITER_AUTO, "auto": ITER_AUTO, "f32": ITER_F32, "f64": ITER_F64,
+          "anchored": ITER_ANCHORED}
 
 
 class KbnbError(RuntimeError):
@@ -337,11 +338,12 @@ def certify_batch(h: Handle, states, betas):
 
 
 def problem_info(h: Handle):
-    i = np.zeros(8, np.int64)
+    i = np.zeros(9, np.int64)
     d = np.zeros(4)
     _check(load().problem_info(h.ptr, _p(i), _p(d)))
     return dict(n=int(i[0]), p=int(i[1]), k=int(i[2]), batch_width=int(i[3]),
                 cert_period=int(i[4]), loss=int(i[5]), gsplit=int(i[6]), rounds=int(i[7]),
+                iteration={1: "f32", 2: "f64", 3: "anchored"}.get(int(i[8]), "?"),
                 L=float(d[0]), lambda2=float(d[1]), M=float(d[2]), device_bytes=float(d[3]))
 
 

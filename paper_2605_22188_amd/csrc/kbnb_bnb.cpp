@@ -71,7 +71,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");
     if (!opt || !res || !res->support)
         return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "options, result and result->support are required");
-    int64_t info[8];
+    int64_t info[9];
     double dinfo[4];
     int rc = problem_info(P, info, dinfo);
     if (rc) return rc;

@@ -127,6 +127,8 @@ struct kbnb_problem {
     double *y = nullptr, *B = nullptr, *Bprev = nullptr, *Z = nullptr, *Qp = nullptr;
     double *lsum = nullptr, *csum = nullptr, *gbuf = nullptr;
     double *Bbest = nullptr;   // iterate of the best certified primal value [mpad][ldp]
+    bool anchored = false;     // anchored float32 iteration
+    Anchor an{};               // its buffers (all NULL when off)
     int8_t *st = nullptr;
     uint8_t *stage_d = nullptr;
     int32_t *gslots_d = nullptr;
@@ -198,17 +200,20 @@ static size_t per_slot_bytes(const kbnb_problem *P)
     b += (size_t)P->tiles_n * 16;                      // lsum, csum
     b += (size_t)P->ldp * 8 + 128 + P->k * 4;          // gather buffer, scalars, support
     b += (size_t)P->pp * 4;                            // sort permutation
+    if (P->anchored) b += (size_t)P->npad * 8 + (size_t)P->ldp * 16;  // S_c, beta_c, grad F(beta_c)
     return b;
 }
 
 // Split-K for a launch covering `mact` columns: enough workgroups to cover
-// the 256 CUs a few times, at most 32 splits (the per-node kernels add the
+// the 256 CUs a few times and no split deeper than 4096 rows (a workgroup
+// walks its split serially), at most 32 splits (the per-node kernels add the
 // partials, exactly the splits the same round's launch wrote).
 static void splits_for(const kbnb_problem *P, int mact, Variant &v)
 {
     const int tiles = (P->pm / GEMM_BM) * (mact / GEMM_BN);
     const int kt = P->npad / GEMM_BK;  // 16-wide k chunks
     int want = std::max(1, (256 + tiles - 1) / tiles);
+    want = std::max(want, (P->npad + 4095) / 4096);
     want = std::min(want, std::max(1, kt / 4));
     want = std::min(want, 32);
     const int chunk = (int)round_up((P->npad + want - 1) / want, GEMM_BK);
@@ -262,6 +267,10 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         mp * P->k * 4,                           // supports
         mp * P->ldp * 8,                         // Bbest
         mp * (size_t)P->pp * 4,                  // sort permutations
+        P->anchored ? mp * P->npad * 8 : 0,      // anchor S_c
+        P->anchored ? mp * P->ldp * 8 : 0,       // anchor beta_c
+        P->anchored ? mp * P->ldp * 8 : 0,       // anchor grad F(beta_c)
+        P->anchored ? (size_t)P->ldp * 8 : 0,    // grad F(0)
     };
     const int nitems = sizeof(sizes) / sizeof(sizes[0]);
     size_t off[32];
@@ -319,6 +328,12 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
     P->ss.sup = (int32_t *)(base + off[18]);
     P->Bbest = (double *)(base + off[19]);
     P->ss.perm = (int32_t *)(base + off[20]);
+    if (P->anchored) {
+        P->an.sc = (double *)(base + off[21]);
+        P->an.bc = (double *)(base + off[22]);
+        P->an.gc = (double *)(base + off[23]);
+        P->an.g0 = (const double *)(base + off[24]);
+    }
     P->slot_dev = base + off[16];
     P->slot_bytes = off[18] + sizes[18] - off[16];
     return 0;
@@ -339,13 +354,14 @@ static void enqueue_round(kbnb_problem *P, const Variant &v)
     hipStream_t s = P->stream;
     const Consts c = consts_for(P, v);
     for (int it = 0; it < P->cert_period; ++it) {
-        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, c, P->ss.status);
+        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, c, P->ss.status, P->an);
         launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, v.gsplit, v.gchunk, c, P->ss.status);
-        launch_prox_iter(s, P->iter_f64, P->Gp, v.gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, c);
+        launch_prox_iter(s, P->iter_f64, P->Gp, v.gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, c, P->an);
     }
-    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, c, P->ss.status);
+    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, c, P->ss.status, P->an.sc);
     launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, v.qsplit, v.qchunk, c, P->ss.status);
-    launch_cert_finish(s, P->Qp, v.qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, c, 1);
+    launch_cert_finish(s, P->Qp, v.qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, c, 1,
+                       P->an, P->Bprev, (float *)P->Yi);
 }
 
 // Kernel types for the timing instrumentation.
@@ -374,18 +390,19 @@ static int enqueue_round_timed(kbnb_problem *P, const Variant &v, std::vector<in
     };
     for (int it = 0; it < P->cert_period; ++it) {
         timed(KT_FWD);
-        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, c, P->ss.status);
+        launch_fwd_dloss(s, P->xtype, P->iter_f64, P->X, P->Yi, P->R, P->y, c, P->ss.status, P->an);
         timed(KT_BWD);
         launch_bwd(s, P->xtype, P->iter_f64, P->XT, P->R, P->Gp, v.gsplit, v.gchunk, c, P->ss.status);
         timed(KT_PROX);
-        launch_prox_iter(s, P->iter_f64, P->Gp, v.gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, c);
+        launch_prox_iter(s, P->iter_f64, P->Gp, v.gsplit, P->B, P->Bprev, P->Yi, P->st, P->ss, c, P->an);
     }
     timed(KT_CFWD);
-    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, c, P->ss.status);
+    launch_cert_fwd(s, P->xtype, P->X, P->B, P->Z, P->y, P->lsum, P->csum, c, P->ss.status, P->an.sc);
     timed(KT_CBWD);
     launch_cert_bwd(s, P->xtype, P->XT, P->Z, P->Qp, v.qsplit, v.qchunk, c, P->ss.status);
     timed(KT_CFIN);
-    launch_cert_finish(s, P->Qp, v.qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, c, 1);
+    launch_cert_finish(s, P->Qp, v.qsplit, P->lsum, P->csum, P->tiles_n, P->B, P->Bbest, P->st, P->ss, c, 1,
+                       P->an, P->Bprev, (float *)P->Yi);
     g_ktime = KernelTiming{};
     HIP_TRY(hipGetLastError());
     return 0;
@@ -489,7 +506,7 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
     do {
         if (nadm) {
             HIP_TRY(hipMemcpyAsync(P->stage_d, P->stage_h, (size_t)nadm * P->rec_bytes, hipMemcpyHostToDevice, s));
-            launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Bbest, P->Yi, P->st, P->ss, P->c);
+            launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Bbest, P->Yi, P->st, P->ss, P->c, P->an);
         }
         std::vector<int> kinds;
         const bool timed = P->timing;
@@ -629,6 +646,25 @@ static int estimate_L(kbnb_problem *P)
     return 0;
 }
 
+// grad F(0) = X^T l'(0, y) in float64: the anchor gradient of every newly
+// admitted node of an anchored problem (l'(0, y) = -2 y squared, -y / 2 logistic)
+static int anchor_grad0(kbnb_problem *P)
+{
+    std::vector<double> yh(P->n), v(P->npad, 0.0);
+    HIP_TRY(hipMemcpy(yh.data(), P->y, sizeof(double) * P->n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < P->n; ++i) v[i] = (P->loss == KBNB_LOSS_SQUARED) ? -2.0 * yh[i] : -0.5 * yh[i];
+    double *dv = nullptr;
+    HIP_TRY(hipMalloc(&dv, sizeof(double) * P->npad));
+    hipError_t e = hipMemcpy(dv, v.data(), sizeof(double) * P->npad, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        launch_matvec_f64(P->stream, P->xtype, P->XT, P->npad, P->p, P->n, dv, const_cast<double *>(P->an.g0));
+        e = hipStreamSynchronize(P->stream);
+    }
+    (void)hipFree(dv);
+    if (e != hipSuccess) return fail(KBNB_E_DEVICE, "anchor gradient failed: %s", hipGetErrorString(e));
+    return 0;
+}
+
 // ---------------------------------------------------------------------------
 // create / destroy
 // ---------------------------------------------------------------------------
@@ -688,9 +724,10 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     if (d->ldx < d->p) return fail(KBNB_E_INVALID_ARGUMENT, "ldx=%lld < p", (long long)d->ldx);
     if (d->batch_width < 0 || d->batch_width > 4096) return fail(KBNB_E_INVALID_ARGUMENT, "batch_width out of range");
     if (d->cert_period < 0 || d->cert_period > 1000) return fail(KBNB_E_INVALID_ARGUMENT, "cert_period out of range");
-    if (d->iter_dtype < KBNB_ITER_AUTO || d->iter_dtype > KBNB_ITER_F64)
+    if (d->iter_dtype < KBNB_ITER_AUTO || d->iter_dtype > KBNB_ITER_ANCHORED)
         return fail(KBNB_E_INVALID_ARGUMENT, "unknown iter_dtype %d", d->iter_dtype);
-    if (d->iter_dtype == KBNB_ITER_F32 && d->x_dtype == KBNB_DTYPE_F64)
+    if ((d->iter_dtype == KBNB_ITER_F32 || d->iter_dtype == KBNB_ITER_ANCHORED) &&
+        d->x_dtype == KBNB_DTYPE_F64)
         return fail(KBNB_E_INVALID_ARGUMENT, "a float32 iteration needs float32 or bfloat16 X");
     int rc = device_ok();
     if (rc) return rc;
@@ -709,6 +746,8 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->xtype = d->x_dtype;
     P->iter_f64 = (d->x_dtype == KBNB_DTYPE_F64) || (d->iter_dtype == KBNB_ITER_F64) ||
                   (d->iter_dtype == KBNB_ITER_AUTO && d->loss == KBNB_LOSS_SQUARED);
+    P->anchored = !P->iter_f64 && (d->iter_dtype == KBNB_ITER_ANCHORED ||
+                                   (d->iter_dtype == KBNB_ITER_AUTO && d->n > 10000));
     P->ti_bytes = P->iter_f64 ? 8 : 4;
     P->ldp = (int)round_up(P->p, 16);
     while (P->pp < P->p) P->pp *= 2;
@@ -803,6 +842,10 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     }
     rc = estimate_L(P);
     if (rc) { free_problem(P); return rc; }
+    if (P->anchored) {
+        rc = anchor_grad0(P);
+        if (rc) { free_problem(P); return rc; }
+    }
     P->c.n = P->n; P->c.p = P->p; P->c.k = P->k; P->c.loss = P->loss;
     P->c.ldp = P->ldp; P->c.npad = P->npad; P->c.pm = P->pm; P->c.mpad = P->mpad; P->c.m = P->m;
     P->c.pp = P->pp;
@@ -928,6 +971,7 @@ extern "C" int problem_info(kbnb_problem *P, int64_t *i_out, double *d_out)
         i_out[0] = P->n; i_out[1] = P->p; i_out[2] = P->k; i_out[3] = P->m;
         i_out[4] = P->cert_period; i_out[5] = P->loss;
         i_out[6] = P->var.back().gsplit; i_out[7] = P->rounds.load();
+        i_out[8] = P->iter_f64 ? KBNB_ITER_F64 : (P->anchored ? KBNB_ITER_ANCHORED : KBNB_ITER_F32);
     }
     if (d_out) {
         d_out[0] = P->L; d_out[1] = P->lambda2; d_out[2] = P->M; d_out[3] = (double)P->bytes;
@@ -1057,9 +1101,9 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     HIP_TRY(hipMemsetAsync(dc, 0, (size_t)P->tiles_n * mpad * 8, T.s));
     SlotState ss{};
     ss.lb = dlb; ss.phi = dphi; ss.kbar = dk; ss.sup = dsup; ss.jstar = djs; ss.slen = dslen;
-    launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c, nullptr);
+    launch_cert_fwd(T.s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c, nullptr, nullptr);
     launch_cert_bwd(T.s, P->xtype, P->XT, dZ, dQ, qsplit, v.qchunk, c, nullptr);
-    launch_cert_finish(T.s, dQ, qsplit, dl, dc, P->tiles_n, dB, nullptr, dst, ss, c, 0);
+    launch_cert_finish(T.s, dQ, qsplit, dl, dc, P->tiles_n, dB, nullptr, dst, ss, c, 0, Anchor{}, nullptr, nullptr);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(psi, dlb, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));
     HIP_TRY(hipMemcpyAsync(phi, dphi, (size_t)m * 8, hipMemcpyDeviceToHost, T.s));

@@ -78,6 +78,18 @@ struct AdmitRec {
 
 enum XType { XT_F64 = 0, XT_F32 = 1, XT_BF16 = 2 };
 
+// Anchored float32 iteration (all pointers NULL when it is off).  Each
+// node's float64 certificate at beta_c also yields the exact gradient there;
+// between certificates the float32 / bfloat16 contractions act on the
+// change D = Y - beta_c only:  S = S_c + X D,  R = l'(S) - l'(S_c),
+// grad F(Y) = grad F(beta_c) + X^T R, so their rounding shrinks with D.
+struct Anchor {
+    double *sc;        // [mpad][npad] S_c = X beta_c (float64)
+    double *bc;        // [mpad][ldp]  beta_c
+    double *gc;        // [mpad][ldp]  grad F(beta_c) (float64)
+    const double *g0;  // [ldp]        grad F(0): the anchor of a newly admitted node
+};
+
 // When `start` is set, the next launch of the calling thread records the
 // kernel's own start/end timestamps in (start, stop) (instrumentation).
 struct KernelTiming {
@@ -88,29 +100,36 @@ extern thread_local KernelTiming g_ktime;
 // ---- launchers (kbnb_kernels.hip) -----------------------------------------
 // iteration GEMMs (Ti = float for float32/bfloat16... instances, double for float64)
 // `status` (nullable) lets a GEMM tile skip when none of its 64 nodes is running
+// an.sc set: Yi holds D = Y - beta_c and R = l'(S_c + X D) - l'(S_c)
 void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
-                      void *R, const double *y, const Consts &c, const int32_t *status);
+                      void *R, const double *y, const Consts &c, const int32_t *status,
+                      const Anchor &an);
 void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
                 void *Gp, int gsplit, int gchunk, const Consts &c, const int32_t *status);
-// G = sum of split-K partials (float, or double when f64), running columns only
-// the per-node kernels sum the split-K partials themselves
+// the per-node kernels sum the split-K partials themselves (plus grad F(beta_c)
+// when anchored, and then write D = Y - beta_c to Yi)
 void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, double *B,
-                      double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c);
+                      double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c,
+                      const Anchor &an);
 // certificate
+// sc_out (nullable): also store S = X B (float64), the anchored iteration's S_c
 void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,
                      const double *y, double *lsum, double *csum, const Consts &c,
-                     const int32_t *status);
+                     const int32_t *status, double *sc_out);
 void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, double *Qp,
                      int qsplit, int qchunk, const Consts &c, const int32_t *status);
 // Bbest (engine only, nullable when update_state is 0): receives B of a
-// certificate that improves the slot's best primal value
+// certificate that improves the slot's best primal value.  Anchored (an.bc
+// set, engine only): the certificate becomes the slot's new anchor, and the
+// next step's D = theta (B - Bprev) is written to Yi (float32).
 void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const double *lsum,
                         const double *csum, int tiles_n, const double *B, double *Bbest,
-                        const int8_t *st, SlotState ss, const Consts &c, int update_state);
+                        const int8_t *st, SlotState ss, const Consts &c, int update_state,
+                        const Anchor &an, const double *Bprev, float *Yi);
 // admission of staged nodes into slots
 void launch_admit(hipStream_t s, bool iter_f64, const uint8_t *stage, int count, int rec_bytes,
                   double *B, double *Bprev, double *Bbest, void *Yi, int8_t *st, SlotState ss,
-                  const Consts &c);
+                  const Consts &c, const Anchor &an);
 // standalone prox over a batch (u given), for the step-level entry point
 void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const int32_t *kbar,
                        double *Bout, int m, double eta, const Consts &c);

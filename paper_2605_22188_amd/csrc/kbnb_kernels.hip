@@ -174,7 +174,7 @@ template <> __device__ __forceinline__ double dloss_t<double>(int loss, double s
 //   EPI_CERT   C = zeta = -l'(acc, y[row]) for row < n, plus per-column sums
 //              of l(acc) and l*(-zeta) over this tile's rows.
 // ---------------------------------------------------------------------------
-enum { EPI_DLOSS = 0, EPI_STORE = 1, EPI_CERT = 2 };
+enum { EPI_DLOSS = 0, EPI_STORE = 1, EPI_CERT = 2, EPI_DLOSS_ANCHOR = 3 };
 
 struct GemmArgs {
     const void *A;
@@ -197,6 +197,8 @@ struct GemmArgs {
     double *lsum;          // [tiles_m][ldsum]
     double *csum;
     int64_t ldsum;
+    const double *sc;      // EPI_DLOSS_ANCHOR: S_c, same layout as C
+    double *sc_out;        // EPI_CERT (nullable): also store S = acc, same layout as C
 };
 
 // XCD-aware tile order shared by the contraction kernels: workgroups are
@@ -253,6 +255,33 @@ __device__ __forceinline__ void epi_store(const GemmArgs &g, const typename V4<T
                 for (int r = 0; r < 4; ++r) {
                     const TC d = dloss_t<TC>(g.loss, acc[i][j][r], (TC)yv[i][r]);
                     o[r] = (rb0 + r < g.n) ? d : (TC)0;
+                }
+                *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = o;
+            }
+        }
+    } else if constexpr (MODE == EPI_DLOSS_ANCHOR) {
+        // acc = X D; S = S_c + acc and R = l'(S) - l'(S_c), formed in float64
+        // (squared loss: exactly 2 acc)
+        TC *C = reinterpret_cast<TC *>(g.C);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = col0 + wn * 32 + j * 16 + lr;
+#pragma unroll
+            for (int i = 0; i < FI; ++i) {
+                const int rb0 = row0 + wm * (BM / 2) + i * 16 + lg * 4;
+                acc_t o;
+                if (g.loss == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o[r] = (rb0 + r < g.n) ? (TC)(2.0 * (double)acc[i][j][r]) : (TC)0;
+                } else {
+                    double sc[4];
+                    ld4(g.sc + (int64_t)col * g.ldc + rb0, sc);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double s = sc[r] + (double)acc[i][j][r];
+                        const double d = dloss_d(g.loss, s, yv[i][r]) - dloss_d(g.loss, sc[r], yv[i][r]);
+                        o[r] = (rb0 + r < g.n) ? (TC)d : (TC)0;
+                    }
                 }
                 *reinterpret_cast<acc_t *>(C + (int64_t)col * g.ldc + rb0) = o;
             }
@@ -455,6 +484,12 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
                     sc += in ? cv : 0.0;
                 }
                 *reinterpret_cast<f64x4 *>(C + (int64_t)col * g.ldc + rb0) = o;
+                if (g.sc_out) {
+                    f64x4 sv;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) sv[r] = (rb0 + r < g.n) ? (double)acc[i][j][r] : 0.0;
+                    *reinterpret_cast<f64x4 *>(g.sc_out + (int64_t)col * g.ldc + rb0) = sv;
+                }
             }
             // reduce over the 4 lane groups holding this column
             sl += __shfl_xor(sl, 16);
@@ -547,7 +582,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
     double yv[FI][4];
-    if constexpr (MODE == EPI_DLOSS) {
+    if constexpr (MODE != EPI_STORE) {
 #pragma unroll
         for (int i = 0; i < FI; ++i) ld4(g.y + row0 + wm * (BM / 2) + i * 16 + lg * 4, yv[i]);
     }
@@ -1182,7 +1217,7 @@ template <typename Ti, int PP, int W>
 __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp, int gsplit,
                                                        double *__restrict__ B, double *__restrict__ Bprev,
                                                        Ti *__restrict__ Yi, const int8_t *__restrict__ stg,
-                                                       SlotState ss, Consts c)
+                                                       SlotState ss, Consts c, Anchor an)
 {
     constexpr int E = PP / (64 * W), NQ = E / 4;
     __shared__ ProxLds<PP> L;
@@ -1194,10 +1229,11 @@ __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp,
     const int j0 = t * E;
     const double th = ss.theta[b];
 
-    double g[E], bo[E], bp[E], u[E], y[E], bet[E];
+    double g[E], bo[E], bp[E], u[E], y[E], bet[E], bcv[E];
     int sv[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) { g[e] = 0.0; bo[e] = 0.0; bp[e] = 0.0; sv[e] = -1; }
+    for (int e = 0; e < E; ++e) { g[e] = 0.0; bo[e] = 0.0; bp[e] = 0.0; sv[e] = -1; bcv[e] = 0.0; }
+    const bool anchored = an.gc != nullptr;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int j = j0 + 4 * q;
@@ -1206,13 +1242,19 @@ __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp,
         ld4(B + off + jj, &bo[4 * q]);
         ld4(Bprev + off + jj, &bp[4 * q]);
         ld4_i8(stg + off + jj, &sv[4 * q]);
+        if (anchored) {
+            ld4(an.gc + off + jj, &g[4 * q]);
+            ld4(an.bc + off + jj, &bcv[4 * q]);
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             bo[4 * q + e] = ok ? bo[4 * q + e] : 0.0;
             bp[4 * q + e] = ok ? bp[4 * q + e] : 0.0;
             sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
+            g[4 * q + e] = ok ? g[4 * q + e] : 0.0;
         }
     }
+    // grad F(Y) = (grad F(beta_c) when anchored) + sum of the partials
     sum_splits<Ti, NQ>(Gp + off, gsplit, gstride, j0, c.ldp, g);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1241,7 +1283,8 @@ __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp,
         if (j < c.ldp) {
             double yn[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) yn[e] = bet[4 * q + e] + thn * (bet[4 * q + e] - bo[4 * q + e]);
+            for (int e = 0; e < 4; ++e)
+                yn[e] = bet[4 * q + e] + thn * (bet[4 * q + e] - bo[4 * q + e]) - bcv[4 * q + e];
             st4(Bprev + off + j, &bo[4 * q]);
             st4(B + off + j, &bet[4 * q]);
             st4(Yi + off + j, yn);
@@ -1325,7 +1368,9 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
                                                          const double *__restrict__ B,
                                                          double *__restrict__ Bbest,
                                                          const int8_t *__restrict__ stg, SlotState ss,
-                                                         Consts c, int update_state)
+                                                         Consts c, int update_state, Anchor an,
+                                                         const double *__restrict__ Bprev,
+                                                         float *__restrict__ Yi)
 {
     constexpr int E = PP / (64 * W), NQ = E / 4;
     constexpr int T = 64 * W;
@@ -1502,6 +1547,28 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
     // replaced only when this certificate improves that value.
     const bool nan = (psi != psi) || (phi != phi);
     const bool improved = !update_state || (!nan && phi < phi_prev);
+    if (update_state && an.bc) {
+        // this certificate becomes the anchor: beta_c = B, grad F(beta_c) =
+        // -X^T zeta (the partial sums above), and the next step's
+        // D = Y - beta_c = theta (B - Bprev)
+        const double th = ss.theta[b];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = j0 + 4 * q;
+            if (j < c.ldp) {
+                double bp[4], gq[4], dq[4];
+                ld4(Bprev + off + j, bp);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    gq[e] = -qv[4 * q + e];
+                    dq[e] = th * (bv[4 * q + e] - bp[e]);
+                }
+                st4(an.bc + off + j, &bv[4 * q]);
+                st4(an.gc + off + j, gq);
+                st4(Yi + off + j, dq);
+            }
+        }
+    }
     if (update_state && improved) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -1558,7 +1625,7 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
 template <typename Ti>
 __global__ __launch_bounds__(64) void k_admit(const uint8_t *__restrict__ stage, int rec_bytes,
                                                double *B, double *Bprev, double *Bbest, Ti *Yi,
-                                               int8_t *stg, SlotState ss, Consts c)
+                                               int8_t *stg, SlotState ss, Consts c, Anchor an)
 {
     const uint8_t *rec = stage + (int64_t)blockIdx.x * rec_bytes;
     const AdmitRec h = *reinterpret_cast<const AdmitRec *>(rec);
@@ -1575,6 +1642,14 @@ __global__ __launch_bounds__(64) void k_admit(const uint8_t *__restrict__ stage,
         Bprev[off + j] = w;
         Bbest[off + j] = w;
         Yi[off + j] = (Ti)w;
+        if (an.bc) {  // anchored at beta_c = 0 (D = w)
+            an.bc[off + j] = 0.0;
+            an.gc[off + j] = an.g0[j];
+        }
+    }
+    if (an.sc) {
+        double *scs = an.sc + (int64_t)b * c.npad;
+        for (int i = threadIdx.x; i < c.npad; i += 64) scs[i] = 0.0;
     }
     if (threadIdx.x == 0) {
         ss.theta[b] = 0.0;
@@ -1678,15 +1753,20 @@ static void gemm_bf16(hipStream_t s, GemmArgs g, int rows, int tiles_n, int spli
 }
 
 void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
-                      void *R, const double *y, const Consts &c, const int32_t *status)
+                      void *R, const double *y, const Consts &c, const int32_t *status,
+                      const Anchor &an)
 {
     GemmArgs g{};
     g.col_status = status;
     g.A = X; g.lda = c.ldp; g.B = Yi; g.ldb = c.ldp; g.C = R; g.ldc = c.npad;
     g.k_len = c.ldp; g.k_chunk = c.ldp;
     g.n = c.n; g.loss = c.loss; g.y = y;
+    g.sc = an.sc;
     const int tn = c.mact / GEMM_BN;
-    if (iter_f64) {
+    if (an.sc && !iter_f64) {
+        if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1);
+        else gemm_bf16<EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1);
+    } else if (iter_f64) {
         if (xtype == XT_F64) gemm<double, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
         else if (xtype == XT_F32) gemm<float, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
         else gemm<uint16_t, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
@@ -1713,10 +1793,11 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
 
 void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,
                      const double *y, double *lsum, double *csum, const Consts &c,
-                     const int32_t *status)
+                     const int32_t *status, double *sc_out)
 {
     GemmArgs g{};
     g.col_status = status;
+    g.sc_out = sc_out;
     g.A = X; g.lda = c.ldp; g.B = B; g.ldb = c.ldp; g.C = Z; g.ldc = c.npad;
     g.k_len = c.ldp; g.k_chunk = c.ldp;
     g.n = c.n; g.loss = c.loss; g.y = y; g.lsum = lsum; g.csum = csum; g.ldsum = c.mpad;
@@ -1752,14 +1833,15 @@ void launch_cert_bwd(hipStream_t s, int xtype, const void *XT, const double *Z, 
     } while (0)
 
 void launch_prox_iter(hipStream_t s, bool iter_f64, const void *Gp, int gsplit, double *B,
-                      double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c)
+                      double *Bprev, void *Yi, const int8_t *st, SlotState ss, const Consts &c,
+                      const Anchor &an)
 {
     if (iter_f64) {
         KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<double, PP, W>), dim3(min(c.m, c.mact)), dim3(64 * W), 0, s,
-                                                 (const double *)Gp, gsplit, B, Bprev, (double *)Yi, st, ss, c));
+                                                 (const double *)Gp, gsplit, B, Bprev, (double *)Yi, st, ss, c, an));
     } else {
         KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_prox_iter<float, PP, W>), dim3(min(c.m, c.mact)), dim3(64 * W), 0, s,
-                                                 (const float *)Gp, gsplit, B, Bprev, (float *)Yi, st, ss, c));
+                                                 (const float *)Gp, gsplit, B, Bprev, (float *)Yi, st, ss, c, an));
     }
 }
 
@@ -1772,23 +1854,25 @@ void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const i
 
 void launch_cert_finish(hipStream_t s, const double *Qp, int qsplit, const double *lsum,
                         const double *csum, int tiles_n, const double *B, double *Bbest,
-                        const int8_t *st, SlotState ss, const Consts &c, int update_state)
+                        const int8_t *st, SlotState ss, const Consts &c, int update_state,
+                        const Anchor &an, const double *Bprev, float *Yi)
 {
     KBNB_PP_DISPATCH(c.p, KBNB_LAUNCH((k_cert_finish<PP, W>), dim3(min(c.m, c.mact)), dim3(64 * W), 0, s, Qp, qsplit,
-                                             lsum, csum, tiles_n, B, Bbest, st, ss, c, update_state));
+                                             lsum, csum, tiles_n, B, Bbest, st, ss, c, update_state,
+                                             an, Bprev, Yi));
 }
 
 void launch_admit(hipStream_t s, bool iter_f64, const uint8_t *stage, int count, int rec_bytes,
                   double *B, double *Bprev, double *Bbest, void *Yi, int8_t *st, SlotState ss,
-                  const Consts &c)
+                  const Consts &c, const Anchor &an)
 {
     if (count <= 0) return;
     if (iter_f64)
         KBNB_LAUNCH((k_admit<double>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
-                           Bbest, (double *)Yi, st, ss, c);
+                           Bbest, (double *)Yi, st, ss, c, an);
     else
         KBNB_LAUNCH((k_admit<float>), dim3(count), dim3(64), 0, s, stage, rec_bytes, B, Bprev,
-                           Bbest, (float *)Yi, st, ss, c);
+                           Bbest, (float *)Yi, st, ss, c, an);
 }
 
 void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int rows, int cols,

@@ -87,7 +87,8 @@ def test_header_constants_match_binding():
     pairs = {"OK": "OK", "TIMEOUT": "TIMEOUT", "CONVERGED": "CONVERGED", "PRUNED": "PRUNED",
              "MAXITER": "MAXITER", "DTYPE_F64": "DTYPE_F64", "DTYPE_F32": "DTYPE_F32",
              "DTYPE_BF16": "DTYPE_BF16", "ITER_AUTO": "ITER_AUTO", "ITER_F32": "ITER_F32",
-             "ITER_F64": "ITER_F64", "MEM_HOST_COPY": "MEM_HOST_COPY",
+             "ITER_F64": "ITER_F64", "ITER_ANCHORED": "ITER_ANCHORED",
+             "MEM_HOST_COPY": "MEM_HOST_COPY",
              "MEM_DEVICE_COPY": "MEM_DEVICE_COPY"}
     for hname, pname in pairs.items():
         assert defs[hname] == getattr(K, pname), hname

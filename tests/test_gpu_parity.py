@@ -161,12 +161,18 @@ def _bound_parity(inst, nodes, batch_width, cert_period, warm=None, sample=None,
 @pytest.mark.parametrize("loss,dtype,it", [(W.SQUARED, "f64", 0), (W.LOGISTIC, "f64", 0),
                                             (W.SQUARED, "f32", 0), (W.LOGISTIC, "f32", 0),
                                             (W.SQUARED, "bf16", 0), (W.LOGISTIC, "bf16", 0),
-                                            (W.LOGISTIC, "f32", "f64")])
+                                            (W.LOGISTIC, "f32", "f64"),
+                                            (W.SQUARED, "f32", "anchored"),
+                                            (W.LOGISTIC, "f32", "anchored"),
+                                            (W.SQUARED, "bf16", "anchored"),
+                                            (W.LOGISTIC, "bf16", "anchored")])
 def test_node_bounds_small_all_nodes(loss, dtype, it):
     """Iteration precision "auto" (0): float64 for the squared loss on any X,
     float32 for the logistic loss on float32 / bfloat16 X (bfloat16 X: the
     products run on bfloat16 MFMA with a three-term split of the float32
-    operand).  "f64": float64 iteration forced on float32 X."""
+    operand).  "f64": float64 iteration forced on float32 X.  "anchored":
+    float32 / bfloat16 products of the change since each node's last float64
+    certificate."""
     announce(f"node bounds 700x50 loss={loss} X {dtype} iteration {it}, 100 nodes on 64 slots")
     inst = W.small_instance(700, 50, 6, loss, seed=5 + loss, rho=0.6, dtype=dtype)
     nodes = W.random_nodes(50, 100, 3, 15, seed=77)
@@ -251,7 +257,9 @@ def test_bnb_plain_squared_500x30_on_gpu():
 
 
 @pytest.mark.parametrize("n,p,k,loss,dtype,it", [(1500, 3000, 10, W.LOGISTIC, "bf16", 0),
-                                                  (2500, 5000, 15, W.SQUARED, "bf16", 0)])
+                                                  (2500, 5000, 15, W.SQUARED, "bf16", 0),
+                                                  (2500, 5000, 15, W.SQUARED, "bf16", "anchored"),
+                                                  (3000, 4000, 12, W.LOGISTIC, "f32", "anchored")])
 def test_node_bounds_wide_nodes(n, p, k, loss, dtype, it):
     """Node bounds at p above 2048, checked by the duality bracket the oracle
     evaluates at the returned iterate: the certified bound LB must satisfy

@@ -38,3 +38,24 @@ def test_autotune_with_given_nodes_and_budget():
     # the 4096-wide candidate cannot fit 64 MiB: skipped with rate 0
     assert out["rates"][1, 0] == 0.0 and out["rates"][0, 0] > 0
     assert out["batch_width"] == 32 and out["sample_nodes"] == 64
+
+
+def test_iteration_precision_resolution():
+    print("[gpu-test] iteration precision: auto resolution", flush=True)
+    cases = [((300, 20, W.SQUARED, "f64"), 0, "f64"),
+             ((300, 20, W.SQUARED, "f32"), 0, "f64"),
+             ((300, 20, W.LOGISTIC, "f32"), 0, "f32"),
+             ((300, 20, W.LOGISTIC, "bf16"), 0, "f32"),
+             ((12000, 20, W.LOGISTIC, "f32"), 0, "anchored"),
+             ((300, 20, W.LOGISTIC, "bf16"), "anchored", "anchored"),
+             ((300, 20, W.SQUARED, "f32"), "f32", "f32")]
+    for (n, p, loss, dt), it, want in cases:
+        inst = W.small_instance(n, p, 4, loss, seed=3, dtype=dt)
+        h = K.create_from_instance(inst, batch_width=8, iter_dtype=it)
+        assert K.problem_info(h)["iteration"] == want, (n, p, loss, dt, it)
+        K.destroy_problem(h)
+    inst = W.small_instance(300, 20, 4, W.LOGISTIC, seed=3, dtype="f64")
+    for it in ("f32", "anchored"):
+        with pytest.raises(K.KbnbError) as e:
+            K.create_from_instance(inst, iter_dtype=it)
+        assert e.value.code == -1

@@ -89,16 +89,23 @@ def f64_from_bf16_bits(b: np.ndarray) -> np.ndarray:
 
 def ar1_design(n: int, p: int, rho: float, rng: np.random.Generator,
                chunk_rows: int = 8192) -> np.ndarray:
-    """Gaussian rows with Toeplitz covariance rho^|j-l| (AR(1) recursion)."""
+    """Gaussian rows with Toeplitz covariance rho^|j-l| (AR(1) recursion).
+
+    Rows are drawn in blocks of chunk_rows standard normals (row-major order);
+    within a block the recursion x_j = rho x_{j-1} + sqrt(1 - rho^2) g_j runs
+    over the columns of the block's transpose, so each step reads and writes
+    contiguous memory (the values do not depend on the layout)."""
     X = np.empty((n, p), dtype=np.float64)
     c = math.sqrt(1.0 - rho * rho)
     for r0 in range(0, n, chunk_rows):
         r1 = min(n, r0 + chunk_rows)
-        g = rng.standard_normal((r1 - r0, p))
-        blk = X[r0:r1]
-        blk[:, 0] = g[:, 0]
+        gt = np.ascontiguousarray(rng.standard_normal((r1 - r0, p)).T)
+        bt = np.empty_like(gt)
+        bt[0] = gt[0]
         for j in range(1, p):
-            blk[:, j] = rho * blk[:, j - 1] + c * g[:, j]
+            np.multiply(bt[j - 1], rho, out=bt[j])
+            bt[j] += c * gt[j]
+        X[r0:r1] = bt.T
     return X
 
 
