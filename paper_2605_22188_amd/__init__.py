@@ -255,6 +255,30 @@ def _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts):
     return arr, keep
 
 
+class PreparedNodes:
+    """Node descriptors marshalled once, for repeated or timed submission."""
+
+    def __init__(self, nodes, upper_bound=math.inf, rel_tol=0.0, max_iters=0, tags=None,
+                 warm_starts=None):
+        self.count = len(nodes)
+        self.arr, self._keep = _node_array(nodes, upper_bound, rel_tol, max_iters, tags,
+                                           warm_starts)
+
+
+def submit_prepared(h: Handle, prep: PreparedNodes):
+    _check(load().submit_nodes(h.ptr, prep.arr, prep.count))
+
+
+def poll_raw(h: Handle, out, cap, timeout_us=-1):
+    """poll_bounds into a caller-owned (BoundResult * cap) array, no supports
+    or iterates; returns (count, return code)."""
+    n = ctypes.c_int32(0)
+    rc = load().poll_bounds(h.ptr, out, int(cap), ctypes.byref(n), None, None, int(timeout_us))
+    if rc < 0:
+        _check(rc)
+    return n.value, rc
+
+
 def submit_nodes(h: Handle, nodes, upper_bound=math.inf, rel_tol=0.0, max_iters=0, tags=None,
                  warm_starts=None):
     """nodes: sequence of (fixed_in, fixed_out) index arrays (or objects with

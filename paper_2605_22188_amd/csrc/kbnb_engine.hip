@@ -106,6 +106,12 @@ struct Variant {
     bool captured = false;
 };
 
+// Host view of one copy of the slot-state block.
+struct HostSlots {
+    int32_t *status = nullptr, *iter = nullptr, *jstar = nullptr, *slen = nullptr, *sup = nullptr;
+    double *lb = nullptr, *phi = nullptr, *gap = nullptr;
+};
+
 struct kbnb_problem {
     // instance
     int n = 0, p = 0, k = 0, loss = 0, xtype = 0;
@@ -133,17 +139,25 @@ struct kbnb_problem {
     uint8_t *stage_d = nullptr;
     int32_t *gslots_d = nullptr;
     SlotState ss{};
-    // pinned host mirrors
-    uint8_t *stage_h = nullptr;
+    // pinned host mirrors, double-buffered: the engine enqueues round r + 1
+    // before it reads round r's slot states
+    uint8_t *stage_h = nullptr;     // two halves of mpad admission records
     int rec_bytes = 0;
-    int32_t *h_status = nullptr, *h_iter = nullptr, *h_jstar = nullptr, *h_slen = nullptr, *h_sup = nullptr;
-    double *h_lb = nullptr, *h_phi = nullptr, *h_gap = nullptr;
+    HostSlots hs[2];
     int32_t *h_gslots = nullptr;
     double *h_gbuf = nullptr;
     char *slot_dev = nullptr;   // contiguous device block of the slot arrays
-    char *slot_host = nullptr;  // pinned mirror of that block
+    char *slot_host = nullptr;  // two pinned mirrors of that block
     size_t slot_bytes = 0;
     hipStream_t stream = nullptr;
+    hipStream_t gstream = nullptr;  // gathers beside a round enqueued ahead (created on first use:
+                                    // streams share the process's few hardware queues)
+    hipEvent_t ev_round[2] = {nullptr, nullptr};
+    int64_t round_id[2] = {0, 0};
+    std::vector<int> round_kinds[2];  // timed launches of the round (instrumentation)
+    double round_useful[2] = {0, 0}, round_slots[2] = {0, 0};
+    std::vector<int64_t> slot_round;  // round at which each slot's node was admitted
+    int64_t next_round = 0;
     bool use_graphs = true;
     Consts c{};
     // engine
@@ -158,7 +172,6 @@ struct kbnb_problem {
     std::vector<Variant> var;        // launch widths 64, 128, ..., mpad
     int active = 0;
     bool shutdown = false;
-    bool busy = false;  // a round is in flight
     int engine_error = 0;
     std::string engine_msg;
     std::mutex api_mu;  // serialises calls on this handle
@@ -433,12 +446,6 @@ static void build_graph(kbnb_problem *P, Variant &v)
     v.graph = ge;
 }
 
-__global__ void k_retire(const int32_t *__restrict__ slots, int count, int32_t *__restrict__ status)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < count) status[slots[r]] = SLOT_EMPTY;
-}
-
 __global__ void k_gather_cols(const double *__restrict__ B, int ldp, int p,
                               const int32_t *__restrict__ slots, double *__restrict__ out)
 {
@@ -450,18 +457,33 @@ __global__ void k_gather_cols(const double *__restrict__ B, int ldp, int p,
 // ---------------------------------------------------------------------------
 // engine worker
 // ---------------------------------------------------------------------------
-static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
+#define HIP_BREAK(expr)                                                                  \
+    {                                                                                    \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            rc = fail(KBNB_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+            break;                                                                       \
+        }                                                                                \
+    }
+
+// Admit queued nodes into the lowest free slots and enqueue one round (its
+// admissions, the captured graph of the narrowest covering width, and the
+// copy of the slot states into host buffer `buf`).  Called and returns with
+// the lock held; `enq` tells whether a round was enqueued.
+static int enqueue_round_async(kbnb_problem *P, std::unique_lock<std::mutex> &lk, int buf, bool &enq)
 {
-    // 1. admission
+    enq = false;
+    const int64_t rid = P->next_round;
     int nadm = 0;
-    std::vector<int> adm_slots;
+    uint8_t *stage = P->stage_h + (size_t)buf * P->mpad * P->rec_bytes;
     while (!P->pending.empty() && !P->free_slots.empty()) {
         PendingNode nd = std::move(P->pending.front());
         P->pending.pop_front();
         const int slot = *P->free_slots.begin();
         P->free_slots.erase(P->free_slots.begin());
         P->occupied[slot] = 1;
-        uint8_t *rec = P->stage_h + (size_t)nadm * P->rec_bytes;
+        P->slot_round[slot] = rid;
+        uint8_t *rec = stage + (size_t)nadm * P->rec_bytes;
         AdmitRec h{};
         h.slot = slot;
         h.kbar = nd.kbar;
@@ -479,17 +501,15 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
         P->slot_n0[slot] = nd.n0;
         ++P->active;
         ++nadm;
-        adm_slots.push_back(slot);
     }
     if (P->active == 0) return 0;
-    double run_useful = 0, run_slots = 0;
-    if (P->timing) {
-        std::vector<char> is_free(P->m, 0);
-        for (int b : P->free_slots) is_free[b] = 1;
+    const bool timed = P->timing;
+    P->round_useful[buf] = P->round_slots[buf] = 0;
+    if (timed) {
         for (int b = 0; b < P->m; ++b)
-            if (!is_free[b]) {
-                run_useful += P->p - P->slot_n0[b];
-                run_slots += 1;
+            if (P->occupied[b]) {
+                P->round_useful[buf] += P->p - P->slot_n0[b];
+                P->round_slots[buf] += 1;
             }
     }
     // launch width: the narrowest variant covering every occupied slot
@@ -499,98 +519,162 @@ static int engine_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk)
     Variant *var = &P->var.back();
     for (Variant &v : P->var)
         if (v.mact >= hi) { var = &v; break; }
-    P->busy = true;
     lk.unlock();
     hipStream_t s = P->stream;
     int rc = 0;
+    P->round_kinds[buf].clear();
     do {
         if (nadm) {
-            HIP_TRY(hipMemcpyAsync(P->stage_d, P->stage_h, (size_t)nadm * P->rec_bytes, hipMemcpyHostToDevice, s));
-            launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Bbest, P->Yi, P->st, P->ss, P->c, P->an);
+            HIP_BREAK(hipMemcpyAsync(P->stage_d, stage, (size_t)nadm * P->rec_bytes, hipMemcpyHostToDevice, s));
+            launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Bbest, P->Yi,
+                         P->st, P->ss, P->c, P->an);
         }
-        std::vector<int> kinds;
-        const bool timed = P->timing;
         if (!timed && P->use_graphs && !var->captured) build_graph(P, *var);
         if (timed) {
-            int trc = enqueue_round_timed(P, *var, kinds);
-            if (trc) return trc;
+            rc = enqueue_round_timed(P, *var, P->round_kinds[buf]);
+            if (rc) break;
         } else if (var->graph) {
-            HIP_TRY(hipGraphLaunch(var->graph, s));
+            HIP_BREAK(hipGraphLaunch(var->graph, s));
         } else {
             enqueue_round(P, *var);
         }
-        HIP_TRY(hipMemcpyAsync(P->slot_host, P->slot_dev, P->slot_bytes, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (timed) {
-            for (size_t e = 0; e < kinds.size(); ++e) {
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, P->ev[2 * e], P->ev[2 * e + 1]));
-                P->kt_ms[kinds[e]] += ms;
-                P->kt_n[kinds[e]] += 1;
-            }
-            P->useful_cols += run_useful * P->cert_period;
-            P->running_cols += run_slots * P->cert_period;
-        }
-        // 3. retire finished slots
-        int nfin = 0;
-        for (int b = 0; b < P->m; ++b) {
-            const int stt = P->h_status[b];
-            if (stt >= 0) P->h_gslots[nfin++] = b;
-        }
-        if (nfin) {
-            HIP_TRY(hipMemcpyAsync(P->gslots_d, P->h_gslots, (size_t)nfin * 4, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_gather_cols, dim3(nfin), dim3(256), 0, s, P->Bbest, P->ldp, P->p, P->gslots_d, P->gbuf);
-            HIP_TRY(hipMemcpyAsync(P->h_gbuf, P->gbuf, (size_t)nfin * P->p * 8, hipMemcpyDeviceToHost, s));
-            // retired slots must not iterate again
-            hipLaunchKernelGGL(k_retire, dim3((nfin + 255) / 256), dim3(256), 0, s, P->gslots_d, nfin, P->ss.status);
-            HIP_TRY(hipStreamSynchronize(s));
-        }
-        lk.lock();
-        for (int r = 0; r < nfin; ++r) {
-            const int b = P->h_gslots[r];
-            DoneNode d;
-            d.r.tag = P->slot_tag[b];
-            d.r.lower_bound = P->h_lb[b];
-            d.r.primal_value = P->h_phi[b];
-            d.r.rel_gap = P->h_gap[b];
-            d.r.status = P->h_status[b];
-            d.r.iterations = P->h_iter[b];
-            d.r.branch_index = P->h_jstar[b];
-            d.r.support_len = P->h_slen[b];
-            d.sup.assign(P->h_sup + (size_t)b * P->k, P->h_sup + (size_t)(b + 1) * P->k);
-            d.beta.assign(P->h_gbuf + (size_t)r * P->p, P->h_gbuf + (size_t)(r + 1) * P->p);
-            P->done.push_back(std::move(d));
-            P->free_slots.insert(b);
-            P->occupied[b] = 0;
-            --P->active;
-        }
-        P->busy = false;
-        P->rounds++;
-        P->cv_done.notify_all();
-        return 0;
+        HIP_BREAK(hipMemcpyAsync(P->slot_host + (size_t)buf * P->slot_bytes, P->slot_dev, P->slot_bytes,
+                                 hipMemcpyDeviceToHost, s));
+        HIP_BREAK(hipEventRecord(P->ev_round[buf], s));
     } while (0);
     lk.lock();
-    P->busy = false;
-    return rc;
+    if (rc) return rc;
+    P->round_id[buf] = rid;
+    P->next_round = rid + 1;
+    enq = true;
+    return 0;
 }
 
+// Wait for the round in host buffer `buf`, gather the best iterates of the
+// nodes that finished in it and hand their results over.  A slot counts only
+// if its node was admitted at or before that round.  With a round already
+// enqueued behind it (`ahead`) the gather runs on the side stream, beside
+// that round; otherwise on the problem's own stream, so it never waits
+// behind other problems' work queued on a shared hardware queue.  Called and
+// returns with the lock held.
+static int process_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk, int buf, bool ahead)
+{
+    lk.unlock();
+    const HostSlots &h = P->hs[buf];
+    const int64_t rid = P->round_id[buf];
+    int rc = 0, nfin = 0;
+    do {
+        HIP_BREAK(hipEventSynchronize(P->ev_round[buf]));
+        const std::vector<int> &kinds = P->round_kinds[buf];
+        for (size_t e = 0; e < kinds.size(); ++e) {
+            float ms = 0.f;
+            HIP_BREAK(hipEventElapsedTime(&ms, P->ev[2 * e], P->ev[2 * e + 1]));
+            P->kt_ms[kinds[e]] += ms;
+            P->kt_n[kinds[e]] += 1;
+        }
+        if (rc) break;
+        if (!kinds.empty()) {
+            P->useful_cols += P->round_useful[buf] * P->cert_period;
+            P->running_cols += P->round_slots[buf] * P->cert_period;
+        }
+        for (int b = 0; b < P->m; ++b)
+            if (P->occupied[b] && P->slot_round[b] <= rid && h.status[b] >= 0) P->h_gslots[nfin++] = b;
+        if (nfin) {
+            if (ahead && !P->gstream) HIP_BREAK(hipStreamCreate(&P->gstream));
+            hipStream_t g = ahead ? P->gstream : P->stream;
+            HIP_BREAK(hipMemcpyAsync(P->gslots_d, P->h_gslots, (size_t)nfin * 4, hipMemcpyHostToDevice, g));
+            hipLaunchKernelGGL(k_gather_cols, dim3(nfin), dim3(256), 0, g, P->Bbest, P->ldp, P->p, P->gslots_d, P->gbuf);
+            HIP_BREAK(hipMemcpyAsync(P->h_gbuf, P->gbuf, (size_t)nfin * P->p * 8, hipMemcpyDeviceToHost, g));
+            HIP_BREAK(hipStreamSynchronize(g));
+        }
+    } while (0);
+    lk.lock();
+    if (rc) return rc;
+    for (int r = 0; r < nfin; ++r) {
+        const int b = P->h_gslots[r];
+        DoneNode d;
+        d.r.tag = P->slot_tag[b];
+        d.r.lower_bound = h.lb[b];
+        d.r.primal_value = h.phi[b];
+        d.r.rel_gap = h.gap[b];
+        d.r.status = h.status[b];
+        d.r.iterations = h.iter[b];
+        d.r.branch_index = h.jstar[b];
+        d.r.support_len = h.slen[b];
+        d.sup.assign(h.sup + (size_t)b * P->k, h.sup + (size_t)(b + 1) * P->k);
+        d.beta.assign(P->h_gbuf + (size_t)r * P->p, P->h_gbuf + (size_t)(r + 1) * P->p);
+        P->done.push_back(std::move(d));
+        // the slot's device status stays >= 0 (not running) until a node is
+        // admitted into it again
+        P->free_slots.insert(b);
+        P->occupied[b] = 0;
+        --P->active;
+    }
+    P->rounds++;
+    P->cv_done.notify_all();
+    return 0;
+}
+
+// Problems of this process with nodes in flight (admitted or queued).
+static std::atomic<int> g_busy_engines{0};
+
+// The worker can keep two rounds in flight: it enqueues round r + 1 and then
+// processes round r, so the device runs a round while the host hands over
+// the previous one's results and stages new admissions.  It does so only
+// while its problem is the only one with work: otherwise other problems'
+// rounds already fill those host gaps, and a second queued round would only
+// add queueing delay to every node.  It also needs 8 occupied slots (a
+// round enqueued ahead runs empty if every node finished, which is likely
+// when few are in flight) and no kernel timing (instrumentation).
 static void engine_main(kbnb_problem *P)
 {
     std::unique_lock<std::mutex> lk(P->mu);
+    int pend = -1, next = 0, rc = 0;
+    bool busy = false;
     for (;;) {
-        P->cv_work.wait(lk, [&] { return P->shutdown || P->active > 0 || !P->pending.empty(); });
-        if (P->shutdown) break;
-        int rc = engine_round(P, lk);
-        if (rc != 0) {
-            P->engine_error = rc;
-            P->engine_msg = g_last_error;
-            // fail every queued and running node
-            P->pending.clear();
-            P->busy = false;
-            P->cv_done.notify_all();
-            break;
+        const bool has_work = P->active > 0 || !P->pending.empty();
+        if (has_work != busy) {
+            busy = has_work;
+            g_busy_engines += busy ? 1 : -1;
         }
+        if (pend < 0) {
+            P->cv_work.wait(lk, [&] { return P->shutdown || P->active > 0 || !P->pending.empty(); });
+            if (P->shutdown) break;
+            if (!busy) {
+                busy = true;
+                ++g_busy_engines;
+            }
+        }
+        bool enq = false;
+        const bool ahead_ok = !P->timing && P->active >= 8 && g_busy_engines.load() <= 1;
+        if (!P->shutdown && (pend < 0 || ahead_ok) && (P->active > 0 || !P->pending.empty())) {
+            rc = enqueue_round_async(P, lk, next, enq);
+            if (rc) break;
+        }
+        if (pend >= 0) {
+            rc = process_round(P, lk, pend, enq);
+            if (rc) break;
+            pend = -1;
+        }
+        if (enq) {
+            pend = next;
+            next ^= 1;
+        }
+        if (P->shutdown && pend < 0) break;
     }
+    if (rc) {
+        P->engine_error = rc;
+        P->engine_msg = g_last_error;
+        // fail every queued node; running ones are abandoned
+        P->pending.clear();
+        P->cv_done.notify_all();
+    }
+    if (pend >= 0) {
+        lk.unlock();
+        (void)hipEventSynchronize(P->ev_round[pend]);
+        lk.lock();
+    }
+    if (busy) --g_busy_engines;
 }
 
 // ---------------------------------------------------------------------------
@@ -697,11 +781,15 @@ static void free_problem(kbnb_problem *P)
     if (P->stream) (void)hipStreamSynchronize(P->stream);
     for (Variant &v : P->var)
         if (v.graph) (void)hipGraphExecDestroy(v.graph);
+    if (P->gstream) (void)hipStreamSynchronize(P->gstream);
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : P->ev_round)
+        if (e) (void)hipEventDestroy(e);
     if (P->arena) (void)hipFree(P->arena);
     void *pins[] = {P->stage_h, P->slot_host, P->h_gslots, P->h_gbuf};
     for (void *q : pins)
         if (q) (void)hipHostFree(q);
+    if (P->gstream) (void)hipStreamDestroy(P->gstream);
     if (P->stream) (void)hipStreamDestroy(P->stream);
     delete P;
 }
@@ -763,9 +851,11 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     const size_t xbytes = (size_t)P->npad * P->ldp * xel;
     P->rec_bytes = (int)round_up(round_up(sizeof(AdmitRec) + P->ldp, 8) + 8 * (size_t)P->ldp, 256);
 
-    if (hipStreamCreate(&P->stream) != hipSuccess) {
-        delete P;
-        return fail(KBNB_E_DEVICE, "hipStreamCreate failed");
+    if (hipStreamCreate(&P->stream) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_round[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_round[1], hipEventDisableTiming) != hipSuccess) {
+        free_problem(P);
+        return fail(KBNB_E_DEVICE, "stream or event creation failed");
     }
     // batch width from the budget
     int m = d->batch_width;
@@ -788,6 +878,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->slot_n0.assign(P->m, 0);
     for (int b = 0; b < P->m; ++b) P->free_slots.insert(b);
     P->occupied.assign(P->m, 0);
+    P->slot_round.assign(P->m, 0);
 
     rc = alloc_arena(P, xbytes, xel);
     if (rc) { free_problem(P); return rc; }
@@ -815,20 +906,24 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     // pinned host mirrors
     {
         const size_t mb = P->mpad;
-        bool okp = hipHostMalloc((void **)&P->stage_h, mb * P->rec_bytes, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->slot_host, P->slot_bytes, 0) == hipSuccess &&
+        bool okp = hipHostMalloc((void **)&P->stage_h, 2 * mb * P->rec_bytes, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->slot_host, 2 * P->slot_bytes, 0) == hipSuccess &&
                    hipHostMalloc((void **)&P->h_gslots, mb * 4, 0) == hipSuccess &&
                    hipHostMalloc((void **)&P->h_gbuf, mb * P->p * 8, 0) == hipSuccess;
         if (okp) {
-            auto view = [&](const void *dev) { return P->slot_host + ((const char *)dev - P->slot_dev); };
-            P->h_status = (int32_t *)view(P->ss.status);
-            P->h_iter = (int32_t *)view(P->ss.iter);
-            P->h_jstar = (int32_t *)view(P->ss.jstar);
-            P->h_slen = (int32_t *)view(P->ss.slen);
-            P->h_sup = (int32_t *)view(P->ss.sup);
-            P->h_lb = (double *)view(P->ss.lb);
-            P->h_phi = (double *)view(P->ss.phi);
-            P->h_gap = (double *)view(P->ss.gap);
+            for (int q = 0; q < 2; ++q) {
+                char *hb = P->slot_host + (size_t)q * P->slot_bytes;
+                auto view = [&](const void *dev) { return hb + ((const char *)dev - P->slot_dev); };
+                HostSlots &h = P->hs[q];
+                h.status = (int32_t *)view(P->ss.status);
+                h.iter = (int32_t *)view(P->ss.iter);
+                h.jstar = (int32_t *)view(P->ss.jstar);
+                h.slen = (int32_t *)view(P->ss.slen);
+                h.sup = (int32_t *)view(P->ss.sup);
+                h.lb = (double *)view(P->ss.lb);
+                h.phi = (double *)view(P->ss.phi);
+                h.gap = (double *)view(P->ss.gap);
+            }
         }
         if (!okp) { free_problem(P); return fail(KBNB_E_OUT_OF_MEMORY, "pinned host allocation failed"); }
     }
