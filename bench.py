@@ -7,16 +7,22 @@ loss, X 5000 x 200 float32 with AR(1) column correlation rho = 0.5, k = 10,
 batch of 256 nodes (|J1| ~ U{0..5}, |J0| ~ U{0..60}, batch seed 1000 + step)
 to a 1e-6 relative duality gap, with UB = +inf so every node is solved.
 
-A step = submit the batch's 256 node descriptors through submit_nodes and
-collect all 256 certified bounds through poll_bounds.  X and y are resident
-in device memory before the timed region; the node descriptors (about 100
-bytes each) cross PCIe inside it.
+A step = one batch's 256 node descriptors submitted through submit_nodes and
+its 256 certified bounds collected through poll_bounds, one batch after
+another (--window W keeps W batches in flight, the next admitted as slots
+free up).  A float64 certificate every 16 steps of each node.  X and y are
+resident in device memory before the timed region; the node descriptors are
+marshalled before it and cross PCIe inside it.
 
 Printed JSON line: the contract fields plus
-  roofline      the dominant kernel's algorithmic rate against its peak, from
-                a kernel-timed pass (hipEvent pairs on the engine stream)
-  cpu_baseline  the float64 oracle on a bounded sample of the same nodes
-  comparator    the same library at batch width 1 (one node at a time)
+  roofline          the dominant kernel's algorithmic rate against its peak,
+                    from a kernel-timed pass (hipEvent pairs on the engine
+                    stream)
+  cpu_baseline      the float64 oracle on a bounded sample of the same nodes
+  comparator        the same library at batch width 1 (one node at a time)
+  time_to_zero_gap  full GPU branch and bound, 10000 x 1000 bfloat16 squared
+  serving           32-problem Poisson serving mix, p50/p99 node latency
+  large_logistic    node bounds on the 100000 x 5000 bfloat16 logistic workload
 """
 from __future__ import annotations
 
@@ -294,13 +300,53 @@ def serving_leg(K, W, torch, args):
             "budget_bytes_per_problem": 2 << 30}
 
 
+def run_stream(K, h, preps, out, window):
+    """Submit the prepared batches keeping `window` batches in flight: batch
+    s + window is submitted as soon as batch s has all its results (the
+    engine admits queued nodes as slots free up).  Tags must be unique across
+    batches (batch s uses s * len + i).  Returns (results as (tag, status,
+    iterations, rel_gap), latencies_s from each node's batch submission)."""
+    if not preps:
+        return [], []
+    nb = len(preps)
+    size = preps[0].count
+    base = preps[0].arr[0].tag // size  # batch index of preps[0]
+    t_sub = [0.0] * nb
+    left = [p.count for p in preps]
+    nxt = 0
+    for _ in range(min(window, nb)):
+        t_sub[nxt] = time.perf_counter()
+        K.submit_prepared(h, preps[nxt])
+        nxt += 1
+    res, lat = [], []
+    total = sum(left)
+    while len(res) < total:
+        cnt, rc = K.poll_raw(h, out, len(out), timeout_us=-1)
+        now = time.perf_counter()
+        for i in range(cnt):
+            r = out[i]
+            b = r.tag // size - base
+            res.append((r.tag, r.status, r.iterations, r.rel_gap))
+            lat.append(now - t_sub[b])
+            left[b] -= 1
+            if left[b] == 0 and nxt < nb:
+                t_sub[nxt] = time.perf_counter()
+                K.submit_prepared(h, preps[nxt])
+                nxt += 1
+        if cnt == 0 and rc == K.TIMEOUT:
+            raise RuntimeError("engine idle with nodes outstanding")
+    return res, lat
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--cert-period", type=int, default=8)
+    ap.add_argument("--cert-period", type=int, default=16)
+    ap.add_argument("--window", type=int, default=1,
+                    help="batches in flight (the next is submitted when one completes)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-nodes", type=int, default=24,
                     help="oracle sample size for the CPU baseline (0 = skip)")
@@ -363,20 +409,16 @@ def main():
     batches = [W.launch_nodes_5000x200(i, args.batch) for i in range(total)]
     # node descriptors are marshalled before the timed region (they cross
     # PCIe inside submit_nodes, in the timed region)
-    preps = [K.PreparedNodes(b, tags=list(range(len(b))), rel_tol=args.tol) for b in batches]
-    out = (K.BoundResult * args.batch)()
+    preps = [K.PreparedNodes(b, tags=[s * args.batch + i for i in range(len(b))], rel_tol=args.tol)
+             for s, b in enumerate(batches)]
+    out = (K.BoundResult * (2 * args.batch))()
 
-    for w in range(args.warmup):
-        run_batch(K, h, preps[w], out)
+    run_stream(K, h, preps[:args.warmup], out, args.window)
     log(f"warmup done ({args.warmup} steps)")
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat_all, results = [], []
-    for s in range(args.steps):
-        res, lat = run_batch(K, h, preps[args.warmup + s], out)
-        lat_all += lat
-        results += res
+    results, lat_all = run_stream(K, h, preps[args.warmup:args.warmup + args.steps], out, args.window)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     iters = [r[2] for r in results]
@@ -388,8 +430,8 @@ def main():
 
     # kernel-timed pass (same configuration, fresh batches)
     K.kernel_stats(h, 1)
-    for s in range(args.profile_steps):
-        run_batch(K, h, preps[args.warmup + args.steps + s], out)
+    if args.profile_steps:
+        run_stream(K, h, preps[args.warmup + args.steps:], out, args.window)
     ks = K.kernel_stats(h, 0)
     n, p = inst.n, inst.p
     launches = ks["launches"]
@@ -489,10 +531,11 @@ def main():
                    "loss": "logistic", "nodes_per_step": args.batch,
                    "batch_width": info["batch_width"], "rel_tol": args.tol,
                    "cert_period": args.cert_period, "certificate_dtype": "f64",
+                   "batches_in_flight": args.window,
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
-                       "measure": "submit of the step's batch to the node's result at poll"},
+                       "measure": "submission of the node's batch to its result at poll"},
         "iterations": {"mean": round(float(np.mean(iters)), 2), "max": int(np.max(iters))},
         "not_converged": int(status_bad),
         "max_rel_gap": float(np.max(gaps)),
