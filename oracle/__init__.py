@@ -79,6 +79,8 @@ def _load():
             "orc_round_branch": (None, [P, vp, vp, vp, vp, vp]),
             "orc_support_value": (d, [P, vp, i, d, d, i, vp]),
             "orc_bnb": (i, [P, d, i, d, d, ctypes.c_long, vp, vp, vp]),
+            "orc_rashomon": (ctypes.c_long, [P, d, ctypes.c_long, d, i, ctypes.c_long,
+                                             ctypes.c_long, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -202,6 +204,21 @@ class Problem:
         return dict(objective=info[0], lower_bound=info[1], rel_gap=info[2],
                     nodes=int(info[3]), status=int(info[4]), updates=int(info[5]),
                     support=supp[supp >= 0].copy(), beta=beta)
+
+
+    def rashomon(self, eps, cap=0, node_tol=1e-9, node_max_iter=100000, max_nodes=1_000_000,
+                 max_out=100000):
+        """Support-level Rashomon set: list of (support tuple, value) by value."""
+        supp = np.full((max_out, self.k), -1, dtype=np.int32)
+        vals = np.empty(max_out)
+        info = np.empty(4)
+        cnt = _load().orc_rashomon(self.ref, float(eps), int(cap), float(node_tol),
+                                   int(node_max_iter), int(max_nodes), int(max_out),
+                                   _ptr(supp), _ptr(vals), _ptr(info))
+        out = [(tuple(int(j) for j in supp[r] if j >= 0), float(vals[r]))
+               for r in range(min(cnt, max_out))]
+        return dict(set=out, count=int(cnt), optimum=info[0], threshold=info[1],
+                    nodes=int(info[2]), status=int(info[3]))
 
 
 # scalar helpers ------------------------------------------------------------

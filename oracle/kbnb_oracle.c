@@ -703,3 +703,197 @@ int orc_bnb(const orc_problem *P, double node_tol, int node_max_iter,
     }
     return status;
 }
+
+
+/* ------------------------------------------------------------------------ */
+/* Rashomon-set collection (Sec. 4.5, "Rashomon-set collection").            */
+/*                                                                           */
+/* The same best-bound tree with two changes:                                */
+/*  - a node is pruned only when its bound exceeds the threshold             */
+/*    tau = min((1 + eps) UB, v_(cap)), v_(cap) the cap-th best value found  */
+/*    (+inf before cap supports are known, or when cap = 0);                 */
+/*  - a node is a leaf only when no indicator is left to decide: kbar = 0    */
+/*    (the free coordinates are forced to zero) or no free coordinate.  Its  */
+/*    support is J1, and v(J1) is computed directly.                         */
+/* Every leaf and every re-optimised rounding support with value <= tau is   */
+/* recorded.  Each support with |S| <= k is the J1 of exactly one leaf, and   */
+/* a pruned node contains only supports with v(S) >= its bound > tau >=       */
+/* (1 + eps) Phi*, so at the end the recorded supports with value at most    */
+/* the final threshold are the set.                                          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int *supp;     /* n x k, ascending, -1 padded */
+    double *val;
+    long n, cap;
+} orc_pool;
+
+static int pool_find(const orc_pool *pl, const int *s, int k)
+{
+    for (long i = 0; i < pl->n; ++i)
+        if (memcmp(pl->supp + i * k, s, sizeof(int) * (size_t)k) == 0) return 1;
+    return 0;
+}
+
+static void pool_add(orc_pool *pl, const int *s, int len, int k, double v)
+{
+    int key[256];
+    for (int r = 0; r < k; ++r) key[r] = r < len ? s[r] : -1;
+    if (pool_find(pl, key, k)) return;
+    if (pl->n == pl->cap) {
+        pl->cap = pl->cap ? 2 * pl->cap : 64;
+        pl->supp = (int *)realloc(pl->supp, sizeof(int) * (size_t)(pl->cap * k));
+        pl->val = (double *)realloc(pl->val, sizeof(double) * (size_t)pl->cap);
+    }
+    memcpy(pl->supp + pl->n * k, key, sizeof(int) * (size_t)k);
+    pl->val[pl->n] = v;
+    ++pl->n;
+}
+
+/* the c-th smallest recorded value (1-based), +inf when fewer are recorded */
+static double pool_kth(const orc_pool *pl, long c)
+{
+    if (c <= 0 || pl->n < c) return INFINITY;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)pl->n);
+    memcpy(tmp, pl->val, sizeof(double) * (size_t)pl->n);
+    /* selection by repeated minimum: plain and small */
+    double v = INFINITY;
+    for (long r = 0; r < c; ++r) {
+        long bi = -1;
+        for (long i = 0; i < pl->n; ++i)
+            if (bi < 0 || tmp[i] < tmp[bi]) bi = i;
+        v = tmp[bi];
+        tmp[bi] = INFINITY;
+    }
+    free(tmp);
+    return v;
+}
+
+static int g_pool_k;
+static const orc_pool *g_pool_sort;
+static int pool_cmp(const void *a, const void *b)
+{
+    const long i = *(const long *)a, j = *(const long *)b;
+    const double vi = g_pool_sort->val[i], vj = g_pool_sort->val[j];
+    if (vi < vj) return -1;
+    if (vi > vj) return 1;
+    return memcmp(g_pool_sort->supp + i * g_pool_k, g_pool_sort->supp + j * g_pool_k,
+                  sizeof(int) * (size_t)g_pool_k);
+}
+
+long orc_rashomon(const orc_problem *P, double eps, long cap, double node_tol,
+                  int node_max_iter, long max_nodes, long max_out,
+                  int *out_supports, double *out_values, double *info)
+{
+    const int p = P->p, k = P->k;
+    const double L = orc_lipschitz(P);
+    orc_heap H = {0};
+    orc_pool pl = {0};
+    long seq = 0, processed = 0;
+    double UB = INFINITY;
+    double *beta = (double *)malloc(sizeof(double) * (size_t)p);
+    double *bre = (double *)malloc(sizeof(double) * (size_t)p);
+    int *supp = (int *)malloc(sizeof(int) * (size_t)(p + 1));
+    int status = 0;
+
+    orc_node root;
+    root.st = (signed char *)calloc((size_t)p, 1);
+    root.warm = (double *)calloc((size_t)p, sizeof(double));
+    root.lb = -INFINITY;
+    root.depth = 0;
+    root.seq = seq++;
+    heap_push(&H, root);
+
+#define TAU() (fmin((1.0 + eps) * UB, pool_kth(&pl, cap)))
+    while (H.n > 0) {
+        if (processed >= max_nodes) {
+            status = 1;
+            break;
+        }
+        orc_node nd = heap_pop(&H);
+        if (nd.lb > TAU()) {
+            free(nd.st); free(nd.warm);
+            continue;
+        }
+        const int kbar = orc_kbar(P, nd.st);
+        int pf = 0, len = 0;
+        for (int j = 0; j < p; ++j)
+            if (nd.st[j] == ORC_FREE) ++pf;
+        if (kbar == 0 || pf == 0) {
+            /* leaf: the support is J1 */
+            for (int j = 0; j < p; ++j)
+                if (nd.st[j] == ORC_IN) supp[len++] = j;
+            const double v = orc_support_value(P, supp, len, L, 1e-13, 50000, bre);
+            ++processed;
+            if (v < UB) UB = v;
+            if (v <= TAU()) pool_add(&pl, supp, len, k, v);
+            free(nd.st); free(nd.warm);
+            continue;
+        }
+        double ninfo[5];
+        orc_node_bound(P, nd.st, L, nd.warm, node_tol, node_max_iter, INFINITY, 0.0, beta, ninfo);
+        ++processed;
+        const double lb = ninfo[0] > nd.lb ? ninfo[0] : nd.lb;
+        /* rounding and re-optimisation: a feasible support and its value */
+        int jstar = -1;
+        orc_round_branch(P, nd.st, beta, supp, &len, &jstar);
+        const double v = orc_support_value(P, supp, len, L, 1e-13, 50000, bre);
+        if (v < UB) UB = v;
+        if (v <= TAU()) pool_add(&pl, supp, len, k, v);
+        if (lb > TAU()) {
+            free(nd.st); free(nd.warm);
+            continue;
+        }
+        if (jstar < 0)  /* no free coordinate is nonzero: branch on the first free one */
+            for (int j = 0; j < p && jstar < 0; ++j)
+                if (nd.st[j] == ORC_FREE) jstar = j;
+        orc_node c0, c1;
+        c0.st = (signed char *)malloc((size_t)p);
+        c1.st = (signed char *)malloc((size_t)p);
+        memcpy(c0.st, nd.st, (size_t)p);
+        memcpy(c1.st, nd.st, (size_t)p);
+        c0.st[jstar] = ORC_OUT;
+        c1.st[jstar] = ORC_IN;
+        c0.warm = (double *)malloc(sizeof(double) * (size_t)p);
+        c1.warm = (double *)malloc(sizeof(double) * (size_t)p);
+        memcpy(c0.warm, beta, sizeof(double) * (size_t)p);
+        memcpy(c1.warm, beta, sizeof(double) * (size_t)p);
+        c0.warm[jstar] = 0.0;
+        c0.lb = c1.lb = lb;
+        c0.depth = c1.depth = nd.depth + 1;
+        c0.seq = seq++;
+        c1.seq = seq++;
+        heap_push(&H, c0);
+        heap_push(&H, c1);
+        free(nd.st); free(nd.warm);
+    }
+    const double tau = TAU();
+#undef TAU
+    while (H.n > 0) {
+        orc_node nd = heap_pop(&H);
+        free(nd.st); free(nd.warm);
+    }
+    free(H.a);
+    /* the set: recorded supports within the final threshold, by value */
+    long *ord = (long *)malloc(sizeof(long) * (size_t)(pl.n + 1));
+    long cnt = 0;
+    for (long i = 0; i < pl.n; ++i)
+        if (pl.val[i] <= tau) ord[cnt++] = i;
+    g_pool_k = k;
+    g_pool_sort = &pl;
+    qsort(ord, (size_t)cnt, sizeof(long), pool_cmp);
+    if (cap > 0 && cnt > cap) cnt = cap;
+    for (long r = 0; r < cnt && r < max_out; ++r) {
+        memcpy(out_supports + r * k, pl.supp + ord[r] * k, sizeof(int) * (size_t)k);
+        out_values[r] = pl.val[ord[r]];
+    }
+    if (info) {
+        info[0] = UB;
+        info[1] = tau;
+        info[2] = (double)processed;
+        info[3] = status;
+    }
+    free(ord);
+    free(pl.supp); free(pl.val);
+    free(beta); free(bre); free(supp);
+    return cnt;
+}

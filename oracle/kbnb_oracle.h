@@ -77,6 +77,17 @@ int orc_bnb(const orc_problem *P, double node_tol, int node_max_iter,
             double gap_tol, double prune_rel, long max_nodes,
             int *support_out, double *beta_out, double *info);
 
+/* Support-level Rashomon set (Sec. 4.5): every support S with |S| <= k and
+ * v(S) <= (1 + eps) Phi*, or the best `cap` of them when cap > 0.
+ * out_supports: max_out x k entries (ascending, -1 padded); out_values:
+ * max_out.  Entries are ordered by value, ties by the support sequence.
+ * info[0..3] = Phi*, final threshold, nodes bounded, status (0 complete,
+ * 1 node limit).  Returns the number of entries in the set (only the first
+ * max_out are written). */
+long orc_rashomon(const orc_problem *P, double eps, long cap, double node_tol,
+                  int node_max_iter, long max_nodes, long max_out,
+                  int *out_supports, double *out_values, double *info);
+
 #ifdef __cplusplus
 }
 #endif

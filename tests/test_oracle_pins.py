@@ -625,3 +625,53 @@ def test_bnb_root_bound_below_optimum():
     root = P.node_bound(np.zeros(30, np.int8), tol=1e-10)
     res = P.bnb()
     assert root["lb"] <= res["objective"] * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Rashomon-set collection (Sec. 4.5): brute force over every support with
+# |S| <= k.  The set's definition is v(S) <= (1 + eps) Phi*, with v computed
+# by the (separately pinned) support_value; a cap N keeps the N best.
+# ---------------------------------------------------------------------------
+def _brute_rashomon(P, p, k, eps, cap=0):
+    vals = {}
+    for size in range(0, k + 1):
+        for S in itertools.combinations(range(p), size):
+            vals[S] = P.support_value(list(S))[0]
+    phi = min(vals.values())
+    tau = (1 + eps) * phi
+    inside = sorted(((v, S) for S, v in vals.items() if v <= tau), key=lambda t: (t[0], t[1]))
+    if cap:
+        inside = inside[:cap]
+    return phi, tau, [(S, v) for v, S in inside]
+
+
+RASHOMON_CASES = [  # loss, n, p, k, seed, eps, cap
+    (0, 60, 10, 3, 50, 0.05, 0), (0, 60, 10, 3, 50, 0.3, 0), (1, 80, 9, 3, 50, 0.05, 0),
+    (1, 80, 9, 3, 50, 0.15, 0), (1, 40, 8, 3, 7, 0.05, 0), (1, 40, 8, 3, 7, 0.2, 12),
+    (0, 60, 10, 3, 51, 0.5, 5)]
+
+
+@pytest.mark.parametrize("loss,n,p,k,seed,eps,cap", RASHOMON_CASES)
+def test_rashomon_matches_brute_force(loss, n, p, k, seed, eps, cap):
+    inst = W.small_instance(n, p, k, loss, seed=seed, rho=0.5)
+    P = oracle.Problem.from_instance(inst)
+    phi, tau, want = _brute_rashomon(P, p, k, eps, cap)
+    got = P.rashomon(eps, cap=cap)
+    assert got["status"] == 0
+    assert got["optimum"] == pytest.approx(phi, rel=1e-12)
+    assert [S for S, _ in got["set"]] == [S for S, _ in want]
+    for (_, v1), (_, v2) in zip(got["set"], want):
+        assert v1 == pytest.approx(v2, rel=1e-12)
+
+
+def test_rashomon_brute_force_cases_include_smaller_supports():
+    """The pin above is only meaningful if some set holds supports of size
+    < k (a leaf rule stopping at #free <= kbar would miss them) and some cap
+    cuts a set short."""
+    inst = W.small_instance(80, 9, 3, 1, seed=50, rho=0.5)
+    P = oracle.Problem.from_instance(inst)
+    _, _, want = _brute_rashomon(P, 9, 3, 0.15)
+    assert any(len(S) < 3 for S, _ in want) and any(len(S) == 3 for S, _ in want)
+    inst = W.small_instance(40, 8, 3, 1, seed=7, rho=0.5)
+    P = oracle.Problem.from_instance(inst)
+    assert len(_brute_rashomon(P, 8, 3, 0.2)[2]) > 12
