@@ -179,6 +179,9 @@ typedef struct {
     int32_t max_fista_iters; /* per node; 0 -> 20000 */
     int64_t max_nodes;       /* 0 -> unlimited */
     double log_every_s;      /* > 0: one progress line on stderr at this period; 0 -> silent */
+    int32_t rashomon;        /* nonzero: also collect the support-level Rashomon set */
+    int32_t rashomon_n;      /* keep only the best N supports (0 -> all) */
+    double rashomon_eps;     /* set threshold (1 + eps) Phi*, eps >= 0 */
 } kbnb_bnb_options;
 
 typedef struct {
@@ -193,6 +196,7 @@ typedef struct {
     double *beta;       /* caller buffer of p entries (or NULL): incumbent coefficients */
     int64_t incumbent_updates;
     double seconds;
+    int64_t rashomon_size; /* entries of the collected set (0 unless collecting) */
 } kbnb_bnb_result;
 
 /*
@@ -207,6 +211,30 @@ typedef struct {
  */
 int branch_and_bound(kbnb_problem *prob, const kbnb_bnb_options *opts,
                      kbnb_bnb_result *result);
+
+/*
+ * Support-level Rashomon set (Sec. 4.5, "Rashomon-set collection"): with
+ * opts->rashomon set, branch_and_bound also collects every support S with
+ * |S| <= k and v(S) <= (1 + rashomon_eps) Phi* (or the best rashomon_n of
+ * them).  A node is then pruned only when its bound exceeds
+ * tau = min((1 + eps) UB, v_(N)) (v_(N) the N-th best value found so far),
+ * and is a leaf only when no indicator is undecided (kbar = 0 or nothing
+ * free); the support J1 of every leaf and every re-optimised rounding
+ * support are evaluated, and those within the final threshold form the set.
+ * Values are certified to the re-optimisation tolerance
+ * (min(1e-7, node_rel_tol / 10) relative), so a support whose value is that
+ * close to the threshold may fall on either side.
+ *
+ * rashomon_entry -- entry i (0-based, by value, ties by the ascending index
+ * sequence) of the set collected by the last such call on `prob`:
+ * support (k entries, ascending, -1 padded), its length, beta (NULL or p
+ * entries: the coefficients on the support, 0 elsewhere) and v(S).  The set
+ * is stored compactly (a prefix trie of the supports, one flat coefficient
+ * array) and freed with the problem.  KBNB_E_INVALID_ARGUMENT when i is out
+ * of range or nothing was collected.
+ */
+int rashomon_entry(kbnb_problem *prob, int64_t i, int32_t *support, int32_t *support_len,
+                   double *beta, double *value);
 
 typedef struct {
     const int32_t *widths;  /* candidate batch widths; NULL -> 64, 128, ..., 2048 */

@@ -64,7 +64,9 @@ class BoundResult(ctypes.Structure):
 class BnbOptions(ctypes.Structure):
     _fields_ = [("time_limit_s", ctypes.c_double), ("rel_gap_tol", ctypes.c_double),
                 ("node_rel_tol", ctypes.c_double), ("max_fista_iters", ctypes.c_int32),
-                ("max_nodes", ctypes.c_int64), ("log_every_s", ctypes.c_double)]
+                ("max_nodes", ctypes.c_int64), ("log_every_s", ctypes.c_double),
+                ("rashomon", ctypes.c_int32), ("rashomon_n", ctypes.c_int32),
+                ("rashomon_eps", ctypes.c_double)]
 
 
 class BnbResult(ctypes.Structure):
@@ -72,7 +74,8 @@ class BnbResult(ctypes.Structure):
                 ("rel_gap", ctypes.c_double), ("nodes", ctypes.c_int64),
                 ("status", ctypes.c_int32), ("support_len", ctypes.c_int32),
                 ("support", ctypes.c_void_p), ("beta", ctypes.c_void_p),
-                ("incumbent_updates", ctypes.c_int64), ("seconds", ctypes.c_double)]
+                ("incumbent_updates", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("rashomon_size", ctypes.c_int64)]
 
 
 class TuneOptions(ctypes.Structure):
@@ -90,8 +93,8 @@ class TuneResult(ctypes.Structure):
 
 
 EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
-           "branch_and_bound", "autotune", "last_error", "prox_batch", "certify_batch",
-           "problem_info", "kernel_stats"]
+           "branch_and_bound", "rashomon_entry", "autotune", "last_error", "prox_batch",
+           "certify_batch", "problem_info", "kernel_stats"]
 
 _lib = None
 
@@ -326,17 +329,37 @@ def bound_nodes(h: Handle, nodes, **kw):
 
 
 def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=0.0,
-                     max_fista_iters=0, max_nodes=0, log_every_s=0.0):
+                     max_fista_iters=0, max_nodes=0, log_every_s=0.0, rashomon_eps=None,
+                     rashomon_n=0):
+    """rashomon_eps (>= 0): also collect the support-level Rashomon set (the
+    best rashomon_n when nonzero), returned as "rashomon": a list of
+    (support tuple, value, beta) ordered by value."""
     sup = np.full(h.k, -1, np.int32)
     beta = np.zeros(h.p)
     o = BnbOptions(time_limit_s=time_limit_s, rel_gap_tol=rel_gap_tol,
                    node_rel_tol=node_rel_tol, max_fista_iters=max_fista_iters,
-                   max_nodes=max_nodes, log_every_s=log_every_s)
+                   max_nodes=max_nodes, log_every_s=log_every_s,
+                   rashomon=0 if rashomon_eps is None else 1, rashomon_n=int(rashomon_n),
+                   rashomon_eps=0.0 if rashomon_eps is None else float(rashomon_eps))
     r = BnbResult(support=_p(sup), beta=_p(beta))
     _check(load().branch_and_bound(h.ptr, ctypes.byref(o), ctypes.byref(r)))
-    return dict(objective=r.objective, lower_bound=r.lower_bound, rel_gap=r.rel_gap,
-                nodes=r.nodes, status=r.status, support=sup[:r.support_len].copy(),
-                beta=beta, incumbent_updates=r.incumbent_updates, seconds=r.seconds)
+    out = dict(objective=r.objective, lower_bound=r.lower_bound, rel_gap=r.rel_gap,
+               nodes=r.nodes, status=r.status, support=sup[:r.support_len].copy(),
+               beta=beta, incumbent_updates=r.incumbent_updates, seconds=r.seconds)
+    if rashomon_eps is not None:
+        out["rashomon"] = [rashomon_entry(h, i) for i in range(r.rashomon_size)]
+    return out
+
+
+def rashomon_entry(h: Handle, i):
+    """Entry i of the last collected Rashomon set: (support tuple, value, beta)."""
+    sup = np.full(h.k, -1, np.int32)
+    beta = np.zeros(h.p)
+    n = ctypes.c_int32(0)
+    v = ctypes.c_double(0.0)
+    _check(load().rashomon_entry(h.ptr, ctypes.c_int64(int(i)), _p(sup), ctypes.byref(n),
+                                 _p(beta), ctypes.byref(v)))
+    return tuple(int(j) for j in sup[:n.value]), v.value, beta
 
 
 def prox_batch(h: Handle, states, u, eta):

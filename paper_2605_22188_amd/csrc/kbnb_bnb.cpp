@@ -1,5 +1,6 @@
 // kbnb_bnb.cpp -- best-bound branch and bound on top of submit_nodes /
-// poll_bounds (paper Sec. 4.1, Fig. 1; Sec. 4.3).
+// poll_bounds (paper Sec. 4.1, Fig. 1; Sec. 4.3), and the support-level
+// Rashomon-set collection on the same tree (Sec. 4.5).
 //
 // The host owns the tree: the open-node queue ordered by parent bound (deeper
 // first on ties, then first-in), the incumbent and the global bound.  The
@@ -10,14 +11,21 @@
 //     re-optimised on the device as the node J1 = support, J0 = complement
 //     (that relaxation is exact, its primal value is an attained objective),
 //     unless the same support was already evaluated;
-//   - a node whose budget cannot bind (kbar = 0 or #free <= kbar) is closed:
-//     its relaxation equals the value of its rounding support;
-//   - otherwise it branches on the returned index into z_j = 0 and z_j = 1
-//     children, both warm-started from the parent iterate (z_j = 0 zeroes
-//     beta_j).
-// Pruning: bound >= UB - 1e-6 |UB|.  Termination: no open or in-flight node,
-// or (UB - global bound) <= rel_gap_tol * |UB|.  The reported lower bound is
-// the least bound over every leaf of the explored tree (pruned nodes, closed
+//   - optimal-support mode: a node whose budget cannot bind (kbar = 0 or
+//     #free <= kbar) is closed: its relaxation equals the value of its
+//     rounding support;
+//   - Rashomon mode: a node is a leaf only when no indicator is undecided
+//     (kbar = 0 or nothing free); its support J1 is evaluated like a
+//     rounding support.  Every support evaluated within the threshold is
+//     recorded;
+//   - otherwise it branches on the returned index (the first free index if
+//     every free coordinate is zero) into z_j = 0 and z_j = 1 children, both
+//     warm-started from the parent iterate (z_j = 0 zeroes beta_j).
+// Pruning: optimal-support mode, bound >= UB - 1e-6 |UB|; Rashomon mode,
+// bound > tau = min((1 + eps) UB, v_(N)), v_(N) the N-th best recorded value.
+// Termination: no open or in-flight node, or (optimal-support mode) (UB -
+// global bound) <= rel_gap_tol * |UB|.  The reported lower bound is the
+// least bound over every leaf of the explored tree (pruned nodes, closed
 // nodes) and every node left open, so it is certified even when pruning used
 // the relative slack.
 #include <algorithm>
@@ -26,6 +34,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <queue>
 #include <set>
 #include <string>
@@ -53,10 +63,64 @@ struct OpenCmp {
     }
 };
 
+enum FlightKind { FL_NODE, FL_SUPPORT };
+
 struct Flight {
-    bool reopt = false;
+    FlightKind kind = FL_NODE;
     Open *node = nullptr;           // bound node
-    std::vector<int32_t> support;   // re-optimisation support
+    std::vector<int32_t> support;   // evaluated support (ascending)
+};
+
+// Compact store of a collected set: the supports in a prefix trie over their
+// ascending index sequences (supports that share a prefix share its nodes),
+// each entry's |S| coefficients in one flat array at its own offset.
+struct RashomonPool {
+    struct TNode {
+        int32_t index, parent, child, sibling;
+    };
+    std::vector<TNode> trie{TNode{-1, -1, -1, -1}};  // node 0: the empty prefix
+    std::vector<int32_t> entry_node;
+    std::vector<double> value;
+    std::vector<int64_t> coef_off;
+    std::vector<double> coef;
+
+    int32_t path(const std::vector<int32_t> &s)
+    {
+        int32_t cur = 0;
+        for (int32_t j : s) {
+            int32_t c = trie[cur].child;
+            while (c >= 0 && trie[c].index != j) c = trie[c].sibling;
+            if (c < 0) {
+                c = (int32_t)trie.size();
+                trie.push_back(TNode{j, cur, -1, trie[cur].child});
+                trie[cur].child = c;
+            }
+            cur = c;
+        }
+        return cur;
+    }
+    void add(const std::vector<int32_t> &s, double v, const std::vector<double> &beta)
+    {
+        entry_node.push_back(path(s));
+        value.push_back(v);
+        coef_off.push_back((int64_t)coef.size());
+        for (int32_t j : s) coef.push_back(beta[j]);
+    }
+    std::vector<int32_t> support(size_t i) const
+    {
+        std::vector<int32_t> s;
+        for (int32_t c = entry_node[i]; c > 0; c = trie[c].parent) s.push_back(trie[c].index);
+        std::reverse(s.begin(), s.end());
+        return s;
+    }
+};
+
+std::mutex g_pool_mu;
+std::map<const kbnb_problem *, std::unique_ptr<RashomonPool>> g_pools;
+
+struct Candidate {
+    double value;
+    std::vector<double> beta;
 };
 
 }  // namespace
@@ -64,6 +128,39 @@ struct Flight {
 extern "C" int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
 namespace kbnb {
 int set_error(int code, const char *fmt, ...);
+// the collected set of a problem that is being destroyed
+void drop_rashomon(const kbnb_problem *P)
+{
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    g_pools.erase(P);
+}
+}  // namespace kbnb
+
+extern "C" int rashomon_entry(kbnb_problem *P, int64_t i, int32_t *support, int32_t *support_len,
+                              double *beta, double *value)
+{
+    if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (!support || !support_len || !value)
+        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "support, support_len and value are required");
+    int64_t info[9];
+    double dinfo[4];
+    int rc = problem_info(P, info, dinfo);
+    if (rc) return rc;
+    const int p = (int)info[1], k = (int)info[2];
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    auto it = g_pools.find(P);
+    if (it == g_pools.end() || i < 0 || i >= (int64_t)it->second->value.size())
+        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "no Rashomon entry %lld", (long long)i);
+    const RashomonPool &pl = *it->second;
+    const std::vector<int32_t> s = pl.support((size_t)i);
+    for (int r = 0; r < k; ++r) support[r] = r < (int)s.size() ? s[r] : -1;
+    *support_len = (int32_t)s.size();
+    *value = pl.value[(size_t)i];
+    if (beta) {
+        std::fill(beta, beta + p, 0.0);
+        for (size_t r = 0; r < s.size(); ++r) beta[s[r]] = pl.coef[(size_t)pl.coef_off[(size_t)i] + r];
+    }
+    return KBNB_OK;
 }
 
 extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kbnb_bnb_result *res)
@@ -71,6 +168,10 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");
     if (!opt || !res || !res->support)
         return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "options, result and result->support are required");
+    const bool rs = opt->rashomon != 0;
+    if (rs && !(opt->rashomon_eps >= 0 && std::isfinite(opt->rashomon_eps)))
+        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "rashomon_eps must be finite and >= 0");
+    if (rs && opt->rashomon_n < 0) return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "rashomon_n must be >= 0");
     int64_t info[9];
     double dinfo[4];
     int rc = problem_info(P, info, dinfo);
@@ -78,21 +179,56 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     const int p = (int)info[1], k = (int)info[2], m = (int)info[3];
     const double gap_tol = opt->rel_gap_tol > 0 ? opt->rel_gap_tol : 1e-6;
     const double node_tol = opt->node_rel_tol > 0 ? opt->node_rel_tol : 1e-6;
+    const double support_tol = std::min(1e-7, 0.1 * node_tol);
     const double prune_rel = 1e-6;
     const int max_it = opt->max_fista_iters > 0 ? opt->max_fista_iters : 20000;
+    const double eps = rs ? opt->rashomon_eps : 0.0;
+    const int64_t capN = rs ? opt->rashomon_n : 0;
     const auto t0 = std::chrono::steady_clock::now();
     auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
 
     std::priority_queue<Open *, std::vector<Open *>, OpenCmp> open;
     std::map<uint64_t, Flight> flight;
     std::multiset<double> flight_lb;
-    std::set<std::vector<int32_t>> evaluated;
+    std::set<std::vector<int32_t>> evaluated;            // supports submitted or known
+    std::map<std::vector<int32_t>, Candidate> recorded;  // Rashomon mode: within the threshold when found
+    std::multiset<double> recorded_vals;
     uint64_t seq = 0, next_tag = 1;
     double UB = INFINITY;
     std::vector<int32_t> best_support;
     std::vector<double> best_beta(p, 0.0);
     int64_t nodes = 0, updates = 0;
     int status = 0;
+
+    // Rashomon threshold: (1 + eps) UB, capped by the N-th best recorded value
+    auto tau = [&]() {
+        const double t = (1.0 + eps) * UB;
+        if (capN > 0 && (int64_t)recorded_vals.size() >= capN) {
+            auto it = recorded_vals.begin();
+            std::advance(it, capN - 1);
+            return std::min(t, *it);
+        }
+        return t;
+    };
+    auto prunable = [&](double lb) { return rs ? lb > tau() : lb >= UB - prune_rel * std::fabs(UB); };
+    auto is_leaf = [&](const Open *o) {
+        const int kbar = k - (int)o->in.size();
+        const int pf = p - (int)o->in.size() - (int)o->out.size();
+        return kbar <= 0 || pf == 0;
+    };
+    // value v of an evaluated support S with iterate beta
+    auto take_support = [&](const std::vector<int32_t> &S, double v, const double *beta) {
+        if (std::isfinite(v) && v < UB) {
+            UB = v;
+            best_support = S;
+            best_beta.assign(beta, beta + p);
+            ++updates;
+        }
+        if (rs && std::isfinite(v) && v <= tau() && !recorded.count(S)) {
+            recorded[S] = Candidate{v, std::vector<double>(beta, beta + p)};
+            recorded_vals.insert(v);
+        }
+    };
 
     Open *root = new Open();
     root->lb = -INFINITY;
@@ -103,24 +239,54 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     const int cap_flight = 2 * m;
     std::vector<kbnb_node_desc> batch;
     std::vector<std::vector<double>> warm_store;
+    std::vector<std::vector<int32_t>> set_store;  // index lists of support evaluations
     std::vector<kbnb_bound_result> out(m);
     std::vector<int32_t> sup((size_t)m * k);
     std::vector<double> betas((size_t)m * p);
-    std::vector<int32_t> full_out;
-    std::vector<std::vector<int32_t>> outs_store;
     double global_lb = -INFINITY;
     double leaf_lb = INFINITY;  // least bound of the discarded subtrees
     double last_log = 0.0;
 
-    auto prunable = [&](double lb) { return lb >= UB - prune_rel * std::fabs(UB); };
+    // a support evaluation: the node J1 = S, J0 = complement
+    auto support_desc = [&](const std::vector<int32_t> &S, std::vector<kbnb_node_desc> &dst) {
+        std::vector<char> ins(p, 0);
+        for (int j : S) ins[j] = 1;
+        std::vector<int32_t> comp;
+        for (int j = 0; j < p; ++j)
+            if (!ins[j]) comp.push_back(j);
+        set_store.push_back(S);
+        set_store.push_back(std::move(comp));
+        kbnb_node_desc d{};
+        const uint64_t tag = next_tag++;
+        d.tag = tag;
+        d.upper_bound = INFINITY;
+        d.rel_tol = support_tol;
+        d.max_iters = max_it;
+        dst.push_back(d);
+        Flight f;
+        f.kind = FL_SUPPORT;
+        f.support = S;
+        flight[tag] = f;
+        evaluated.insert(S);
+    };
+    // the index pointers of support evaluations, once set_store no longer moves
+    auto bind_sets = [&](std::vector<kbnb_node_desc> &v) {
+        size_t si = 0;
+        for (auto &d : v) {
+            if (flight[d.tag].kind != FL_SUPPORT) continue;
+            const std::vector<int32_t> &in = set_store[si++];
+            const std::vector<int32_t> &ou = set_store[si++];
+            d.n_in = (int32_t)in.size();
+            d.fixed_in = in.data();
+            d.n_out = (int32_t)ou.size();
+            d.fixed_out = ou.data();
+        }
+    };
 
     for (;;) {
         // drop open nodes that the incumbent prunes (the queue is ordered by bound)
         while (!open.empty() && prunable(open.top()->lb)) {
-            Open *o = open.top();
-            open.pop();
-            leaf_lb = std::min(leaf_lb, o->lb);
-            delete o;
+            leaf_lb = std::min(leaf_lb, open.top()->lb);
             // every remaining node has a bound at least as large
             while (!open.empty()) {
                 delete open.top();
@@ -130,29 +296,39 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         double lb_open = open.empty() ? INFINITY : open.top()->lb;
         double lb_fl = flight_lb.empty() ? INFINITY : *flight_lb.begin();
         global_lb = std::min(lb_open, lb_fl);
-        bool reopt_pending = false;
+        bool support_pending = false;
         for (auto &f : flight)
-            if (f.second.reopt) { reopt_pending = true; break; }
+            if (f.second.kind == FL_SUPPORT) { support_pending = true; break; }
         if (open.empty() && flight.empty()) break;
-        if (std::isfinite(UB) && !reopt_pending && global_lb >= UB - gap_tol * std::fabs(UB)) break;
+        if (!rs && std::isfinite(UB) && !support_pending && global_lb >= UB - gap_tol * std::fabs(UB)) break;
         if (opt->time_limit_s > 0 && elapsed() > opt->time_limit_s) { status = 1; break; }
         if (opt->max_nodes > 0 && nodes >= opt->max_nodes) { status = 2; break; }
         if (opt->log_every_s > 0 && elapsed() - last_log >= opt->log_every_s) {
             last_log = elapsed();
-            fprintf(stderr, "[bnb] %.1fs nodes %lld open %zu in flight %zu UB %.10g LB %.10g\n",
+            fprintf(stderr, "[bnb] %.1fs nodes %lld open %zu in flight %zu UB %.10g LB %.10g%s\n",
                     last_log, (long long)nodes, open.size(), flight.size(), UB,
-                    std::min(global_lb, leaf_lb));
+                    std::min(global_lb, leaf_lb), rs ? " (collecting)" : "");
             fflush(stderr);
         }
 
         // fill the device
         batch.clear();
         warm_store.clear();
-        outs_store.clear();
+        set_store.clear();
         int room = cap_flight - (int)flight.size();
         while (room > 0 && !open.empty()) {
             Open *o = open.top();
             open.pop();
+            if (rs && is_leaf(o)) {
+                // Rashomon leaf: its support J1 is evaluated (once)
+                if (!evaluated.count(o->in)) {
+                    support_desc(o->in, batch);
+                    --room;
+                }
+                leaf_lb = std::min(leaf_lb, o->lb);
+                delete o;
+                continue;
+            }
             kbnb_node_desc d{};
             const uint64_t tag = next_tag++;
             d.tag = tag;
@@ -164,7 +340,9 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 warm_store.emplace_back(p, 0.0);
                 for (size_t r = 0; r < o->wi.size(); ++r) warm_store.back()[o->wi[r]] = o->wv[r];
             }
-            d.upper_bound = UB;
+            // the engine stops a node at bound >= ub - 1e-6 |ub|; in Rashomon
+            // mode that must imply bound > tau
+            d.upper_bound = rs ? tau() * (1.0 + 4e-6) : UB;
             d.rel_tol = node_tol;
             d.max_iters = max_it;
             batch.push_back(d);
@@ -174,24 +352,26 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             flight_lb.insert(o->lb);
             --room;
         }
-        // warm-start pointers are set once the storage no longer moves
+        // warm-start and index pointers are set once the storage no longer moves
         {
             size_t wsi = 0;
             for (auto &d : batch) {
-                Open *o = flight[d.tag].node;
-                if (!o->wi.empty()) d.warm_start = warm_store[wsi++].data();
+                Flight &f = flight[d.tag];
+                if (f.kind == FL_NODE && !f.node->wi.empty()) d.warm_start = warm_store[wsi++].data();
             }
+            bind_sets(batch);
         }
         if (!batch.empty()) {
             rc = submit_nodes(P, batch.data(), (int32_t)batch.size());
-            if (rc) return rc;
+            if (rc) break;
         }
         // collect results
         int32_t got = 0;
         rc = poll_bounds(P, out.data(), m, &got, sup.data(), betas.data(), 200000);
-        if (rc < 0) return rc;
-        std::vector<kbnb_node_desc> reopts;
-        std::vector<std::vector<int32_t>> reopt_in, reopt_out;
+        if (rc < 0) break;
+        rc = 0;
+        std::vector<kbnb_node_desc> evals;
+        set_store.clear();
         for (int r = 0; r < got; ++r) {
             const kbnb_bound_result &br = out[r];
             auto it = flight.find(br.tag);
@@ -199,14 +379,8 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             Flight f = std::move(it->second);
             flight.erase(it);
             const double *beta = betas.data() + (size_t)r * p;
-            if (f.reopt) {
-                const double v = br.primal_value;
-                if (std::isfinite(v) && v < UB) {
-                    UB = v;
-                    best_support = f.support;
-                    best_beta.assign(beta, beta + p);
-                    ++updates;
-                }
+            if (f.kind == FL_SUPPORT) {
+                take_support(f.support, br.primal_value, beta);
                 continue;
             }
             Open *o = f.node;
@@ -220,22 +394,21 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             }
             // rounding support -> re-optimisation
             std::vector<int32_t> S(sup.begin() + (size_t)r * k, sup.begin() + (size_t)r * k + br.support_len);
-            if (!S.empty() && evaluated.insert(S).second) {
-                reopt_in.push_back(S);
-                std::vector<char> ins(p, 0);
-                for (int j : S) ins[j] = 1;
-                std::vector<int32_t> comp;
-                for (int j = 0; j < p; ++j)
-                    if (!ins[j]) comp.push_back(j);
-                reopt_out.push_back(comp);
-            }
+            if (!S.empty() && !evaluated.count(S)) support_desc(S, evals);
             const int kbar = k - (int)o->in.size();
             const int pf = p - (int)o->in.size() - (int)o->out.size();
-            const int j = br.branch_index;
-            if (kbar <= 0 || pf <= kbar || j < 0) {
+            int j = br.branch_index;
+            if (!rs && (kbar <= 0 || pf <= kbar || j < 0)) {
                 leaf_lb = std::min(leaf_lb, lb);
                 delete o;
                 continue;
+            }
+            if (j < 0) {  // Rashomon mode: every free coordinate is zero
+                std::vector<char> dec(p, 0);
+                for (int q : o->in) dec[q] = 1;
+                for (int q : o->out) dec[q] = 1;
+                for (int q = 0; q < p && j < 0; ++q)
+                    if (!dec[q]) j = q;
             }
             for (int side = 0; side < 2; ++side) {
                 Open *c = new Open();
@@ -258,44 +431,25 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             }
             delete o;
         }
-        if (!reopt_in.empty()) {
-            for (size_t r = 0; r < reopt_in.size(); ++r) {
-                kbnb_node_desc d{};
-                const uint64_t tag = next_tag++;
-                d.tag = tag;
-                d.n_in = (int32_t)reopt_in[r].size();
-                d.fixed_in = reopt_in[r].data();
-                d.n_out = (int32_t)reopt_out[r].size();
-                d.fixed_out = reopt_out[r].data();
-                d.upper_bound = INFINITY;
-                d.rel_tol = std::min(1e-7, 0.1 * node_tol);
-                d.max_iters = max_it;
-                reopts.push_back(d);
-                Flight f;
-                f.reopt = true;
-                f.support = reopt_in[r];
-                flight[tag] = f;
-            }
-            rc = submit_nodes(P, reopts.data(), (int32_t)reopts.size());
-            if (rc) return rc;
+        if (!evals.empty()) {
+            bind_sets(evals);
+            rc = submit_nodes(P, evals.data(), (int32_t)evals.size());
+            if (rc) break;
         }
     }
     // drain in-flight work so the handle is reusable
     while (!flight.empty()) {
         int32_t got = 0;
-        rc = poll_bounds(P, out.data(), m, &got, sup.data(), betas.data(), 200000);
-        if (rc < 0) return rc;
+        int prc = poll_bounds(P, out.data(), m, &got, sup.data(), betas.data(), 200000);
+        if (prc < 0) {
+            if (!rc) rc = prc;
+            break;
+        }
         for (int r = 0; r < got; ++r) {
             auto it = flight.find(out[r].tag);
             if (it == flight.end()) continue;
-            if (it->second.reopt) {
-                const double v = out[r].primal_value;
-                if (std::isfinite(v) && v < UB) {
-                    UB = v;
-                    best_support = it->second.support;
-                    best_beta.assign(betas.data() + (size_t)r * p, betas.data() + (size_t)(r + 1) * p);
-                    ++updates;
-                }
+            if (it->second.kind == FL_SUPPORT) {
+                if (!rc) take_support(it->second.support, out[r].primal_value, betas.data() + (size_t)r * p);
             } else {
                 // unexplored: its parent's bound still holds for its subtree
                 global_lb = std::min(global_lb, it->second.node->lb);
@@ -303,16 +457,14 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             }
             flight.erase(it);
         }
-        if (got == 0 && rc == KBNB_TIMEOUT) {
-            // nothing is progressing: should not happen; avoid spinning forever
-            break;
-        }
+        if (got == 0 && prc == KBNB_TIMEOUT) break;  // nothing is progressing
     }
     while (!open.empty()) {
         global_lb = std::min(global_lb, open.top()->lb);
         delete open.top();
         open.pop();
     }
+    if (rc) return rc;
     res->objective = UB;
     res->lower_bound = std::min(std::min(global_lb, leaf_lb), UB);
     res->rel_gap = std::isfinite(UB) ? (UB - res->lower_bound) / std::max(std::fabs(UB), 1e-12) : INFINITY;
@@ -322,6 +474,24 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     for (int r = 0; r < k; ++r) res->support[r] = r < (int)best_support.size() ? best_support[r] : -1;
     if (res->beta) memcpy(res->beta, best_beta.data(), sizeof(double) * p);
     res->incumbent_updates = updates;
+    res->rashomon_size = 0;
+    if (rs) {
+        // the set: recorded supports within the final threshold, by value,
+        // ties by the support sequence; the best N when capped
+        const double t = tau();
+        std::vector<std::pair<double, const std::vector<int32_t> *>> sel;
+        for (auto &kv : recorded)
+            if (kv.second.value <= t) sel.push_back({kv.second.value, &kv.first});
+        std::sort(sel.begin(), sel.end(), [](const auto &a, const auto &b) {
+            return a.first != b.first ? a.first < b.first : *a.second < *b.second;
+        });
+        if (capN > 0 && (int64_t)sel.size() > capN) sel.resize((size_t)capN);
+        auto pool = std::make_unique<RashomonPool>();
+        for (auto &e : sel) pool->add(*e.second, e.first, recorded[*e.second].beta);
+        res->rashomon_size = (int64_t)sel.size();
+        std::lock_guard<std::mutex> g(g_pool_mu);
+        g_pools[P] = std::move(pool);
+    }
     res->seconds = elapsed();
     return KBNB_OK;
 }

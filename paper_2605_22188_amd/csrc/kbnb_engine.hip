@@ -953,9 +953,14 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     return KBNB_OK;
 }
 
+namespace kbnb {
+void drop_rashomon(const kbnb_problem *P);
+}
+
 extern "C" int destroy_problem(kbnb_problem *P)
 {
     if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    kbnb::drop_rashomon(P);
     free_problem(P);
     return KBNB_OK;
 }

@@ -1,0 +1,73 @@
+"""GPU Rashomon-set collection against the oracle's (pinned by brute force).
+
+Values on the GPU are certified to the support re-optimisation tolerance
+(1e-7 relative), the oracle's to 1e-13, so a support whose value lies within
+2e-6 of the threshold may fall on either side: outside that band the sets
+must agree, values to 1e-6, and every returned iterate must attain its value
+(the oracle's primal value at it, on its support)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_22188_amd as K
+import workloads as W
+from test_oracle_pins import RASHOMON_CASES, weak_logistic_120x20
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(inst, eps, cap, batch_width=64):
+    P = oracle.Problem.from_instance(inst)
+    ref = P.rashomon(eps, cap=cap, node_tol=1e-9)
+    h = K.create_from_instance(inst, batch_width=batch_width)
+    out = K.branch_and_bound(h, rashomon_eps=eps, rashomon_n=cap)
+    K.destroy_problem(h)
+    assert out["status"] == 0
+    assert out["objective"] == pytest.approx(ref["optimum"], rel=1e-6)
+    got = {S: (v, b) for S, v, b in out["rashomon"]}
+    want = dict(ref["set"])
+    vals = [v for _, v, _ in out["rashomon"]]
+    assert vals == sorted(vals)
+    # the threshold of the comparison: the oracle's, and with a cap its N-th value
+    tau = ref["threshold"]
+    band = 2e-6 * abs(tau)
+    for S, v in want.items():
+        if v < tau - band:
+            assert S in got, (S, v, tau)
+            assert got[S][0] == pytest.approx(v, rel=1e-6)
+    for S, (v, b) in got.items():
+        assert S in want or abs(v - tau) <= band, (S, v, tau)
+        st = np.full(inst.p, -1, np.int8)
+        st[list(S)] = 1
+        assert np.all(b[np.setdiff1d(np.arange(inst.p), list(S))] == 0.0)
+        assert P.primal(st, b) == pytest.approx(v, rel=1e-9)
+    return out, ref
+
+
+@pytest.mark.parametrize("loss,n,p,k,seed,eps,cap", RASHOMON_CASES)
+def test_rashomon_small_cases(loss, n, p, k, seed, eps, cap):
+    print(f"[gpu-test] rashomon loss={loss} {n}x{p} k={k} eps={eps} cap={cap}", flush=True)
+    inst = W.small_instance(n, p, k, loss, seed=seed, rho=0.5)
+    _compare(inst, eps, cap)
+
+
+@pytest.mark.parametrize("eps,cap", [(0.02, 0), (0.05, 40)])
+def test_rashomon_weak_logistic_120x20(eps, cap):
+    print(f"[gpu-test] rashomon weak logistic 120x20 eps={eps} cap={cap}", flush=True)
+    out, ref = _compare(weak_logistic_120x20(), eps, cap)
+    assert len(out["rashomon"]) >= (40 if cap else 150)
+
+
+def test_rashomon_entry_errors_and_plain_bnb_unchanged():
+    print("[gpu-test] rashomon entry errors", flush=True)
+    inst = W.plain_bnb_squared_500x30()
+    h = K.create_from_instance(inst, batch_width=64)
+    with pytest.raises(K.KbnbError):
+        K.rashomon_entry(h, 0)            # nothing collected yet
+    out = K.branch_and_bound(h, rashomon_eps=0.05)
+    assert [S for S, _, _ in out["rashomon"]] == [(0, 6, 12, 18, 24)]
+    with pytest.raises(K.KbnbError):
+        K.rashomon_entry(h, 1)
+    plain = K.branch_and_bound(h)
+    assert list(plain["support"]) == [0, 6, 12, 18, 24] and "rashomon" not in plain
+    K.destroy_problem(h)

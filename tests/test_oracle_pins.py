@@ -675,3 +675,20 @@ def test_rashomon_brute_force_cases_include_smaller_supports():
     inst = W.small_instance(40, 8, 3, 1, seed=7, rho=0.5)
     P = oracle.Problem.from_instance(inst)
     assert len(_brute_rashomon(P, 8, 3, 0.2)[2]) > 12
+
+
+def weak_logistic_120x20():
+    """Weak signal (|beta*_j| = 0.3, SNR-free labels): many near-optimal supports."""
+    return W.make_instance("weak_logistic_120x20", 120, 20, 0.5, 4, W.LOGISTIC, 1.0, 2.0, W.F64, 3,
+                           snr=1.0, beta_values=np.full(4, 0.3))
+
+
+def test_rashomon_matches_brute_force_p20():
+    """6196 supports (|S| <= 4 of 20); the set has supports of sizes 3 and 4."""
+    inst = weak_logistic_120x20()
+    P = oracle.Problem.from_instance(inst)
+    phi, tau, want = _brute_rashomon(P, 20, 4, 0.02)
+    got = P.rashomon(0.02)
+    assert got["optimum"] == pytest.approx(phi, rel=1e-12)
+    assert [S for S, _ in got["set"]] == [S for S, _ in want]
+    assert len(want) > 100
