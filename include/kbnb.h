@@ -236,6 +236,50 @@ int branch_and_bound(kbnb_problem *prob, const kbnb_bnb_options *opts,
 int rashomon_entry(kbnb_problem *prob, int64_t i, int32_t *support, int32_t *support_len,
                    double *beta, double *value);
 
+/*
+ * Compact pool of supports (App. "compact Rashomon pool storage", with its
+ * trie figure).  A pool holds N records; record m is (end node l_m, value
+ * Phi_m) in a prefix trie of T nodes: node 0 is the root, node v >= 1 has
+ * parent p(v) and edge label a(v) (a feature index), and the labels on the
+ * path from the root to l_m are the support's insertion sequence.  Records
+ * whose sequences share a prefix share its nodes; a record's end node may
+ * be an inner node when its sequence is a prefix of another's.  The
+ * coefficients of record m, ordered like its path labels, are
+ * c[o_m .. o_{m+1}) of one flat vector c, with o_0 = 0 and
+ * o_{m+1} = o_m + |S_m| (0-based).  Trie nodes are numbered in creation
+ * order.  Host-only calls: none touches the device.  A pool is owned by its
+ * caller and freed with pool_destroy; calls on one pool must not overlap.
+ *
+ * pool_create -- a new empty pool in *out (T = 1, N = 0).
+ * pool_destroy -- frees the pool (NULL is accepted).
+ * pool_add -- appends a record: seq[0..len) the insertion sequence (distinct
+ *   indices >= 0; len 0 is the empty support, ending at the root), coef
+ *   (len values, or NULL for zeros), value Phi.  KBNB_E_INVALID_ARGUMENT for
+ *   a negative or repeated index.
+ * pool_info -- N, T and o_N (any pointer may be NULL).
+ * pool_export -- copies p(v), a(v) (T entries each, -1 for the root), the
+ *   end nodes and values (N each), the offsets (N + 1) and c (o_N); any
+ *   pointer may be NULL to skip that array.
+ * pool_record -- record m (0-based): its path labels (root first; seq holds
+ *   at least the record's length), their count, its coefficients in the
+ *   same order and its value; seq, len, coef and value may be NULL.
+ *   KBNB_E_INVALID_ARGUMENT when m is out of range.
+ * rashomon_pool -- a copy of the set collected by the last Rashomon call of
+ *   branch_and_bound on `prob` as a new pool (records by value as in
+ *   rashomon_entry, each sequence ascending); the caller destroys it.
+ *   KBNB_E_INVALID_ARGUMENT when nothing was collected.
+ */
+typedef struct kbnb_pool kbnb_pool;
+int pool_create(kbnb_pool **out);
+int pool_destroy(kbnb_pool *pool);
+int pool_add(kbnb_pool *pool, const int32_t *seq, int32_t len, const double *coef, double value);
+int pool_info(const kbnb_pool *pool, int64_t *records, int64_t *trie_nodes, int64_t *coefs);
+int pool_export(const kbnb_pool *pool, int32_t *parent, int32_t *label, int32_t *end_node,
+                double *values, int64_t *offsets, double *coef);
+int pool_record(const kbnb_pool *pool, int64_t m, int32_t *seq, int32_t *len, double *coef,
+                double *value);
+int rashomon_pool(kbnb_problem *prob, kbnb_pool **out);
+
 typedef struct {
     const int32_t *widths;  /* candidate batch widths; NULL -> 64, 128, ..., 2048 */
     int32_t n_widths;

@@ -94,7 +94,8 @@ class TuneResult(ctypes.Structure):
 
 EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
            "branch_and_bound", "rashomon_entry", "autotune", "last_error", "prox_batch",
-           "certify_batch", "problem_info", "kernel_stats"]
+           "certify_batch", "problem_info", "kernel_stats", "pool_create", "pool_destroy",
+           "pool_add", "pool_info", "pool_export", "pool_record", "rashomon_pool"]
 
 _lib = None
 
@@ -120,6 +121,13 @@ def load():
         lib.certify_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         lib.problem_info.argtypes = [vp, vp, vp]
         lib.kernel_stats.argtypes = [vp, i32, vp]
+        lib.pool_create.argtypes = [ctypes.POINTER(vp)]
+        lib.pool_destroy.argtypes = [vp]
+        lib.pool_add.argtypes = [vp, vp, i32, vp, dbl]
+        lib.pool_info.argtypes = [vp, vp, vp, vp]
+        lib.pool_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        lib.pool_record.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+        lib.rashomon_pool.argtypes = [vp, ctypes.POINTER(vp)]
         for name in EXPORTS:
             if name != "last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -360,6 +368,72 @@ def rashomon_entry(h: Handle, i):
     _check(load().rashomon_entry(h.ptr, ctypes.c_int64(int(i)), _p(sup), ctypes.byref(n),
                                  _p(beta), ctypes.byref(v)))
     return tuple(int(j) for j in sup[:n.value]), v.value, beta
+
+
+class Pool:
+    """A compact support pool (trie + offsets + flat coefficients), owned here."""
+
+    def __init__(self, ptr=None):
+        if ptr is None:
+            ptr = ctypes.c_void_p()
+            _check(load().pool_create(ctypes.byref(ptr)))
+        self.ptr = ptr
+
+    @classmethod
+    def from_problem(cls, h: Handle):
+        """A copy of the set collected by the last Rashomon call on h."""
+        ptr = ctypes.c_void_p()
+        _check(load().rashomon_pool(h.ptr, ctypes.byref(ptr)))
+        return cls(ptr)
+
+    def close(self):
+        if self.ptr is not None and self.ptr.value:
+            load().pool_destroy(self.ptr)
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, seq, coef=None, value=0.0):
+        sq = np.ascontiguousarray(seq, dtype=np.int32)
+        c = None if coef is None else np.ascontiguousarray(coef, dtype=np.float64)
+        assert c is None or c.shape == sq.shape
+        _check(load().pool_add(self.ptr, _p(sq) if sq.size else None, int(sq.size),
+                               None if c is None else _p(c), float(value)))
+
+    def info(self):
+        """(records N, trie nodes T, stored coefficients o_N)."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().pool_info(self.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def __len__(self):
+        return self.info()[0]
+
+    def export(self):
+        """The stored arrays: parent p(v), label a(v), end nodes, values, offsets o, coefficients c."""
+        N, T, C = self.info()
+        out = dict(parent=np.empty(T, np.int32), label=np.empty(T, np.int32),
+                   end_node=np.empty(N, np.int32), values=np.empty(N),
+                   offsets=np.empty(N + 1, np.int64), coef=np.empty(C))
+        _check(load().pool_export(self.ptr, _p(out["parent"]), _p(out["label"]),
+                                  _p(out["end_node"]), _p(out["values"]), _p(out["offsets"]),
+                                  _p(out["coef"])))
+        return out
+
+    def record(self, m):
+        """Record m: (path labels root first, coefficients in that order, value)."""
+        n = ctypes.c_int32(0)
+        _check(load().pool_record(self.ptr, int(m), None, ctypes.byref(n), None, None))
+        seq = np.empty(max(n.value, 1), np.int32)
+        coef = np.empty(max(n.value, 1))
+        v = ctypes.c_double(0.0)
+        _check(load().pool_record(self.ptr, int(m), _p(seq), ctypes.byref(n), _p(coef),
+                                  ctypes.byref(v)))
+        return tuple(int(j) for j in seq[:n.value]), coef[:n.value].copy(), v.value
 
 
 def prox_batch(h: Handle, states, u, eta):

@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkbnb.so")
-SOURCES = ["kbnb_kernels.hip", "kbnb_engine.hip", "kbnb_bnb.cpp", "kbnb_tune.cpp"]
+SOURCES = ["kbnb_kernels.hip", "kbnb_engine.hip", "kbnb_bnb.cpp", "kbnb_tune.cpp",
+           "kbnb_pool.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

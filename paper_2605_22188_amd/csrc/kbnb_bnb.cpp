@@ -71,53 +71,6 @@ struct Flight {
     std::vector<int32_t> support;   // evaluated support (ascending)
 };
 
-// Compact store of a collected set: the supports in a prefix trie over their
-// ascending index sequences (supports that share a prefix share its nodes),
-// each entry's |S| coefficients in one flat array at its own offset.
-struct RashomonPool {
-    struct TNode {
-        int32_t index, parent, child, sibling;
-    };
-    std::vector<TNode> trie{TNode{-1, -1, -1, -1}};  // node 0: the empty prefix
-    std::vector<int32_t> entry_node;
-    std::vector<double> value;
-    std::vector<int64_t> coef_off;
-    std::vector<double> coef;
-
-    int32_t path(const std::vector<int32_t> &s)
-    {
-        int32_t cur = 0;
-        for (int32_t j : s) {
-            int32_t c = trie[cur].child;
-            while (c >= 0 && trie[c].index != j) c = trie[c].sibling;
-            if (c < 0) {
-                c = (int32_t)trie.size();
-                trie.push_back(TNode{j, cur, -1, trie[cur].child});
-                trie[cur].child = c;
-            }
-            cur = c;
-        }
-        return cur;
-    }
-    void add(const std::vector<int32_t> &s, double v, const std::vector<double> &beta)
-    {
-        entry_node.push_back(path(s));
-        value.push_back(v);
-        coef_off.push_back((int64_t)coef.size());
-        for (int32_t j : s) coef.push_back(beta[j]);
-    }
-    std::vector<int32_t> support(size_t i) const
-    {
-        std::vector<int32_t> s;
-        for (int32_t c = entry_node[i]; c > 0; c = trie[c].parent) s.push_back(trie[c].index);
-        std::reverse(s.begin(), s.end());
-        return s;
-    }
-};
-
-std::mutex g_pool_mu;
-std::map<const kbnb_problem *, std::unique_ptr<RashomonPool>> g_pools;
-
 struct Candidate {
     double value;
     std::vector<double> beta;
@@ -128,40 +81,11 @@ struct Candidate {
 extern "C" int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
 namespace kbnb {
 int set_error(int code, const char *fmt, ...);
-// the collected set of a problem that is being destroyed
-void drop_rashomon(const kbnb_problem *P)
-{
-    std::lock_guard<std::mutex> g(g_pool_mu);
-    g_pools.erase(P);
-}
+// the collected set's storage (kbnb_pool.cpp)
+kbnb_pool *pool_new();
+void pool_append(kbnb_pool *pl, const std::vector<int32_t> &seq, const double *coef, double v);
+void store_rashomon(const kbnb_problem *P, kbnb_pool *pl);
 }  // namespace kbnb
-
-extern "C" int rashomon_entry(kbnb_problem *P, int64_t i, int32_t *support, int32_t *support_len,
-                              double *beta, double *value)
-{
-    if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");
-    if (!support || !support_len || !value)
-        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "support, support_len and value are required");
-    int64_t info[9];
-    double dinfo[4];
-    int rc = problem_info(P, info, dinfo);
-    if (rc) return rc;
-    const int p = (int)info[1], k = (int)info[2];
-    std::lock_guard<std::mutex> g(g_pool_mu);
-    auto it = g_pools.find(P);
-    if (it == g_pools.end() || i < 0 || i >= (int64_t)it->second->value.size())
-        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "no Rashomon entry %lld", (long long)i);
-    const RashomonPool &pl = *it->second;
-    const std::vector<int32_t> s = pl.support((size_t)i);
-    for (int r = 0; r < k; ++r) support[r] = r < (int)s.size() ? s[r] : -1;
-    *support_len = (int32_t)s.size();
-    *value = pl.value[(size_t)i];
-    if (beta) {
-        std::fill(beta, beta + p, 0.0);
-        for (size_t r = 0; r < s.size(); ++r) beta[s[r]] = pl.coef[(size_t)pl.coef_off[(size_t)i] + r];
-    }
-    return KBNB_OK;
-}
 
 extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kbnb_bnb_result *res)
 {
@@ -193,6 +117,11 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     std::set<std::vector<int32_t>> evaluated;            // supports submitted or known
     std::map<std::vector<int32_t>, Candidate> recorded;  // Rashomon mode: within the threshold when found
     std::multiset<double> recorded_vals;
+    // Rashomon leaves: a leaf's certified bound is its support's evaluated
+    // bound; leaves whose support is still being evaluated wait for it
+    // (with their parent's bound, which holds meanwhile)
+    std::map<std::vector<int32_t>, double> support_lb;
+    std::map<std::vector<int32_t>, double> leaf_waiting;
     uint64_t seq = 0, next_tag = 1;
     double UB = INFINITY;
     std::vector<int32_t> best_support;
@@ -216,8 +145,15 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         const int pf = p - (int)o->in.size() - (int)o->out.size();
         return kbar <= 0 || pf == 0;
     };
-    // value v of an evaluated support S with iterate beta
-    auto take_support = [&](const std::vector<int32_t> &S, double v, const double *beta) {
+    double leaf_lb = INFINITY;  // least bound of the discarded subtrees
+    // evaluated support S: value v (attained at beta) and certified bound lb
+    auto take_support = [&](const std::vector<int32_t> &S, double v, double lb, const double *beta) {
+        support_lb[S] = lb;
+        auto w = leaf_waiting.find(S);
+        if (w != leaf_waiting.end()) {
+            leaf_lb = std::min(leaf_lb, lb);
+            leaf_waiting.erase(w);
+        }
         if (std::isfinite(v) && v < UB) {
             UB = v;
             best_support = S;
@@ -244,7 +180,6 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     std::vector<int32_t> sup((size_t)m * k);
     std::vector<double> betas((size_t)m * p);
     double global_lb = -INFINITY;
-    double leaf_lb = INFINITY;  // least bound of the discarded subtrees
     double last_log = 0.0;
 
     // a support evaluation: the node J1 = S, J0 = complement
@@ -321,11 +256,18 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             open.pop();
             if (rs && is_leaf(o)) {
                 // Rashomon leaf: its support J1 is evaluated (once)
-                if (!evaluated.count(o->in)) {
-                    support_desc(o->in, batch);
-                    --room;
+                auto known = support_lb.find(o->in);
+                if (known != support_lb.end()) {
+                    leaf_lb = std::min(leaf_lb, known->second);
+                } else {
+                    auto w = leaf_waiting.find(o->in);
+                    if (w == leaf_waiting.end()) leaf_waiting[o->in] = o->lb;
+                    else w->second = std::min(w->second, o->lb);
+                    if (!evaluated.count(o->in)) {
+                        support_desc(o->in, batch);
+                        --room;
+                    }
                 }
-                leaf_lb = std::min(leaf_lb, o->lb);
                 delete o;
                 continue;
             }
@@ -380,7 +322,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             flight.erase(it);
             const double *beta = betas.data() + (size_t)r * p;
             if (f.kind == FL_SUPPORT) {
-                take_support(f.support, br.primal_value, beta);
+                take_support(f.support, br.primal_value, br.lower_bound, beta);
                 continue;
             }
             Open *o = f.node;
@@ -449,7 +391,9 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             auto it = flight.find(out[r].tag);
             if (it == flight.end()) continue;
             if (it->second.kind == FL_SUPPORT) {
-                if (!rc) take_support(it->second.support, out[r].primal_value, betas.data() + (size_t)r * p);
+                if (!rc)
+                    take_support(it->second.support, out[r].primal_value, out[r].lower_bound,
+                                 betas.data() + (size_t)r * p);
             } else {
                 // unexplored: its parent's bound still holds for its subtree
                 global_lb = std::min(global_lb, it->second.node->lb);
@@ -464,6 +408,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         delete open.top();
         open.pop();
     }
+    for (auto &w : leaf_waiting) global_lb = std::min(global_lb, w.second);
     if (rc) return rc;
     res->objective = UB;
     res->lower_bound = std::min(std::min(global_lb, leaf_lb), UB);
@@ -486,11 +431,16 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             return a.first != b.first ? a.first < b.first : *a.second < *b.second;
         });
         if (capN > 0 && (int64_t)sel.size() > capN) sel.resize((size_t)capN);
-        auto pool = std::make_unique<RashomonPool>();
-        for (auto &e : sel) pool->add(*e.second, e.first, recorded[*e.second].beta);
+        kbnb_pool *pool = kbnb::pool_new();
+        std::vector<double> c;
+        for (auto &e : sel) {
+            const std::vector<double> &beta = recorded[*e.second].beta;
+            c.clear();
+            for (int32_t j : *e.second) c.push_back(beta[(size_t)j]);
+            kbnb::pool_append(pool, *e.second, c.data(), e.first);
+        }
         res->rashomon_size = (int64_t)sel.size();
-        std::lock_guard<std::mutex> g(g_pool_mu);
-        g_pools[P] = std::move(pool);
+        kbnb::store_rashomon(P, pool);
     }
     res->seconds = elapsed();
     return KBNB_OK;

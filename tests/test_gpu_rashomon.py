@@ -24,6 +24,8 @@ def _compare(inst, eps, cap, batch_width=64):
     K.destroy_problem(h)
     assert out["status"] == 0
     assert out["objective"] == pytest.approx(ref["optimum"], rel=1e-6)
+    # the whole tree was decided: its bound meets the optimum
+    assert out["rel_gap"] <= 1e-6 and out["lower_bound"] <= out["objective"]
     got = {S: (v, b) for S, v, b in out["rashomon"]}
     want = dict(ref["set"])
     vals = [v for _, v, _ in out["rashomon"]]
@@ -54,8 +56,23 @@ def test_rashomon_small_cases(loss, n, p, k, seed, eps, cap):
 @pytest.mark.parametrize("eps,cap", [(0.02, 0), (0.05, 40)])
 def test_rashomon_weak_logistic_120x20(eps, cap):
     print(f"[gpu-test] rashomon weak logistic 120x20 eps={eps} cap={cap}", flush=True)
-    out, ref = _compare(weak_logistic_120x20(), eps, cap)
+    inst = weak_logistic_120x20()
+    out, ref = _compare(inst, eps, cap)
     assert len(out["rashomon"]) >= (40 if cap else 150)
+    # the same set through the compact pool: ascending sequences, coefficients
+    # in path order, and prefixes shared
+    h = K.create_from_instance(inst, batch_width=64)
+    out2 = K.branch_and_bound(h, rashomon_eps=eps, rashomon_n=cap)
+    pool = K.Pool.from_problem(h)
+    K.destroy_problem(h)
+    N, T, C = pool.info()
+    assert N == len(out2["rashomon"]) and C == sum(len(S) for S, _, _ in out2["rashomon"])
+    assert T - 1 < C
+    for m, (S, v, b) in enumerate(out2["rashomon"]):
+        seq, coef, val = pool.record(m)
+        assert seq == S and val == v
+        np.testing.assert_array_equal(coef, b[list(S)])
+    pool.close()
 
 
 def test_rashomon_entry_errors_and_plain_bnb_unchanged():
@@ -64,6 +81,8 @@ def test_rashomon_entry_errors_and_plain_bnb_unchanged():
     h = K.create_from_instance(inst, batch_width=64)
     with pytest.raises(K.KbnbError):
         K.rashomon_entry(h, 0)            # nothing collected yet
+    with pytest.raises(K.KbnbError):
+        K.Pool.from_problem(h)
     out = K.branch_and_bound(h, rashomon_eps=0.05)
     assert [S for S, _, _ in out["rashomon"]] == [(0, 6, 12, 18, 24)]
     with pytest.raises(K.KbnbError):
