@@ -22,7 +22,9 @@ Printed JSON line: the contract fields plus
   comparator        the same library at batch width 1 (one node at a time)
   time_to_zero_gap  full GPU branch and bound, 10000 x 1000 bfloat16 squared
   serving           32-problem Poisson serving mix, p50/p99 node latency
-  large_logistic    node bounds on the 100000 x 5000 bfloat16 logistic workload
+  large_logistic    node bounds on the 100000 x 5000 bfloat16 logistic workload,
+                    and its branch and bound collecting the supports within 1%
+                    of the optimum (Rashomon set)
 """
 from __future__ import annotations
 
@@ -131,7 +133,7 @@ def _draw(kind, q=None):
     else:
         inst = W.large_logistic_100000x5000_bf16()
     return dict(X_store=inst.X_store, y=inst.y, k=inst.k, loss=inst.loss, lambda2=inst.lambda2,
-                M=inst.M, dtype=inst.dtype, n=inst.n, p=inst.p)
+                M=inst.M, dtype=inst.dtype, n=inst.n, p=inst.p, beta_true=inst.beta_true)
 
 
 def large_leg(K, W, torch, args):
@@ -165,6 +167,20 @@ def large_leg(K, W, torch, args):
     K.kernel_stats(h, 1)
     K.bound_nodes(h, nodes[8 + args.large_batch:], rel_tol=1e-6)
     ks = K.kernel_stats(h, 0)
+    rash = None
+    if args.large_rashomon > 0:
+        # certify the optimum and collect every support within (1 + eps) of it
+        log(f"large: branch and bound with Rashomon eps {args.large_rashomon}")
+        ob = K.branch_and_bound(h, time_limit_s=args.bnb_time_limit, log_every_s=10.0,
+                                rashomon_eps=args.large_rashomon)
+        true_sup = [int(j) for j in np.flatnonzero(d["beta_true"])]
+        rash = {"eps": args.large_rashomon, "seconds": round(ob["seconds"], 3),
+                "nodes": int(ob["nodes"]), "status": int(ob["status"]),
+                "objective": ob["objective"], "rel_gap": ob["rel_gap"],
+                "set_size": len(ob["rashomon"]),
+                "incumbent_is_true_support": [int(j) for j in ob["support"]] == true_sup,
+                "values": [v for _, v, _ in ob["rashomon"][:10]]}
+        log(f"large: rashomon {rash}")
     K.destroy_problem(h)
     n = d["n"]
     iters = [r["iterations"] for r in res]
@@ -189,7 +205,7 @@ def large_leg(K, W, torch, args):
             "max_rel_gap": float(max(r["rel_gap"] for r in res)),
             "iteration_products": "bfloat16 MFMA (three-term split of the float32 operand) of "
                                   "the change since each node's last float64 certificate",
-            "kernels": kern}
+            "kernels": kern, "rashomon_bnb": rash}
 
 
 def serving_leg(K, W, torch, args):
@@ -363,6 +379,8 @@ def main():
     ap.add_argument("--large", type=int, default=1,
                     help="run the 100000 x 5000 bfloat16 logistic node-bound leg")
     ap.add_argument("--large-batch", type=int, default=256)
+    ap.add_argument("--large-rashomon", type=float, default=0.01,
+                    help="eps of the Rashomon branch and bound on the large workload (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
