@@ -280,6 +280,35 @@ int pool_record(const kbnb_pool *pool, int64_t m, int32_t *seq, int32_t *len, do
                 double *value);
 int rashomon_pool(kbnb_problem *prob, kbnb_pool **out);
 
+/*
+ * Variable importance over a pool (App. "variable importance analysis based
+ * on the Rashomon set").  Record m is the model beta^(m) with its stored
+ * coefficients on its labels and 0 elsewhere.
+ *
+ * rashomon_reliance -- fixed-model reliance of every stored coefficient,
+ *   R_j^(m) = (1/n) sum_i l(y_i, eta_i - x_ij beta_j) - (1/n) sum_i l(y_i, eta_i),
+ *   eta = X beta^(m): the increase of the mean loss when feature j's fitted
+ *   contribution is removed and the other coefficients are kept (the paper
+ *   states it for the logistic loss; the squared loss takes its own l).  It
+ *   runs on the device in float64 from the stored instance values of `prob`
+ *   (one workgroup per record).  reliance: caller buffer of o_N doubles laid
+ *   out like the pool's coefficient vector c (entry o_m + r belongs to the
+ *   r-th path label of record m); R_j^(m) = 0 for j not in S_m and is not
+ *   stored.  KBNB_E_INVALID_ARGUMENT when a label is not in [0, p).
+ *
+ * pool_summary -- per-feature summaries over the N records, host-only, into
+ *   out[9][p] (rows, each p entries): support frequency (share of records
+ *   whose support holds j), mean coefficient, mean |coefficient|, share of
+ *   records with a positive coefficient, coefficient minimum and maximum,
+ *   and, from `reliance` (o_N entries as written by rashomon_reliance, or
+ *   NULL: rows of zeros), the reliance minimum, maximum and mean.  A record
+ *   without j contributes coefficient 0 and reliance 0 to every row, so the
+ *   [min, max] rows are the ranges over the whole pool.  All zeros when the
+ *   pool is empty.  KBNB_E_INVALID_ARGUMENT when a label is not in [0, p).
+ */
+int rashomon_reliance(kbnb_problem *prob, const kbnb_pool *pool, double *reliance);
+int pool_summary(const kbnb_pool *pool, int32_t p, const double *reliance, double *out);
+
 typedef struct {
     const int32_t *widths;  /* candidate batch widths; NULL -> 64, 128, ..., 2048 */
     int32_t n_widths;

@@ -81,6 +81,7 @@ def _load():
             "orc_bnb": (i, [P, d, i, d, d, ctypes.c_long, vp, vp, vp]),
             "orc_rashomon": (ctypes.c_long, [P, d, ctypes.c_long, d, i, ctypes.c_long,
                                              ctypes.c_long, vp, vp, vp]),
+            "orc_reliance": (None, [P, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -219,6 +220,15 @@ class Problem:
                for r in range(min(cnt, max_out))]
         return dict(set=out, count=int(cnt), optimum=info[0], threshold=info[1],
                     nodes=int(info[2]), status=int(info[3]))
+
+
+    def reliance(self, beta):
+        """Fixed-model reliance R[j] of model beta (p entries; 0 where beta_j = 0)."""
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        assert b.shape == (self.p,)
+        out = np.empty(self.p)
+        _load().orc_reliance(self.ref, _ptr(b), _ptr(out))
+        return out
 
 
 # scalar helpers ------------------------------------------------------------

@@ -897,3 +897,24 @@ long orc_rashomon(const orc_problem *P, double eps, long cap, double node_tol,
     free(beta); free(bre); free(supp);
     return cnt;
 }
+
+/* Fixed-model reliance: drop feature j's fitted contribution from the linear
+ * predictor, keep every other coefficient, and compare the mean losses. */
+void orc_reliance(const orc_problem *P, const double *beta, double *R)
+{
+    double *eta = (double *)malloc(sizeof(double) * (size_t)P->n);
+    matvec(P, beta, eta);
+    double base = 0.0;
+    for (int i = 0; i < P->n; ++i) base += orc_loss(P->loss, eta[i], P->y[i]);
+    for (int j = 0; j < P->p; ++j) {
+        if (beta[j] == 0.0) {
+            R[j] = 0.0;
+            continue;
+        }
+        double dropped = 0.0;
+        for (int i = 0; i < P->n; ++i)
+            dropped += orc_loss(P->loss, eta[i] - P->X[(size_t)i * P->p + j] * beta[j], P->y[i]);
+        R[j] = (dropped - base) / (double)P->n;
+    }
+    free(eta);
+}

@@ -88,6 +88,12 @@ long orc_rashomon(const orc_problem *P, double eps, long cap, double node_tol,
                   int node_max_iter, long max_nodes, long max_out,
                   int *out_supports, double *out_values, double *info);
 
+/* Fixed-model reliance (appendix on variable importance over the Rashomon
+ * set) of one model beta (p entries): for every feature j,
+ *   R[j] = (1/n) sum_i l(eta_i - x_ij beta_j, y_i) - (1/n) sum_i l(eta_i, y_i),
+ * eta = X beta; R[j] = 0 where beta_j = 0. */
+void orc_reliance(const orc_problem *P, const double *beta, double *R);
+
 #ifdef __cplusplus
 }
 #endif

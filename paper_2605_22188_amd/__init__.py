@@ -95,7 +95,8 @@ class TuneResult(ctypes.Structure):
 EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
            "branch_and_bound", "rashomon_entry", "autotune", "last_error", "prox_batch",
            "certify_batch", "problem_info", "kernel_stats", "pool_create", "pool_destroy",
-           "pool_add", "pool_info", "pool_export", "pool_record", "rashomon_pool"]
+           "pool_add", "pool_info", "pool_export", "pool_record", "rashomon_pool",
+           "rashomon_reliance", "pool_summary"]
 
 _lib = None
 
@@ -128,6 +129,8 @@ def load():
         lib.pool_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         lib.pool_record.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
         lib.rashomon_pool.argtypes = [vp, ctypes.POINTER(vp)]
+        lib.rashomon_reliance.argtypes = [vp, vp, vp]
+        lib.pool_summary.argtypes = [vp, i32, vp, vp]
         for name in EXPORTS:
             if name != "last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -434,6 +437,27 @@ class Pool:
         _check(load().pool_record(self.ptr, int(m), _p(seq), ctypes.byref(n), _p(coef),
                                   ctypes.byref(v)))
         return tuple(int(j) for j in seq[:n.value]), coef[:n.value].copy(), v.value
+
+
+SUMMARY_ROWS = ("freq", "mean", "abs_mean", "pos_frac", "coef_min", "coef_max",
+                "reliance_min", "reliance_max", "reliance_mean")
+
+
+def rashomon_reliance(h: Handle, pool: Pool):
+    """Fixed-model reliance of every stored coefficient of `pool` on h's
+    instance, laid out like the pool's coefficient vector."""
+    C = pool.info()[2]
+    out = np.zeros(max(C, 1))
+    _check(load().rashomon_reliance(h.ptr, pool.ptr, _p(out)))
+    return out[:C]
+
+
+def pool_summary(pool: Pool, p, reliance=None):
+    """Per-feature summaries over the pool's records (dict of length-p arrays)."""
+    out = np.zeros((9, int(p)))
+    rel = None if reliance is None else np.ascontiguousarray(reliance, dtype=np.float64)
+    _check(load().pool_summary(pool.ptr, int(p), None if rel is None else _p(rel), _p(out)))
+    return dict(zip(SUMMARY_ROWS, out))
 
 
 def prox_batch(h: Handle, states, u, eta):

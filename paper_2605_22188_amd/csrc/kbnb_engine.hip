@@ -1213,6 +1213,53 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     return KBNB_OK;
 }
 
+// Fixed-model reliance of every stored coefficient of a pool (read through
+// the pool's public calls), computed on the device from the instance.
+extern "C" int rashomon_reliance(kbnb_problem *P, const kbnb_pool *pool, double *reliance)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (!pool || !reliance) return fail(KBNB_E_INVALID_ARGUMENT, "pool and reliance are required");
+    int64_t N = 0, T = 0, C = 0;
+    int rc = pool_info(pool, &N, &T, &C);
+    if (rc) return rc;
+    if (N == 0) return KBNB_OK;
+    if (N > (int64_t)INT32_MAX) return fail(KBNB_E_INVALID_ARGUMENT, "too many records");
+    std::vector<int32_t> parent((size_t)T), label((size_t)T), end((size_t)N);
+    std::vector<int64_t> off((size_t)N + 1);
+    std::vector<double> coef((size_t)std::max<int64_t>(C, 1));
+    rc = pool_export(pool, parent.data(), label.data(), end.data(), nullptr, off.data(), coef.data());
+    if (rc) return rc;
+    // labels of every record in path order (root first), the order of its coefficients
+    std::vector<int32_t> lab((size_t)std::max<int64_t>(C, 1));
+    for (int64_t m = 0; m < N; ++m) {
+        int64_t r = off[(size_t)m + 1];
+        for (int32_t v = end[(size_t)m]; v > 0; v = parent[(size_t)v]) {
+            const int32_t j = label[(size_t)v];
+            if (j < 0 || j >= P->p)
+                return fail(KBNB_E_INVALID_ARGUMENT, "record %lld holds feature %d outside [0, %d)", (long long)m, j,
+                            P->p);
+            lab[(size_t)--r] = j;
+        }
+    }
+    std::lock_guard<std::mutex> g(P->api_mu);
+    TmpStream Ts;
+    HIP_TRY(hipStreamCreate(&Ts.s));
+    int32_t *dlab;
+    int64_t *doff;
+    double *dcoef, *dout;
+    if ((rc = Ts.alloc(&dlab, (size_t)std::max<int64_t>(C, 1))) || (rc = Ts.alloc(&doff, (size_t)N + 1)) ||
+        (rc = Ts.alloc(&dcoef, (size_t)std::max<int64_t>(C, 1))) || (rc = Ts.alloc(&dout, (size_t)std::max<int64_t>(C, 1))))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(dlab, lab.data(), sizeof(int32_t) * (size_t)C, hipMemcpyHostToDevice, Ts.s));
+    HIP_TRY(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * ((size_t)N + 1), hipMemcpyHostToDevice, Ts.s));
+    HIP_TRY(hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * (size_t)C, hipMemcpyHostToDevice, Ts.s));
+    launch_reliance(Ts.s, P->xtype, P->XT, P->npad, P->n, P->loss, P->y, dlab, doff, dcoef, (int)N, dout);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(reliance, dout, sizeof(double) * (size_t)C, hipMemcpyDeviceToHost, Ts.s));
+    HIP_TRY(hipStreamSynchronize(Ts.s));
+    return KBNB_OK;
+}
+
 extern "C" int kernel_stats(kbnb_problem *P, int32_t mode, double *out)
 {
     if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");

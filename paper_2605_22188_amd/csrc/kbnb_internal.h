@@ -136,6 +136,10 @@ void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const i
 // power iteration pieces: out[r] = sum_c A[r][c] v[c] in float64
 void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int rows, int cols,
                        const double *v, double *out);
+// fixed-model reliance of pool records (float64): record m's labels and
+// coefficients are lab/coef[off[m] .. off[m + 1]); out has the same layout
+void launch_reliance(hipStream_t s, int xtype, const void *XT, int64_t npad, int n, int loss, const double *y,
+                     const int32_t *lab, const int64_t *off, const double *coef, int nrec, double *out);
 // convert/transposed copies
 void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
                       int npad, int pm);

@@ -1887,6 +1887,76 @@ void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int
         KBNB_LAUNCH((k_matvec<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)A, lda, rows, cols, v, out);
 }
 
+// ---------------------------------------------------------------------------
+// Fixed-model reliance over a pool of sparse models (appendix on variable
+// importance over the Rashomon set): for record m with coefficients c on the
+// labels lab of its support,
+//   R = (1/n) sum_i [ l(eta_i - x_{i,lab_r} c_r, y_i) - l(eta_i, y_i) ],
+//   eta = X_{:,lab} c,
+// one workgroup per record, float64 from the stored values of X^T (rows of
+// X^T are columns of X, contiguous over i).  Labels are taken in groups of
+// 16 (eta is recomputed per group).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double cvt_d(double v) { return v; }
+__device__ __forceinline__ double cvt_d(float v) { return (double)v; }
+__device__ __forceinline__ double cvt_d(uint16_t v) { return (double)bf16_to_f(v); }
+
+template <typename TA>
+__global__ __launch_bounds__(256) void k_reliance(const TA *__restrict__ XT, int64_t npad, int n, int loss,
+                                                  const double *__restrict__ y, const int32_t *__restrict__ lab,
+                                                  const int64_t *__restrict__ off, const double *__restrict__ coef,
+                                                  double *__restrict__ out)
+{
+    constexpr int RG = 16;
+    __shared__ double red[4][RG];
+    const int m = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t o0 = off[m];
+    const int kl = (int)(off[m + 1] - o0);
+    const int32_t *L = lab + o0;
+    const double *C = coef + o0;
+    for (int g0 = 0; g0 < kl; g0 += RG) {
+        double acc[RG];
+#pragma unroll
+        for (int r = 0; r < RG; ++r) acc[r] = 0.0;
+        for (int i = tid; i < n; i += 256) {
+            double eta = 0.0;
+            for (int r = 0; r < kl; ++r) eta += cvt_d(XT[(int64_t)L[r] * npad + i]) * C[r];
+            const double yi = y[i];
+            const double base = loss_d(loss, eta, yi);
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                if (g0 + r < kl) {
+                    const double xv = cvt_d(XT[(int64_t)L[g0 + r] * npad + i]);
+                    acc[r] += loss_d(loss, eta - xv * C[g0 + r], yi) - base;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            double v = wave_sum(acc[r]);
+            if (lane == 0) red[wave][r] = v;
+        }
+        __syncthreads();
+        if (tid < RG && g0 + tid < kl)
+            out[o0 + g0 + tid] = (red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]) / (double)n;
+        __syncthreads();
+    }
+}
+
+void launch_reliance(hipStream_t s, int xtype, const void *XT, int64_t npad, int n, int loss, const double *y,
+                     const int32_t *lab, const int64_t *off, const double *coef, int nrec, double *out)
+{
+    if (nrec <= 0) return;
+    dim3 grid(nrec);
+    if (xtype == XT_F64)
+        KBNB_LAUNCH((k_reliance<double>), grid, dim3(256), 0, s, (const double *)XT, npad, n, loss, y, lab, off, coef, out);
+    else if (xtype == XT_F32)
+        KBNB_LAUNCH((k_reliance<float>), grid, dim3(256), 0, s, (const float *)XT, npad, n, loss, y, lab, off, coef, out);
+    else
+        KBNB_LAUNCH((k_reliance<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)XT, npad, n, loss, y, lab, off, coef, out);
+}
+
 void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
                       int npad, int pm)
 {

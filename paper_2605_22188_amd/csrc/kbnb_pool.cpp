@@ -154,6 +154,61 @@ extern "C" int pool_record(const kbnb_pool *pool, int64_t m, int32_t *seq, int32
     return KBNB_OK;
 }
 
+extern "C" int pool_summary(const kbnb_pool *pool, int32_t p, const double *reliance, double *out)
+{
+    if (!pool) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL pool");
+    if (p <= 0 || !out) return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "p > 0 and out are required");
+    const size_t N = pool->value.size(), P = (size_t)p;
+    for (size_t v = 1; v < pool->label.size(); ++v)
+        if (pool->label[v] >= p)
+            return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "feature %d outside [0, %d)", pool->label[v], p);
+    double *freq = out, *mean = out + P, *amean = out + 2 * P, *pos = out + 3 * P, *cmin = out + 4 * P,
+           *cmax = out + 5 * P, *rmin = out + 6 * P, *rmax = out + 7 * P, *rmean = out + 8 * P;
+    std::fill(out, out + 9 * P, 0.0);
+    if (N == 0) return KBNB_OK;
+    // a feature absent from a record has coefficient 0 and reliance 0 there
+    std::vector<int64_t> cnt(P, 0);
+    for (size_t m = 0; m < N; ++m) {
+        const std::vector<int32_t> s = pool->path((int64_t)m);
+        const int64_t o = pool->offset[m];
+        for (size_t r = 0; r < s.size(); ++r) {
+            const size_t j = (size_t)s[r];
+            const double c = pool->coef[(size_t)o + r];
+            const double rv = reliance ? reliance[(size_t)o + r] : 0.0;
+            if (cnt[j] == 0) {
+                cmin[j] = cmax[j] = c;
+                rmin[j] = rmax[j] = rv;
+            } else {
+                cmin[j] = std::min(cmin[j], c);
+                cmax[j] = std::max(cmax[j], c);
+                rmin[j] = std::min(rmin[j], rv);
+                rmax[j] = std::max(rmax[j], rv);
+            }
+            ++cnt[j];
+            mean[j] += c;
+            amean[j] += std::fabs(c);
+            pos[j] += c > 0 ? 1.0 : 0.0;
+            rmean[j] += rv;
+        }
+    }
+    for (size_t j = 0; j < P; ++j) {
+        if (cnt[j] < (int64_t)N) {  // some records leave j out: their 0 joins the ranges
+            cmin[j] = std::min(cmin[j], 0.0);
+            cmax[j] = std::max(cmax[j], 0.0);
+            rmin[j] = std::min(rmin[j], 0.0);
+            rmax[j] = std::max(rmax[j], 0.0);
+        }
+        freq[j] = (double)cnt[j] / (double)N;
+        mean[j] /= (double)N;
+        amean[j] /= (double)N;
+        pos[j] /= (double)N;
+        rmean[j] /= (double)N;
+    }
+    if (!reliance)
+        for (size_t j = 0; j < P; ++j) rmin[j] = rmax[j] = rmean[j] = 0.0;
+    return KBNB_OK;
+}
+
 extern "C" int rashomon_pool(kbnb_problem *P, kbnb_pool **out)
 {
     if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");

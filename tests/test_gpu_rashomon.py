@@ -90,3 +90,59 @@ def test_rashomon_entry_errors_and_plain_bnb_unchanged():
     plain = K.branch_and_bound(h)
     assert list(plain["support"]) == [0, 6, 12, 18, 24] and "rashomon" not in plain
     K.destroy_problem(h)
+
+
+def _reliance_vs_oracle(inst, eps, cap):
+    h = K.create_from_instance(inst, batch_width=64)
+    out = K.branch_and_bound(h, rashomon_eps=eps, rashomon_n=cap)
+    pool = K.Pool.from_problem(h)
+    rel = K.rashomon_reliance(h, pool)
+    K.destroy_problem(h)
+    P = oracle.Problem.from_instance(inst)
+    mean_loss = None
+    N, _, C = pool.info()
+    assert N == len(out["rashomon"]) and rel.shape == (C,)
+    o = 0
+    for m in range(N):
+        seq, coef, _ = pool.record(m)
+        beta = np.zeros(inst.p)
+        beta[list(seq)] = coef
+        want = P.reliance(beta)
+        if mean_loss is None:
+            mean_loss = abs(P.primal(np.where(beta != 0, 1, -1).astype(np.int8), beta)) / inst.n
+        # float64 sums of n terms in another order
+        for r, j in enumerate(seq):
+            assert abs(rel[o + r] - want[j]) <= 1e-11 * (mean_loss + abs(want[j])), (m, j)
+        o += len(seq)
+    s = K.pool_summary(pool, inst.p, rel)
+    pool.close()
+    return out, s
+
+
+def test_reliance_matches_oracle_logistic_pool():
+    print("[gpu-test] reliance on the weak logistic 120x20 pool", flush=True)
+    out, s = _reliance_vs_oracle(weak_logistic_120x20(), 0.05, 40)
+    assert len(out["rashomon"]) == 40
+    # every record holds its own support: frequencies sum to the mean support size
+    assert s["freq"].sum() == pytest.approx(np.mean([len(S) for S, _, _ in out["rashomon"]]))
+
+
+def test_reliance_matches_oracle_squared_pool():
+    print("[gpu-test] reliance on a squared-loss pool (float32 X)", flush=True)
+    inst = W.small_instance(300, 16, 4, 0, seed=31, rho=0.7, dtype="f32")
+    _reliance_vs_oracle(inst, 0.2, 25)
+
+
+def test_reliance_errors():
+    print("[gpu-test] reliance errors", flush=True)
+    inst = W.small_instance(60, 10, 3, 0, seed=50)
+    h = K.create_from_instance(inst, batch_width=64)
+    pool = K.Pool()
+    pool.add([1, 12], [0.5, 0.5], 1.0)  # feature 12 outside [0, 10)
+    with pytest.raises(K.KbnbError):
+        K.rashomon_reliance(h, pool)
+    empty = K.Pool()
+    assert K.rashomon_reliance(h, empty).shape == (0,)
+    K.destroy_problem(h)
+    pool.close()
+    empty.close()

@@ -692,3 +692,42 @@ def test_rashomon_matches_brute_force_p20():
     assert got["optimum"] == pytest.approx(phi, rel=1e-12)
     assert [S for S, _ in got["set"]] == [S for S, _ in want]
     assert len(want) > 100
+
+
+# ---------------------------------------------------------------------------
+# Fixed-model reliance (appendix on variable importance over the Rashomon
+# set): zero off the support, the squared-loss closed form, and for the
+# logistic loss the first-order expansion in the removed coefficient.
+# ---------------------------------------------------------------------------
+
+def test_reliance_zero_off_support_and_squared_closed_form():
+    inst = W.small_instance(90, 12, 4, oracle.SQUARED, seed=21)
+    P = oracle.Problem.from_instance(inst)
+    beta = np.zeros(12)
+    beta[[1, 5, 9]] = [0.7, -1.3, 0.25]
+    R = P.reliance(beta)
+    assert np.all(R[[0, 2, 3, 4, 6, 7, 8, 10, 11]] == 0.0)
+    # (r + x_j b_j)^2 - r^2 = 2 r x_j b_j + x_j^2 b_j^2 with r = y - X beta
+    X, y, n = P.X, P.y, P.n
+    r = y - X @ beta
+    for j in (1, 5, 9):
+        want = (2.0 * beta[j] * (X[:, j] @ r) + beta[j] ** 2 * (X[:, j] @ X[:, j])) / n
+        assert R[j] == pytest.approx(want, rel=1e-12, abs=1e-14)
+
+
+def test_reliance_logistic_first_order_in_the_removed_coefficient():
+    inst = W.small_instance(150, 10, 4, oracle.LOGISTIC, seed=22)
+    P = oracle.Problem.from_instance(inst)
+    X, y, n = P.X, P.y, P.n
+    base = np.zeros(10)
+    base[[0, 3, 7]] = [0.9, -0.6, 0.4]
+    for h in (1e-3, 1e-4):
+        beta = base.copy()
+        beta[5] = h
+        R = P.reliance(beta)
+        eta = X @ beta
+        # d/dt mean l(eta - t x_5) at t = 0 is -(1/n) sum x_i5 l'(eta_i),
+        # l'(s) = -y / (1 + exp(y s)); the remainder is O(h^2)
+        dl = -y / (1.0 + np.exp(y * eta))
+        first = -h * (X[:, 5] @ dl) / n
+        assert abs(R[5] - first) <= 2.0 * h * h * (X[:, 5] ** 2).mean()

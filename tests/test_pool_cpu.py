@@ -111,3 +111,35 @@ def test_pool_errors():
     pool.add([4, 1], None, 1.0)
     assert pool.record(1)[1].tolist() == [0.0, 0.0]
     pool.close()
+
+
+def test_pool_summary_on_the_worked_example():
+    """Summaries over the four records of the paper's storage example, worked
+    by hand: feature 18 is in three records with coefficients 0.4, 0.5, 0.2
+    and absent (0) from the fourth; feature 2 has -1.2 and -1.0 in two."""
+    g = _example()
+    pool = K.Pool()
+    for seq, coef in zip(g["insertion_sequences"], g["coefficients"]):
+        pool.add(seq, coef, value=1.0)
+    rel = np.arange(1, 12, dtype=np.float64) / 10.0  # laid out like c
+    s = K.pool_summary(pool, 20, rel)
+    assert s["freq"][18] == 0.75 and s["freq"][2] == 0.5 and s["freq"][4] == 0.25
+    assert s["freq"][0] == 0.0 and s["freq"].sum() == 11 / 4
+    assert s["mean"][18] == pytest.approx(0.275) and s["abs_mean"][18] == pytest.approx(0.275)
+    assert s["mean"][2] == pytest.approx(-0.55) and s["abs_mean"][2] == pytest.approx(0.55)
+    assert s["pos_frac"][18] == 0.75 and s["pos_frac"][2] == 0.0 and s["pos_frac"][4] == 0.25
+    assert (s["coef_min"][18], s["coef_max"][18]) == (0.0, 0.5)
+    assert (s["coef_min"][2], s["coef_max"][2]) == (-1.2, 0.0)
+    # reliance of 18: entries 1, 4, 7 of c (0.1, 0.4, 0.7), and 0 in record 4
+    assert (s["reliance_min"][18], s["reliance_max"][18]) == (0.0, 0.7)
+    assert s["reliance_mean"][18] == pytest.approx(0.3)
+    # feature 12: only record 4 (entry 10 of c: 1.0)
+    assert (s["reliance_min"][12], s["reliance_max"][12], s["reliance_mean"][12]) == (0.0, 1.0, 0.25)
+    s0 = K.pool_summary(pool, 20)
+    assert not s0["reliance_max"].any()
+    with pytest.raises(K.KbnbError):
+        K.pool_summary(pool, 18)  # feature 18 outside [0, 18)
+    empty = K.Pool()
+    assert not K.pool_summary(empty, 5)["freq"].any()
+    pool.close()
+    empty.close()
