@@ -25,6 +25,9 @@ Printed JSON line: the contract fields plus
   large_logistic    node bounds on the 100000 x 5000 bfloat16 logistic workload,
                     and its branch and bound collecting the supports within 1%
                     of the optimum (Rashomon set)
+  rashomon_importance  variable importance (support frequency, fixed-model
+                    reliance) over a Rashomon pool of the logistic 1000 x 1000
+                    workload
 """
 from __future__ import annotations
 
@@ -208,6 +211,48 @@ def large_leg(K, W, torch, args):
             "kernels": kern, "rashomon_bnb": rash}
 
 
+def importance_leg(K, W, torch, args):
+    """Variable importance over a Rashomon pool on the logistic 1000 x 1000
+    workload (rho 0.9, k 10, lambda2 1, M 2, float32 X): branch and bound
+    collecting the best 1000 supports within 10% of the incumbent under a
+    time limit (the set is not certified within it), then the fixed-model
+    reliance of every stored coefficient on the device and the per-feature
+    summaries."""
+    inst = W.make_instance("logistic_1000x1000_rho0.9", 1000, 1000, 0.9, 10, W.LOGISTIC, 1.0,
+                           2.0, W.F32, 0)
+    h = K.create_from_instance(inst, batch_width=1024)
+    ob = K.branch_and_bound(h, time_limit_s=args.importance_seconds, log_every_s=10.0,
+                            rashomon_eps=0.1, rashomon_n=1000)
+    pool = K.Pool.from_problem(h)
+    N, T, C = pool.info()
+    K.rashomon_reliance(h, pool)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rel = K.rashomon_reliance(h, pool)
+    t_rel = time.perf_counter() - t
+    t = time.perf_counter()
+    s = K.pool_summary(pool, inst.p, rel)
+    t_sum = time.perf_counter() - t
+    pool.close()
+    K.destroy_problem(h)
+    true_sup = [int(j) for j in np.flatnonzero(inst.beta_true)]
+    top_freq = [int(j) for j in np.argsort(-s["freq"], kind="stable")[:len(true_sup)]]
+    top_rel = [int(j) for j in np.argsort(-s["reliance_mean"], kind="stable")[:len(true_sup)]]
+    vals = [v for _, v, _ in ob["rashomon"]]
+    res = {"workload": "logistic_1000x1000_rho0.9_k10", "eps": 0.1, "cap": 1000,
+           "time_limit_s": args.importance_seconds, "nodes": int(ob["nodes"]),
+           "status": ["complete", "time limit", "node limit"][ob["status"]],
+           "records": int(N), "trie_nodes": int(T), "stored_coefficients": int(C),
+           "worst_over_best": vals[-1] / vals[0] if vals else None,
+           "reliance_s": round(t_rel, 5),
+           "reliance_loss_evals_per_s": round(C * inst.n / t_rel, 1) if t_rel > 0 else None,
+           "summary_s": round(t_sum, 5),
+           "true_support": true_sup, "top_frequency": sorted(top_freq),
+           "top_mean_reliance": sorted(top_rel)}
+    log(f"importance: {res}")
+    return res
+
+
 def serving_leg(K, W, torch, args):
     """Serving mix: 32 concurrent problems (n ~ U{1000..20000}, p ~ U{100..3000},
     k ~ U{5..20}, squared/logistic 50/50, rho in {0.3, 0.6, 0.9}, float32 X),
@@ -379,6 +424,8 @@ def main():
     ap.add_argument("--large", type=int, default=1,
                     help="run the 100000 x 5000 bfloat16 logistic node-bound leg")
     ap.add_argument("--large-batch", type=int, default=256)
+    ap.add_argument("--importance-seconds", type=float, default=20.0,
+                    help="collection time of the variable-importance leg (0: skip)")
     ap.add_argument("--large-rashomon", type=float, default=0.01,
                     help="eps of the Rashomon branch and bound on the large workload (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -530,6 +577,7 @@ def main():
     ttz = bnb_leg(K, W, torch, args) if args.bnb else None
     serving = serving_leg(K, W, torch, args) if args.serving else None
     large = large_leg(K, W, torch, args) if args.large else None
+    importance = importance_leg(K, W, torch, args) if args.importance_seconds > 0 else None
 
     lat_ms = np.array(lat_all) * 1e3
     out = {
@@ -565,6 +613,7 @@ def main():
         "time_to_zero_gap": ttz,
         "serving": serving,
         "large_logistic": large,
+        "rashomon_importance": importance,
         "setup_s": round(t_setup, 3),
     }
     K.destroy_problem(h)
