@@ -213,6 +213,29 @@ int branch_and_bound(kbnb_problem *prob, const kbnb_bnb_options *opts,
                      kbnb_bnb_result *result);
 
 /*
+ * evaluate_supports -- batched re-optimisation of supports (Sec. 4.3): for
+ * support S_i, the entries supports[i * k .. i * k + k) up to the first -1
+ * (distinct features in [0, p), at most 64 of them),
+ *   v(S_i) = min { F(X beta) + lambda2 ||beta||^2 : supp beta in S_i,
+ *                  |beta_j| <= M },
+ * the relaxation of the node J1 = S_i, J0 = the rest, which is exact.  On
+ * the device in float64 from the stored instance values, one workgroup per
+ * support (gathered columns, accelerated proximal gradient, the dual bound
+ * of the restricted problem every 10 steps), blocking.  Outputs per
+ * support: values[i] = the objective at the returned coefficients (attained
+ * there), lower_bounds[i] = a certified lower bound of v(S_i) (weak
+ * duality, <= values[i]), betas (NULL or count x p: the coefficients, 0 off
+ * S_i), status (NULL or count: 0 when (value - bound) <= rel_tol |value|, 2
+ * at the step limit) and iterations (NULL or count).  rel_tol 0 -> 1e-9;
+ * max_iters 0 -> 20000.  branch_and_bound re-optimises through the same
+ * kernel when k <= 64.  KBNB_E_INVALID_ARGUMENT for an index outside
+ * [0, p), a repeated index or more than 64 features.
+ */
+int evaluate_supports(kbnb_problem *prob, int32_t count, const int32_t *supports, double rel_tol,
+                      int32_t max_iters, double *values, double *lower_bounds, double *betas,
+                      int32_t *status, int32_t *iterations);
+
+/*
  * Support-level Rashomon set (Sec. 4.5, "Rashomon-set collection"): with
  * opts->rashomon set, branch_and_bound also collects every support S with
  * |S| <= k and v(S) <= (1 + rashomon_eps) Phi* (or the best rashomon_n of

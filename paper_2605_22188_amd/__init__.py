@@ -96,7 +96,7 @@ EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
            "branch_and_bound", "rashomon_entry", "autotune", "last_error", "prox_batch",
            "certify_batch", "problem_info", "kernel_stats", "pool_create", "pool_destroy",
            "pool_add", "pool_info", "pool_export", "pool_record", "rashomon_pool",
-           "rashomon_reliance", "pool_summary"]
+           "rashomon_reliance", "pool_summary", "evaluate_supports"]
 
 _lib = None
 
@@ -131,6 +131,7 @@ def load():
         lib.rashomon_pool.argtypes = [vp, ctypes.POINTER(vp)]
         lib.rashomon_reliance.argtypes = [vp, vp, vp]
         lib.pool_summary.argtypes = [vp, i32, vp, vp]
+        lib.evaluate_supports.argtypes = [vp, i32, vp, dbl, i32, vp, vp, vp, vp, vp]
         for name in EXPORTS:
             if name != "last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -437,6 +438,27 @@ class Pool:
         _check(load().pool_record(self.ptr, int(m), _p(seq), ctypes.byref(n), _p(coef),
                                   ctypes.byref(v)))
         return tuple(int(j) for j in seq[:n.value]), coef[:n.value].copy(), v.value
+
+
+def evaluate_supports(h: Handle, supports, rel_tol=0.0, max_iters=0):
+    """Batched re-optimisation of supports (each a sequence of feature
+    indices); returns dict of arrays: value, lower_bound, beta (count x p),
+    status, iterations."""
+    count = len(supports)
+    sup = np.full((max(count, 1), h.k), -1, np.int32)
+    for i, S in enumerate(supports):
+        S = list(S)
+        assert len(S) <= h.k
+        sup[i, :len(S)] = S
+    val = np.zeros(max(count, 1))
+    low = np.zeros(max(count, 1))
+    bet = np.zeros((max(count, 1), h.p))
+    st = np.zeros(max(count, 1), np.int32)
+    it = np.zeros(max(count, 1), np.int32)
+    _check(load().evaluate_supports(h.ptr, count, _p(sup), float(rel_tol), int(max_iters), _p(val),
+                                    _p(low), _p(bet), _p(st), _p(it)))
+    return dict(value=val[:count], lower_bound=low[:count], beta=bet[:count], status=st[:count],
+                iterations=it[:count])
 
 
 SUMMARY_ROWS = ("freq", "mean", "abs_mean", "pos_frac", "coef_min", "coef_max",

@@ -85,6 +85,10 @@ int set_error(int code, const char *fmt, ...);
 kbnb_pool *pool_new();
 void pool_append(kbnb_pool *pl, const std::vector<int32_t> &seq, const double *coef, double v);
 void store_rashomon(const kbnb_problem *P, kbnb_pool *pl);
+// batched support re-optimisation on the device (kbnb_engine.hip)
+int eval_supports(kbnb_problem *P, const int32_t *lab, const int64_t *off, int count, int maxlen,
+                  const double *warm, double tol, int max_iter, double *values, double *lower, double *coefs,
+                  int32_t *status, int32_t *iters);
 }  // namespace kbnb
 
 extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kbnb_bnb_result *res)
@@ -182,8 +186,51 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     double global_lb = -INFINITY;
     double last_log = 0.0;
 
+    // Support evaluations: with k <= 64 and n <= 32768 they are batched into
+    // the dedicated re-optimisation kernel (flush_supports, between device
+    // rounds of the driver); otherwise each is the node J1 = S, J0 =
+    // complement.  The kernel walks all n rows of a support in one workgroup
+    // per step, which stops paying off on tall instances, where the batched
+    // node contractions are faster.
+    const bool dev_reopt = k <= 64 && info[0] <= 32768;
+    std::vector<std::vector<int32_t>> pending;
+    auto flush_supports = [&]() -> int {
+        if (pending.empty()) return 0;
+        std::vector<int32_t> lab;
+        std::vector<int64_t> off(1, 0);
+        int maxlen = 0;
+        for (const auto &S : pending) {
+            lab.insert(lab.end(), S.begin(), S.end());
+            off.push_back((int64_t)lab.size());
+            maxlen = std::max(maxlen, (int)S.size());
+        }
+        const size_t cnt = pending.size();
+        std::vector<double> val(cnt), low(cnt), coef(std::max<size_t>(lab.size(), 1));
+        int erc = kbnb::eval_supports(P, lab.data(), off.data(), (int)cnt, maxlen, nullptr, support_tol, max_it,
+                                      val.data(), low.data(), coef.data(), nullptr, nullptr);
+        if (erc) return erc;
+        std::vector<double> dense;
+        for (size_t i = 0; i < cnt; ++i) {
+            const std::vector<int32_t> &S = pending[i];
+            const double v = val[i];
+            // a dense beta only for a support that is kept
+            const bool keep = std::isfinite(v) && (v < UB || (rs && v <= tau() && !recorded.count(S)));
+            if (keep) {
+                dense.assign(p, 0.0);
+                for (size_t r = 0; r < S.size(); ++r) dense[(size_t)S[r]] = coef[(size_t)off[i] + r];
+            }
+            take_support(S, v, low[i], keep ? dense.data() : nullptr);
+        }
+        pending.clear();
+        return 0;
+    };
     // a support evaluation: the node J1 = S, J0 = complement
     auto support_desc = [&](const std::vector<int32_t> &S, std::vector<kbnb_node_desc> &dst) {
+        if (dev_reopt) {
+            pending.push_back(S);
+            evaluated.insert(S);
+            return;
+        }
         std::vector<char> ins(p, 0);
         for (int j : S) ins[j] = 1;
         std::vector<int32_t> comp;
@@ -294,6 +341,8 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             flight_lb.insert(o->lb);
             --room;
         }
+        rc = flush_supports();
+        if (rc) break;
         // warm-start and index pointers are set once the storage no longer moves
         {
             size_t wsi = 0;
@@ -373,12 +422,15 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             }
             delete o;
         }
+        rc = flush_supports();
+        if (rc) break;
         if (!evals.empty()) {
             bind_sets(evals);
             rc = submit_nodes(P, evals.data(), (int32_t)evals.size());
             if (rc) break;
         }
     }
+    if (!rc) rc = flush_supports();
     // drain in-flight work so the handle is reusable
     while (!flight.empty()) {
         int32_t got = 0;

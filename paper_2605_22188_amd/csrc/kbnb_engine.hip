@@ -150,6 +150,9 @@ struct kbnb_problem {
     char *slot_host = nullptr;  // two pinned mirrors of that block
     size_t slot_bytes = 0;
     hipStream_t stream = nullptr;
+    hipStream_t sstream = nullptr;  // support re-optimisation (created on first use)
+    void *sbuf = nullptr;           // its device buffers, grown on demand
+    size_t sbuf_bytes = 0;
     hipStream_t gstream = nullptr;  // gathers beside a round enqueued ahead (created on first use:
                                     // streams share the process's few hardware queues)
     hipEvent_t ev_round[2] = {nullptr, nullptr};
@@ -789,6 +792,9 @@ static void free_problem(kbnb_problem *P)
     void *pins[] = {P->stage_h, P->slot_host, P->h_gslots, P->h_gbuf};
     for (void *q : pins)
         if (q) (void)hipHostFree(q);
+    if (P->sstream) (void)hipStreamSynchronize(P->sstream);
+    if (P->sbuf) (void)hipFree(P->sbuf);
+    if (P->sstream) (void)hipStreamDestroy(P->sstream);
     if (P->gstream) (void)hipStreamDestroy(P->gstream);
     if (P->stream) (void)hipStreamDestroy(P->stream);
     delete P;
@@ -1210,6 +1216,106 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     if (supports) HIP_TRY(hipMemcpyAsync(supports, dsup, (size_t)m * P->k * 4, hipMemcpyDeviceToHost, T.s));
     if (branch) HIP_TRY(hipMemcpyAsync(branch, djs, (size_t)m * 4, hipMemcpyDeviceToHost, T.s));
     HIP_TRY(hipStreamSynchronize(T.s));
+    return KBNB_OK;
+}
+
+namespace kbnb {
+// Batched support re-optimisation on the problem's side stream (the engine's
+// rounds continue meanwhile).  Supports: lab[off[i] .. off[i + 1]), at most
+// SUPPORT_EVAL_MAX labels each, validated by the caller; coefs out in the
+// same layout.  Blocking.
+int eval_supports(kbnb_problem *P, const int32_t *lab, const int64_t *off, int count, int maxlen,
+                  const double *warm, double tol, int max_iter, double *values, double *lower, double *coefs,
+                  int32_t *status, int32_t *iters)
+{
+    if (count <= 0) return KBNB_OK;
+    if (maxlen > SUPPORT_EVAL_MAX)
+        return fail(KBNB_E_INVALID_ARGUMENT, "support of %d features (at most %d)", maxlen, SUPPORT_EVAL_MAX);
+    std::lock_guard<std::mutex> g(P->api_mu);
+    if (!P->sstream) HIP_TRY(hipStreamCreate(&P->sstream));
+    const size_t C = (size_t)off[count], Cn = std::max<size_t>(C, 1), N = (size_t)count;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t b_lab = al(Cn * 4), b_off = al((N + 1) * 8), b_warm = al(Cn * 8), b_coef = al(Cn * 8),
+                 b_val = al(N * 8), b_low = al(N * 8), b_st = al(N * 4), b_it = al(N * 4);
+    const size_t need = b_lab + b_off + b_warm + b_coef + b_val + b_low + b_st + b_it;
+    if (need > P->sbuf_bytes) {
+        HIP_TRY(hipStreamSynchronize(P->sstream));
+        if (P->sbuf) (void)hipFree(P->sbuf);
+        P->sbuf = nullptr;
+        P->sbuf_bytes = 0;
+        const size_t want = std::max(need, (size_t)1 << 20);
+        if (hipMalloc(&P->sbuf, want) != hipSuccess) return fail(KBNB_E_OUT_OF_MEMORY, "hipMalloc failed");
+        P->sbuf_bytes = want;
+    }
+    char *b = (char *)P->sbuf;
+    int32_t *dlab = (int32_t *)b; b += b_lab;
+    int64_t *doff = (int64_t *)b; b += b_off;
+    double *dwarm = (double *)b; b += b_warm;
+    double *dcoef = (double *)b; b += b_coef;
+    double *dval = (double *)b; b += b_val;
+    double *dlow = (double *)b; b += b_low;
+    int32_t *dst = (int32_t *)b; b += b_st;
+    int32_t *dit = (int32_t *)b;
+    hipStream_t s = P->sstream;
+    HIP_TRY(hipMemcpyAsync(dlab, lab, 4 * C, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(doff, off, 8 * (N + 1), hipMemcpyHostToDevice, s));
+    if (warm) HIP_TRY(hipMemcpyAsync(dwarm, warm, 8 * C, hipMemcpyHostToDevice, s));
+    if (launch_support_eval(s, P->xtype, P->XT, P->npad, P->n, P->loss, P->y, dlab, doff, count, maxlen,
+                            warm ? dwarm : nullptr, P->lambda2, P->M, tol, max_iter, 10, dcoef, dval, dlow, dst,
+                            dit) != 0)
+        return fail(KBNB_E_INVALID_ARGUMENT, "support too long");
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(values, dval, 8 * N, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(lower, dlow, 8 * N, hipMemcpyDeviceToHost, s));
+    if (coefs) HIP_TRY(hipMemcpyAsync(coefs, dcoef, 8 * C, hipMemcpyDeviceToHost, s));
+    if (status) HIP_TRY(hipMemcpyAsync(status, dst, 4 * N, hipMemcpyDeviceToHost, s));
+    if (iters) HIP_TRY(hipMemcpyAsync(iters, dit, 4 * N, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return KBNB_OK;
+}
+}  // namespace kbnb
+
+extern "C" int evaluate_supports(kbnb_problem *P, int32_t count, const int32_t *supports, double rel_tol,
+                                 int32_t max_iters, double *values, double *lower_bounds, double *betas,
+                                 int32_t *status, int32_t *iterations)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (count < 0 || (count > 0 && (!supports || !values || !lower_bounds)))
+        return fail(KBNB_E_INVALID_ARGUMENT, "supports, values and lower_bounds are required");
+    if (count == 0) return KBNB_OK;
+    if (!(rel_tol >= 0.0) || max_iters < 0) return fail(KBNB_E_INVALID_ARGUMENT, "bad rel_tol or max_iters");
+    const double tol = rel_tol > 0.0 ? rel_tol : 1e-9;
+    const int mi = max_iters > 0 ? max_iters : 20000;
+    const int k = P->k, p = P->p;
+    std::vector<int32_t> lab;
+    std::vector<int64_t> off(1, 0);
+    std::vector<char> seen(p, 0);
+    int maxlen = 0;
+    for (int i = 0; i < count; ++i) {
+        const int32_t *S = supports + (size_t)i * k;
+        int len = 0;
+        while (len < k && S[len] >= 0) ++len;
+        for (int r = 0; r < len; ++r) {
+            if (S[r] >= p) return fail(KBNB_E_INVALID_ARGUMENT, "support %d: index %d outside [0, %d)", i, S[r], p);
+            if (seen[S[r]]) return fail(KBNB_E_INVALID_ARGUMENT, "support %d: index %d repeated", i, S[r]);
+            seen[S[r]] = 1;
+            lab.push_back(S[r]);
+        }
+        for (int r = 0; r < len; ++r) seen[S[r]] = 0;
+        maxlen = std::max(maxlen, len);
+        off.push_back((int64_t)lab.size());
+    }
+    if (maxlen > SUPPORT_EVAL_MAX)
+        return fail(KBNB_E_INVALID_ARGUMENT, "supports of more than %d features", SUPPORT_EVAL_MAX);
+    std::vector<double> coefs(std::max<size_t>(lab.size(), 1));
+    int rc = kbnb::eval_supports(P, lab.data(), off.data(), count, maxlen, nullptr, tol, mi, values, lower_bounds,
+                                 coefs.data(), status, iterations);
+    if (rc) return rc;
+    if (betas) {
+        std::fill(betas, betas + (size_t)count * p, 0.0);
+        for (int i = 0; i < count; ++i)
+            for (int64_t q = off[i]; q < off[i + 1]; ++q) betas[(size_t)i * p + lab[(size_t)q]] = coefs[(size_t)q];
+    }
     return KBNB_OK;
 }
 

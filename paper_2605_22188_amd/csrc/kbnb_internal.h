@@ -140,6 +140,14 @@ void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int
 // coefficients are lab/coef[off[m] .. off[m + 1]); out has the same layout
 void launch_reliance(hipStream_t s, int xtype, const void *XT, int64_t npad, int n, int loss, const double *y,
                      const int32_t *lab, const int64_t *off, const double *coef, int nrec, double *out);
+// batched support re-optimisation in float64 (supports of at most 64 features;
+// returns -1 when maxlen exceeds that); lab/off as for launch_reliance
+constexpr int SUPPORT_EVAL_MAX = 64;
+int launch_support_eval(hipStream_t s, int xtype, const void *XT, int64_t npad, int n, int loss,
+                        const double *y, const int32_t *lab, const int64_t *off, int count, int maxlen,
+                        const double *warm, double lambda2, double M, double tol, int max_iter,
+                        int cert_every, double *beta_out, double *value, double *lower, int32_t *status,
+                        int32_t *iters);
 // convert/transposed copies
 void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
                       int npad, int pm);

@@ -1957,6 +1957,310 @@ void launch_reliance(hipStream_t s, int xtype, const void *XT, int64_t npad, int
         KBNB_LAUNCH((k_reliance<uint16_t>), grid, dim3(256), 0, s, (const uint16_t *)XT, npad, n, loss, y, lab, off, coef, out);
 }
 
+// ---------------------------------------------------------------------------
+// Batched support re-optimisation (Sec. 4.3): for each support S of at most
+// KB features,
+//   v(S) = min { F(X_S beta) + lambda2 ||beta||^2 : |beta_j| <= M },
+// the relaxation of the node J1 = S, J0 = the rest, which is exact.  One
+// workgroup (256 threads) per support, float64 throughout, from the stored
+// values of the support's rows of X^T (columns of X, contiguous over i):
+//   1. the Gram matrix X_S^T X_S in one pass over LDS row tiles; the step
+//      1 / L uses L = c_l min(||G||_F, max_r sum_q |G_rq|) >= c_l lambda_max;
+//   2. accelerated proximal gradient on the |S| coordinates (prox of
+//      lambda2 beta^2 plus the box: clip(u / (1 + 2 eta lambda2), +-M)),
+//      gradient restart, one pass over X_S per step;
+//   3. every `cert_every` steps the certificate at beta: Phi = F(X_S beta) +
+//      lambda2 ||beta||^2 and the dual value at zeta = -l'(X_S beta),
+//      Psi = -sum l*(-zeta) - 2 lambda2 sum_j H_M(x_j^T zeta / (2 lambda2)),
+//      a lower bound of v(S) by weak duality; stop when
+//      (Phi_best - Psi_best) <= tol |Phi_best|.
+// Returns the best certified beta (it attains value = Phi_best), the best
+// Psi, status (0 converged, 2 iteration limit) and the steps taken.
+// ---------------------------------------------------------------------------
+struct SupportArgs {
+    const void *XT;
+    int64_t npad;
+    int n, loss;
+    const double *y;
+    const int32_t *lab;    // labels of support m: lab[off[m] .. off[m + 1])
+    const int64_t *off;
+    const double *warm;    // nullable: starting coefficients, same layout
+    double lambda2, M, c_loss, tol;
+    int max_iter, cert_every;
+    double *beta_out;      // same layout as lab
+    double *value, *lower;
+    int32_t *status, *iters;
+};
+
+template <typename TA, int KB>
+__global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
+{
+    constexpr int TR = 2048 / KB;  // rows per Gram tile (128, 64 or 32)
+    constexpr int NPAIR = KB * (KB + 1) / 2;
+    constexpr int PT = (NPAIR + 255) / 256;
+    __shared__ int32_t L[KB];
+    __shared__ double Bv[KB], Bp[KB], Yv[KB], Bb[KB], Bn[KB];
+    __shared__ double G[KB][KB + 1];
+    __shared__ double tile[TR][KB + 1];
+    __shared__ double red[4][KB + 2];
+    __shared__ double sc[8];  // eta, theta, tmom, phi_best, psi_best, done, restart dot
+    const TA *XT = reinterpret_cast<const TA *>(a.XT);
+    const int m = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t o0 = a.off[m];
+    const int kl = (int)(a.off[m + 1] - o0);
+    if (tid < KB) {
+        L[tid] = (tid < kl) ? a.lab[o0 + tid] : 0;
+        double w = (a.warm && tid < kl) ? a.warm[o0 + tid] : 0.0;
+        w = fmin(fmax(w, -a.M), a.M);
+        Bv[tid] = w;
+        Bp[tid] = w;
+        Yv[tid] = w;
+        Bb[tid] = w;
+    }
+    __syncthreads();
+
+    // 1. Gram matrix: thread t owns pairs t + 256 v, (r, q) with r <= q
+    int pr[PT], pq[PT];
+    double gacc[PT];
+#pragma unroll
+    for (int v = 0; v < PT; ++v) {
+        int pi = tid + 256 * v, r = 0;
+        const int np = kl * (kl + 1) / 2;
+        if (pi < np) {
+            while (pi >= kl - r) { pi -= kl - r; ++r; }
+            pr[v] = r;
+            pq[v] = r + pi;
+        } else {
+            pr[v] = -1;
+            pq[v] = 0;
+        }
+        gacc[v] = 0.0;
+    }
+    for (int i0 = 0; i0 < a.n && kl > 0; i0 += TR) {
+        for (int e = tid; e < TR * kl; e += 256) {
+            const int r = e / TR, row = e - r * TR, i = i0 + row;
+            tile[row][r] = (i < a.n) ? cvt_d(XT[(int64_t)L[r] * a.npad + i]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < PT; ++v) {
+            if (pr[v] >= 0) {
+                double acc = 0.0;
+                for (int row = 0; row < TR; ++row) acc += tile[row][pr[v]] * tile[row][pq[v]];
+                gacc[v] += acc;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < PT; ++v) {
+        if (pr[v] >= 0) {
+            G[pr[v]][pq[v]] = gacc[v];
+            G[pq[v]][pr[v]] = gacc[v];
+        }
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double rs = 0.0, fr = 0.0;
+        if (tid < kl)
+            for (int q = 0; q < kl; ++q) {
+                rs += fabs(G[tid][q]);
+                fr += G[tid][q] * G[tid][q];
+            }
+        double gmax = rs;
+        for (int o = 32; o > 0; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o));
+        fr = wave_sum(fr);
+        if (tid == 0) {
+            double lam = fmin(sqrt(fr), gmax);
+            const double Lc = a.c_loss * lam;
+            sc[0] = (Lc > 0.0) ? 1.0 / (Lc * 1.000001) : 1.0;
+            sc[1] = 0.0;        // theta
+            sc[2] = 1.0;        // t
+            sc[3] = INFINITY;   // best primal
+            sc[4] = -INFINITY;  // best dual
+            sc[5] = 0.0;        // done
+        }
+    }
+    __syncthreads();
+    const double eta = sc[0];
+    const double shrink = 1.0 / (1.0 + 2.0 * eta * a.lambda2);
+    int it = 0;
+    for (;; ++it) {
+        const bool cert = (it % a.cert_every) == 0 || it >= a.max_iter;
+        // pass over the rows: gradient at Y, or (cert) the certificate at beta
+        double g[KB];
+#pragma unroll
+        for (int r = 0; r < KB; ++r) g[r] = 0.0;
+        double al = 0.0, ac = 0.0;
+        const double *pt = cert ? Bv : Yv;
+        // U rows per thread at a time (rows past n read row 0 and contribute
+        // 0), so their loads are in flight together; U shrinks as KB grows to
+        // keep the row values the two passes share in registers
+        constexpr int U = (KB <= 16) ? 4 : ((KB <= 32) ? 2 : 1);
+        for (int i0 = tid; i0 < a.n; i0 += 256 * U) {
+            int64_t ri[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ok[u] = i0 + 256 * u < a.n;
+                ri[u] = ok[u] ? i0 + 256 * u : 0;
+            }
+            double sv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) sv[u] = 0.0;
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                if (r < kl) {
+                    const TA *col = XT + (int64_t)L[r] * a.npad;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) sv[u] += cvt_d(col[ri[u]]) * pt[r];
+                }
+            }
+            double dv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double yi = a.y[ri[u]];
+                if (cert) {
+                    double z, lv, cv;
+                    cert_terms(a.loss, sv[u], yi, z, lv, cv);
+                    al += ok[u] ? lv : 0.0;
+                    ac += ok[u] ? cv : 0.0;
+                    dv[u] = ok[u] ? z : 0.0;
+                } else {
+                    dv[u] = ok[u] ? dloss_d(a.loss, sv[u], yi) : 0.0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                if (r < kl) {
+                    const TA *col = XT + (int64_t)L[r] * a.npad;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acc += cvt_d(col[ri[u]]) * dv[u];
+                    g[r] += acc;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            if (r < kl) {
+                const double v = wave_sum(g[r]);
+                if (lane == 0) red[wave][r] = v;
+            }
+        }
+        if (cert) {
+            al = wave_sum(al);
+            ac = wave_sum(ac);
+            if (lane == 0) {
+                red[wave][KB] = al;
+                red[wave][KB + 1] = ac;
+            }
+        }
+        __syncthreads();
+        if (cert) {
+            if (tid < 64) {
+                // q_r = x_r^T zeta / (2 lambda2); penalty and dual terms over r < kl
+                double pen = 0.0, dterm = 0.0;
+                if (tid < kl) {
+                    const double qv = (red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]) / (2.0 * a.lambda2);
+                    pen = Bv[tid] * Bv[tid];
+                    dterm = huber(qv, a.M);
+                }
+                pen = wave_sum(pen);
+                dterm = wave_sum(dterm);
+                if (tid == 0) {
+                    const double fl = red[0][KB] + red[1][KB] + red[2][KB] + red[3][KB];
+                    const double fc = red[0][KB + 1] + red[1][KB + 1] + red[2][KB + 1] + red[3][KB + 1];
+                    const double phi = fl + a.lambda2 * pen;
+                    const double psi = -fc - 2.0 * a.lambda2 * dterm;
+                    if (phi < sc[3]) {
+                        sc[3] = phi;
+                        sc[6] = 1.0;  // take beta as the best
+                    } else {
+                        sc[6] = 0.0;
+                    }
+                    if (psi > sc[4]) sc[4] = psi;
+                    const double den = fmax(fabs(sc[3]), 1e-12);
+                    sc[5] = ((sc[3] - sc[4]) <= a.tol * den || it >= a.max_iter) ? 1.0 : 0.0;
+                }
+            }
+            __syncthreads();
+            if (tid < kl && sc[6] != 0.0) Bb[tid] = Bv[tid];
+            if (sc[5] != 0.0) break;
+            __syncthreads();
+            continue;  // the certificate pass takes no step
+        }
+        // proximal step from Y, restart test, momentum
+        if (tid < 64) {
+            double dot = 0.0;
+            if (tid < kl) {
+                const double gr = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+                const double u = Yv[tid] - eta * gr;
+                const double bn = fmin(fmax(u * shrink, -a.M), a.M);
+                Bn[tid] = bn;
+                dot = (Yv[tid] - bn) * (bn - Bv[tid]);
+            }
+            dot = wave_sum(dot);
+            if (tid == 0) {
+                const double tm = sc[2];
+                if (dot > 0.0) {
+                    sc[2] = 1.0;
+                    sc[1] = 0.0;
+                } else {
+                    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tm * tm));
+                    sc[1] = (tm - 1.0) / tn;
+                    sc[2] = tn;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < kl) {
+            const double th = sc[1];
+            Bp[tid] = Bv[tid];
+            Bv[tid] = Bn[tid];
+            Yv[tid] = Bn[tid] + th * (Bn[tid] - Bp[tid]);
+        }
+        __syncthreads();
+    }
+    if (tid < kl) a.beta_out[o0 + tid] = Bb[tid];
+    if (tid == 0) {
+        a.value[m] = sc[3];
+        a.lower[m] = fmin(sc[4], sc[3]);
+        a.status[m] = (sc[3] - sc[4] <= a.tol * fmax(fabs(sc[3]), 1e-12)) ? 0 : 2;
+        a.iters[m] = it;
+    }
+}
+
+int launch_support_eval(hipStream_t s, int xtype, const void *XT, int64_t npad, int n, int loss,
+                        const double *y, const int32_t *lab, const int64_t *off, int count, int maxlen,
+                        const double *warm, double lambda2, double M, double tol, int max_iter,
+                        int cert_every, double *beta_out, double *value, double *lower, int32_t *status,
+                        int32_t *iters)
+{
+    if (count <= 0) return 0;
+    SupportArgs a{};
+    a.XT = XT; a.npad = npad; a.n = n; a.loss = loss; a.y = y; a.lab = lab; a.off = off; a.warm = warm;
+    a.lambda2 = lambda2; a.M = M; a.c_loss = (loss == 0) ? 2.0 : 0.25; a.tol = tol;
+    a.max_iter = max_iter; a.cert_every = cert_every;
+    a.beta_out = beta_out; a.value = value; a.lower = lower; a.status = status; a.iters = iters;
+    const dim3 grid(count);
+#define KBNB_SUP(TA, KB) KBNB_LAUNCH((k_support_eval<TA, KB>), grid, dim3(256), 0, s, a)
+#define KBNB_SUP_T(TA)                      \
+    do {                                    \
+        if (maxlen <= 16) KBNB_SUP(TA, 16); \
+        else if (maxlen <= 32) KBNB_SUP(TA, 32); \
+        else KBNB_SUP(TA, 64);              \
+    } while (0)
+    if (maxlen > 64) return -1;
+    if (xtype == XT_F64) KBNB_SUP_T(double);
+    else if (xtype == XT_F32) KBNB_SUP_T(float);
+    else KBNB_SUP_T(uint16_t);
+#undef KBNB_SUP_T
+#undef KBNB_SUP
+    return 0;
+}
+
 void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
                       int npad, int pm)
 {
