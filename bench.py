@@ -73,6 +73,20 @@ def measured_traffic(kernel):
     return blob["traffic_bytes_per_launch"].get(kernel)
 
 
+def host_cpu():
+    """The host's CPU model and logical core count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def run_batch(K, h, prep, out):
     """Submit one prepared batch through the C ABI and wait for every result
     (polled into the preallocated `out`); returns (results in completion
@@ -301,64 +315,75 @@ def serving_leg(K, W, torch, args):
     t_sat = time.perf_counter() - t0
     sat_rate = 32 * burst / t_sat
     log(f"serving: saturated {sat_rate:.0f} node bounds/s")
-    # Poisson stream
-    lam = args.serve_load * sat_rate / 32
-    dur = args.serve_seconds
-    lat, converged, done = [], [0], [0]
-    lock = threading.Lock()
+    def stream(load, seed0):
+        """Poisson arrivals at `load` times the saturated rate for serve_seconds;
+        runs until every request has its result."""
+        lam = load * sat_rate / 32
+        dur = args.serve_seconds
+        lat, converged, done = [], [0], [0]
+        lock = threading.Lock()
+        rng_i = [np.random.Generator(np.random.PCG64(seed0 + i)) for i in range(32)]
+        requests_i = [requests(i, int(lam * dur * 2) + 16) for i in range(32)]
+        t_start = [0.0]
 
-    def run(i):
-        h = handles[i]
-        arr = np.cumsum(rng_i[i].exponential(1.0 / lam, size=int(lam * dur * 2) + 16))
-        arr = arr[arr < dur]
-        nodes = requests_i[i][:len(arr)]
-        start = t_start[0]
-        sub, nxt = {}, 0
-        while nxt < len(arr) or sub:
-            now = time.perf_counter() - start
-            due = []
-            while nxt < len(arr) and arr[nxt] <= now:
-                due.append(nxt)
-                nxt += 1
-            if due:
-                K.submit_nodes(h, [nodes[j] for j in due], tags=due, rel_tol=1e-6,
-                               max_iters=it_cap)
-                for j in due:
-                    sub[j] = arr[j]
-            wait = (arr[nxt] - now) if nxt < len(arr) else 0.05
-            res, _ = K.poll_bounds(h, cap=1024, timeout_us=max(0, int(wait * 1e6)),
-                                   supports=False, betas=False)
-            tnow = time.perf_counter() - start
-            with lock:
-                for r in res:
-                    a = sub.pop(r["tag"])
-                    lat.append(tnow - a)
-                    done[0] += 1
-                    converged[0] += r["status"] == K.CONVERGED
+        def run(i):
+            h = handles[i]
+            arr = np.cumsum(rng_i[i].exponential(1.0 / lam, size=int(lam * dur * 2) + 16))
+            arr = arr[arr < dur]
+            nodes = requests_i[i][:len(arr)]
+            start = t_start[0]
+            sub, nxt = {}, 0
+            while nxt < len(arr) or sub:
+                now = time.perf_counter() - start
+                due = []
+                while nxt < len(arr) and arr[nxt] <= now:
+                    due.append(nxt)
+                    nxt += 1
+                if due:
+                    K.submit_nodes(h, [nodes[j] for j in due], tags=due, rel_tol=1e-6,
+                                   max_iters=it_cap)
+                    for j in due:
+                        sub[j] = arr[j]
+                wait = (arr[nxt] - now) if nxt < len(arr) else 0.05
+                res, _ = K.poll_bounds(h, cap=1024, timeout_us=max(0, int(wait * 1e6)),
+                                       supports=False, betas=False)
+                tnow = time.perf_counter() - start
+                with lock:
+                    for r in res:
+                        a = sub.pop(r["tag"])
+                        lat.append(tnow - a)
+                        done[0] += 1
+                        converged[0] += r["status"] == K.CONVERGED
 
-    rng_i = [np.random.Generator(np.random.PCG64(900 + i)) for i in range(32)]
-    requests_i = [requests(i, int(lam * dur * 2) + 16) for i in range(32)]
-    t_start = [time.perf_counter()]
-    threads = [threading.Thread(target=run, args=(i,)) for i in range(32)]
-    for th in threads:
-        th.start()
-    for th in threads:
-        th.join()
-    wall = time.perf_counter() - t_start[0]
+        t_start[0] = time.perf_counter()
+        threads = [threading.Thread(target=run, args=(i,)) for i in range(32)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        wall = time.perf_counter() - t_start[0]
+        lat_ms = np.array(lat) * 1e3
+        log(f"serving: load {load}: {done[0]} requests in {wall:.1f}s, "
+            f"p50 {np.percentile(lat_ms, 50):.2f} ms, p99 {np.percentile(lat_ms, 99):.2f} ms")
+        return {"offered_load": load, "requests": int(done[0]), "seconds": round(wall, 2),
+                "bounds_per_s": round(done[0] / wall, 1),
+                "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                               "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+                "converged_fraction": round(converged[0] / max(1, done[0]), 4)}
+
+    main = stream(args.serve_load, 900)
+    sweep = None
+    if args.serve_sweep:
+        sweep = [stream(float(x), 2000 + 100 * j) for j, x in enumerate(args.serve_sweep.split(","))]
     for h in handles:
         K.destroy_problem(h)
-    lat_ms = np.array(lat) * 1e3
-    log(f"serving: {done[0]} requests in {wall:.1f}s, p50 {np.percentile(lat_ms, 50):.2f} ms, "
-        f"p99 {np.percentile(lat_ms, 99):.2f} ms")
-    return {"workload": "serving_mix_32_problems_f32", "problems": 32,
-            "offered_load": args.serve_load, "saturated_rate": round(sat_rate, 1),
-            "requests": int(done[0]), "seconds": round(wall, 2),
-            "bounds_per_s": round(done[0] / wall, 1),
-            "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
-                           "p99": round(float(np.percentile(lat_ms, 99)), 3)},
-            "converged_fraction": round(converged[0] / max(1, done[0]), 4),
-            "max_iters": it_cap, "batch_widths": widths,
-            "budget_bytes_per_problem": 2 << 30}
+    res = {"workload": "serving_mix_32_problems_f32", "problems": 32,
+           "saturated_rate": round(sat_rate, 1), "max_iters": it_cap, "batch_widths": widths,
+           "budget_bytes_per_problem": 2 << 30}
+    res.update(main)
+    if sweep is not None:
+        res["sweep"] = sweep
+    return res
 
 
 def run_stream(K, h, preps, out, window):
@@ -409,6 +434,10 @@ def main():
     ap.add_argument("--window", type=int, default=1,
                     help="batches in flight (the next is submitted when one completes)")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repetitions of the K steps (value is the first)")
+    ap.add_argument("--cpu-par-nodes", type=int, default=64,
+                    help="nodes of the node-parallel oracle run (0: skip)")
     ap.add_argument("--cpu-nodes", type=int, default=24,
                     help="oracle sample size for the CPU baseline (0 = skip)")
     ap.add_argument("--comparator-nodes", type=int, default=32,
@@ -421,6 +450,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.5)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--serve-iters", type=int, default=2000)
+    ap.add_argument("--serve-sweep", type=str, default="",
+                    help="comma-separated offered loads to sweep after the main point")
     ap.add_argument("--large", type=int, default=1,
                     help="run the 100000 x 5000 bfloat16 logistic node-bound leg")
     ap.add_argument("--large-batch", type=int, default=256)
@@ -492,6 +523,16 @@ def main():
     nodes_done = args.steps * args.batch
     value = nodes_done / elapsed
     log(f"timed: {nodes_done} nodes in {elapsed:.4f}s -> {value:.1f} node bounds/s")
+    # the same K batches timed again (value is the first run; the spread of
+    # the repetitions is reported beside it)
+    reps = [value]
+    for _ in range(max(0, args.repeats - 1)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_stream(K, h, preps[args.warmup:args.warmup + args.steps], out, args.window)
+        torch.cuda.synchronize()
+        reps.append(nodes_done / (time.perf_counter() - t1))
+    log(f"repetitions: {[round(v) for v in reps]}")
 
     # kernel-timed pass (same configuration, fresh batches)
     K.kernel_stats(h, 1)
@@ -571,8 +612,24 @@ def main():
                "kind": "oracle",
                "sample": (f"first {len(sample)} nodes of batch seed 1000 of the 5000x200 logistic "
                           f"workload, rel. tol {args.tol:g}, float64, one thread, "
-                          f"{tcpu:.1f}s")}
+                          f"{tcpu:.1f}s"),
+               "host": host_cpu()}
         log(f"cpu oracle: {cpu['value']} node bounds/s")
+        if args.cpu_par_nodes > 0:
+            # node-parallel: independent nodes on the host's cores (the
+            # oracle's C calls release the interpreter lock)
+            from concurrent.futures import ThreadPoolExecutor
+            threads = max(1, min(16, os.cpu_count() or 1))
+            par = batches[0][:args.cpu_par_nodes]
+            tpar = time.perf_counter()
+            with ThreadPoolExecutor(threads) as ex:
+                list(ex.map(lambda nd: P.node_bound(W.node_state(p, nd), tol=args.tol), par))
+            tpar = time.perf_counter() - tpar
+            cpu["node_parallel"] = {
+                "value": round(len(par) / tpar, 3), "unit": "node bounds/s", "cores": threads,
+                "kind": "oracle, node-parallel threads",
+                "sample": f"first {len(par)} nodes of batch seed 1000, {tpar:.1f}s"}
+            log(f"cpu oracle node-parallel: {cpu['node_parallel']}")
 
     ttz = bnb_leg(K, W, torch, args) if args.bnb else None
     serving = serving_leg(K, W, torch, args) if args.serving else None
@@ -602,6 +659,8 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "measure": "submission of the node's batch to its result at poll"},
+        "repetitions": {"values": [round(v, 1) for v in reps],
+                        "median": round(float(np.median(reps)), 1)},
         "iterations": {"mean": round(float(np.mean(iters)), 2), "max": int(np.max(iters))},
         "not_converged": int(status_bad),
         "max_rel_gap": float(np.max(gaps)),
