@@ -182,6 +182,8 @@ typedef struct {
     int32_t rashomon;        /* nonzero: also collect the support-level Rashomon set */
     int32_t rashomon_n;      /* keep only the best N supports (0 -> all) */
     double rashomon_eps;     /* set threshold (1 + eps) Phi*, eps >= 0 */
+    int32_t node_order;      /* open-node order: 0 best bound (ties: deeper, then first in),
+                                1 depth first (ties: smaller bound, then first in) */
 } kbnb_bnb_options;
 
 typedef struct {
@@ -200,9 +202,11 @@ typedef struct {
 } kbnb_bnb_result;
 
 /*
- * branch_and_bound -- blocking best-bound branch and bound built on
- * submit_nodes / poll_bounds (Sec. 4.1, Fig. 1): the host keeps the open-node
- * queue; each batch of open nodes is bounded on the device; a node is pruned
+ * branch_and_bound -- blocking branch and bound built on submit_nodes /
+ * poll_bounds (Sec. 4.1, Fig. 1): the host keeps the open-node queue (best
+ * bound first, or depth first with opts->node_order = 1; the reported lower
+ * bound is the least bound of the whole tree in either order); each batch of
+ * open nodes is bounded on the device; a node is pruned
  * when its bound reaches the incumbent; otherwise its rounding support is
  * re-optimised (Sec. 4.3) to update the incumbent, and the node is branched
  * on the free coordinate with the largest |beta_j| into z_j = 0 / z_j = 1

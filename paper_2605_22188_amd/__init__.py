@@ -66,7 +66,7 @@ class BnbOptions(ctypes.Structure):
                 ("node_rel_tol", ctypes.c_double), ("max_fista_iters", ctypes.c_int32),
                 ("max_nodes", ctypes.c_int64), ("log_every_s", ctypes.c_double),
                 ("rashomon", ctypes.c_int32), ("rashomon_n", ctypes.c_int32),
-                ("rashomon_eps", ctypes.c_double)]
+                ("rashomon_eps", ctypes.c_double), ("node_order", ctypes.c_int32)]
 
 
 class BnbResult(ctypes.Structure):
@@ -342,17 +342,19 @@ def bound_nodes(h: Handle, nodes, **kw):
 
 def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=0.0,
                      max_fista_iters=0, max_nodes=0, log_every_s=0.0, rashomon_eps=None,
-                     rashomon_n=0):
+                     rashomon_n=0, node_order=0):
     """rashomon_eps (>= 0): also collect the support-level Rashomon set (the
     best rashomon_n when nonzero), returned as "rashomon": a list of
-    (support tuple, value, beta) ordered by value."""
+    (support tuple, value, beta) ordered by value.  node_order: 0 best bound,
+    1 depth first."""
     sup = np.full(h.k, -1, np.int32)
     beta = np.zeros(h.p)
     o = BnbOptions(time_limit_s=time_limit_s, rel_gap_tol=rel_gap_tol,
                    node_rel_tol=node_rel_tol, max_fista_iters=max_fista_iters,
                    max_nodes=max_nodes, log_every_s=log_every_s,
                    rashomon=0 if rashomon_eps is None else 1, rashomon_n=int(rashomon_n),
-                   rashomon_eps=0.0 if rashomon_eps is None else float(rashomon_eps))
+                   rashomon_eps=0.0 if rashomon_eps is None else float(rashomon_eps),
+                   node_order=int(node_order))
     r = BnbResult(support=_p(sup), beta=_p(beta))
     _check(load().branch_and_bound(h.ptr, ctypes.byref(o), ctypes.byref(r)))
     out = dict(objective=r.objective, lower_bound=r.lower_bound, rel_gap=r.rel_gap,

@@ -2,8 +2,9 @@
 // poll_bounds (paper Sec. 4.1, Fig. 1; Sec. 4.3), and the support-level
 // Rashomon-set collection on the same tree (Sec. 4.5).
 //
-// The host owns the tree: the open-node queue ordered by parent bound (deeper
-// first on ties, then first-in), the incumbent and the global bound.  The
+// The host owns the tree: the open-node queue (by parent bound, deeper first
+// on ties, then first-in; or depth first on request), the incumbent and the
+// global bound.  The
 // device bounds whole batches: the driver keeps up to two batch widths of
 // nodes in flight so finished slots are refilled at once.  For every node
 // that survives its bound:
@@ -54,9 +55,13 @@ struct Open {
     std::vector<double> wv;
 };
 
+// Queue order: best bound (smaller bound, then deeper, then first in), or
+// depth first (deeper, then smaller bound, then first in).
 struct OpenCmp {
+    bool dfs = false;
     bool operator()(const Open *a, const Open *b) const
     {
+        if (dfs && a->depth != b->depth) return a->depth < b->depth;
         if (a->lb != b->lb) return a->lb > b->lb;
         if (a->depth != b->depth) return a->depth < b->depth;
         return a->seq > b->seq;
@@ -115,7 +120,21 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     const auto t0 = std::chrono::steady_clock::now();
     auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
 
-    std::priority_queue<Open *, std::vector<Open *>, OpenCmp> open;
+    if (opt->node_order != 0 && opt->node_order != 1)
+        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "node_order must be 0 or 1");
+    const bool dfs = opt->node_order == 1;
+    std::priority_queue<Open *, std::vector<Open *>, OpenCmp> open(OpenCmp{dfs});
+    std::multiset<double> open_lbs;  // bounds of the open nodes (the least is the queue's)
+    auto push_open = [&](Open *o) {
+        open_lbs.insert(o->lb);
+        open.push(o);
+    };
+    auto pop_open = [&]() {
+        Open *o = open.top();
+        open.pop();
+        open_lbs.erase(open_lbs.find(o->lb));
+        return o;
+    };
     std::map<uint64_t, Flight> flight;
     std::multiset<double> flight_lb;
     std::set<std::vector<int32_t>> evaluated;            // supports submitted or known
@@ -174,7 +193,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     root->lb = -INFINITY;
     root->depth = 0;
     root->seq = seq++;
-    open.push(root);
+    push_open(root);
 
     const int cap_flight = 2 * m;
     std::vector<kbnb_node_desc> batch;
@@ -266,16 +285,13 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     };
 
     for (;;) {
-        // drop open nodes that the incumbent prunes (the queue is ordered by bound)
-        while (!open.empty() && prunable(open.top()->lb)) {
-            leaf_lb = std::min(leaf_lb, open.top()->lb);
-            // every remaining node has a bound at least as large
-            while (!open.empty()) {
-                delete open.top();
-                open.pop();
-            }
+        // drop open nodes that the incumbent prunes: when the least open
+        // bound is prunable, every open node is
+        if (!open_lbs.empty() && prunable(*open_lbs.begin())) {
+            leaf_lb = std::min(leaf_lb, *open_lbs.begin());
+            while (!open.empty()) delete pop_open();
         }
-        double lb_open = open.empty() ? INFINITY : open.top()->lb;
+        double lb_open = open_lbs.empty() ? INFINITY : *open_lbs.begin();
         double lb_fl = flight_lb.empty() ? INFINITY : *flight_lb.begin();
         global_lb = std::min(lb_open, lb_fl);
         bool support_pending = false;
@@ -299,8 +315,12 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         set_store.clear();
         int room = cap_flight - (int)flight.size();
         while (room > 0 && !open.empty()) {
-            Open *o = open.top();
-            open.pop();
+            Open *o = pop_open();
+            if (prunable(o->lb)) {  // depth first: pruned at the pop
+                leaf_lb = std::min(leaf_lb, o->lb);
+                delete o;
+                continue;
+            }
             if (rs && is_leaf(o)) {
                 // Rashomon leaf: its support J1 is evaluated (once)
                 auto known = support_lb.find(o->in);
@@ -418,7 +438,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                         c->wv.push_back(beta[q]);
                     }
                 }
-                open.push(c);
+                push_open(c);
             }
             delete o;
         }
@@ -456,9 +476,9 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         if (got == 0 && prc == KBNB_TIMEOUT) break;  // nothing is progressing
     }
     while (!open.empty()) {
-        global_lb = std::min(global_lb, open.top()->lb);
-        delete open.top();
-        open.pop();
+        Open *o = pop_open();
+        global_lb = std::min(global_lb, o->lb);
+        delete o;
     }
     for (auto &w : leaf_waiting) global_lb = std::min(global_lb, w.second);
     if (rc) return rc;

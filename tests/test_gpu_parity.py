@@ -242,18 +242,42 @@ def test_invalid_nodes_are_rejected_atomically():
     K.destroy_problem(h)
 
 
-def test_bnb_plain_squared_500x30_on_gpu():
-    announce("branch_and_bound squared 500x30 f64")
+@pytest.mark.parametrize("order", [0, 1])
+def test_bnb_plain_squared_500x30_on_gpu(order):
+    announce(f"branch_and_bound squared 500x30 f64, node order {order}")
     inst = W.plain_bnb_squared_500x30()
     P = oracle.Problem.from_instance(inst)
     ref = P.bnb()
     h = K.create_from_instance(inst, batch_width=64)
-    out = K.branch_and_bound(h)
+    out = K.branch_and_bound(h, node_order=order)
     assert out["status"] == 0
     assert list(out["support"]) == list(ref["support"])
     assert out["objective"] == pytest.approx(ref["objective"], rel=1e-6)
     assert out["lower_bound"] <= ref["objective"] * (1 + 1e-9)
+    assert out["rel_gap"] <= 1e-6
+    with pytest.raises(K.KbnbError):
+        K.branch_and_bound(h, node_order=2)
     K.destroy_problem(h)
+
+
+def test_bnb_depth_first_logistic_and_rashomon():
+    announce("branch_and_bound depth first: logistic 80x9 and its Rashomon set")
+    inst = W.small_instance(80, 9, 3, W.LOGISTIC, seed=50, rho=0.5)
+    P = oracle.Problem.from_instance(inst)
+    ref = P.rashomon(0.15, node_tol=1e-9)
+    h = K.create_from_instance(inst, batch_width=64)
+    best = K.branch_and_bound(h)
+    dfs = K.branch_and_bound(h, node_order=1)
+    assert dfs["status"] == 0 and dfs["rel_gap"] <= 1e-6
+    assert list(dfs["support"]) == list(best["support"])
+    assert dfs["objective"] == pytest.approx(ref["optimum"], rel=1e-6)
+    rs = K.branch_and_bound(h, node_order=1, rashomon_eps=0.15)
+    K.destroy_problem(h)
+    band = 2e-6 * abs(ref["threshold"])
+    got = {S for S, _, _ in rs["rashomon"]}
+    for S, v in ref["set"]:
+        if v < ref["threshold"] - band:
+            assert S in got, S
 
 
 @pytest.mark.parametrize("n,p,k,loss,dtype,it", [(1500, 3000, 10, W.LOGISTIC, "bf16", 0),
