@@ -511,6 +511,10 @@ def main():
 
     run_stream(K, h, preps[:args.warmup], out, args.window)
     log(f"warmup done ({args.warmup} steps)")
+    # the driver's own garbage collection stays out of the timed regions
+    import gc
+    gc.collect()
+    gc.disable()
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -532,6 +536,7 @@ def main():
         run_stream(K, h, preps[args.warmup:args.warmup + args.steps], out, args.window)
         torch.cuda.synchronize()
         reps.append(nodes_done / (time.perf_counter() - t1))
+    gc.enable()
     log(f"repetitions: {[round(v) for v in reps]}")
 
     # kernel-timed pass (same configuration, fresh batches)
