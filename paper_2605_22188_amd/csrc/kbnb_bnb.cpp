@@ -91,9 +91,10 @@ kbnb_pool *pool_new();
 void pool_append(kbnb_pool *pl, const std::vector<int32_t> &seq, const double *coef, double v);
 void store_rashomon(const kbnb_problem *P, kbnb_pool *pl);
 // batched support re-optimisation on the device (kbnb_engine.hip)
-int eval_supports(kbnb_problem *P, const int32_t *lab, const int64_t *off, int count, int maxlen,
-                  const double *warm, double tol, int max_iter, double *values, double *lower, double *coefs,
-                  int32_t *status, int32_t *iters);
+int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off, int count, int maxlen,
+                         const double *warm, double tol, int max_iter);
+int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double *coefs, int32_t *status,
+                          int32_t *iters);
 }  // namespace kbnb
 
 extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kbnb_bnb_result *res)
@@ -204,44 +205,69 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     std::vector<double> betas((size_t)m * p);
     double global_lb = -INFINITY;
     double last_log = 0.0;
+    double t_poll = 0, t_flush = 0, t_fill = 0, t_res = 0;  // host time split (progress lines)
 
     // Support evaluations: with k <= 64 and n <= 32768 they are batched into
-    // the dedicated re-optimisation kernel (flush_supports, between device
-    // rounds of the driver); otherwise each is the node J1 = S, J0 =
+    // the dedicated re-optimisation kernel (one batch on the device at a
+    // time, beside the node rounds); otherwise each is the node J1 = S, J0 =
     // complement.  The kernel walks all n rows of a support in one workgroup
     // per step, which stops paying off on tall instances, where the batched
     // node contractions are faster.
     const bool dev_reopt = k <= 64 && info[0] <= 32768;
-    std::vector<std::vector<int32_t>> pending;
-    auto flush_supports = [&]() -> int {
-        if (pending.empty()) return 0;
-        std::vector<int32_t> lab;
-        std::vector<int64_t> off(1, 0);
-        int maxlen = 0;
-        for (const auto &S : pending) {
-            lab.insert(lab.end(), S.begin(), S.end());
-            off.push_back((int64_t)lab.size());
-            maxlen = std::max(maxlen, (int)S.size());
-        }
-        const size_t cnt = pending.size();
-        std::vector<double> val(cnt), low(cnt), coef(std::max<size_t>(lab.size(), 1));
-        int erc = kbnb::eval_supports(P, lab.data(), off.data(), (int)cnt, maxlen, nullptr, support_tol, max_it,
-                                      val.data(), low.data(), coef.data(), nullptr, nullptr);
+    // One batch of support evaluations is on the device at a time: each pass
+    // of the loop collects the batch launched in the previous pass (it ran
+    // while the host filled and processed nodes) and launches the pending
+    // supports.
+    std::vector<std::vector<int32_t>> pending, inflight;
+    std::vector<int32_t> in_lab;   // inputs of the batch in flight, alive until collected
+    std::vector<int64_t> in_off;
+    auto collect_supports = [&]() -> int {
+        if (inflight.empty()) return 0;
+        const size_t cnt = inflight.size();
+        std::vector<double> val(cnt), low(cnt), coef(std::max<size_t>(in_lab.size(), 1));
+        int erc = kbnb::eval_supports_collect(P, val.data(), low.data(), coef.data(), nullptr, nullptr);
         if (erc) return erc;
         std::vector<double> dense;
         for (size_t i = 0; i < cnt; ++i) {
-            const std::vector<int32_t> &S = pending[i];
+            const std::vector<int32_t> &S = inflight[i];
             const double v = val[i];
             // a dense beta only for a support that is kept
             const bool keep = std::isfinite(v) && (v < UB || (rs && v <= tau() && !recorded.count(S)));
             if (keep) {
                 dense.assign(p, 0.0);
-                for (size_t r = 0; r < S.size(); ++r) dense[(size_t)S[r]] = coef[(size_t)off[i] + r];
+                for (size_t r = 0; r < S.size(); ++r) dense[(size_t)S[r]] = coef[(size_t)in_off[i] + r];
             }
             take_support(S, v, low[i], keep ? dense.data() : nullptr);
         }
+        inflight.clear();
+        return 0;
+    };
+    auto launch_supports = [&]() -> int {
+        if (pending.empty() || !inflight.empty()) return 0;
+        in_lab.clear();
+        in_off.assign(1, 0);
+        int maxlen = 0;
+        for (const auto &S : pending) {
+            in_lab.insert(in_lab.end(), S.begin(), S.end());
+            in_off.push_back((int64_t)in_lab.size());
+            maxlen = std::max(maxlen, (int)S.size());
+        }
+        int erc = kbnb::eval_supports_launch(P, in_lab.data(), in_off.data(), (int)pending.size(), maxlen, nullptr,
+                                             support_tol, max_it);
+        if (erc) return erc;
+        inflight.swap(pending);
         pending.clear();
         return 0;
+    };
+    // collect the batch in flight and launch the pending one
+    auto cycle_supports = [&]() -> int {
+        int erc = collect_supports();
+        return erc ? erc : launch_supports();
+    };
+    // everything evaluated (blocking)
+    auto flush_supports = [&]() -> int {
+        int erc = cycle_supports();
+        return erc ? erc : collect_supports();
     };
     // a support evaluation: the node J1 = S, J0 = complement
     auto support_desc = [&](const std::vector<int32_t> &S, std::vector<kbnb_node_desc> &dst) {
@@ -294,22 +320,35 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         double lb_open = open_lbs.empty() ? INFINITY : *open_lbs.begin();
         double lb_fl = flight_lb.empty() ? INFINITY : *flight_lb.begin();
         global_lb = std::min(lb_open, lb_fl);
-        bool support_pending = false;
+        const bool batch_pending = !pending.empty() || !inflight.empty();
+        bool support_pending = batch_pending;
         for (auto &f : flight)
             if (f.second.kind == FL_SUPPORT) { support_pending = true; break; }
-        if (open.empty() && flight.empty()) break;
-        if (!rs && std::isfinite(UB) && !support_pending && global_lb >= UB - gap_tol * std::fabs(UB)) break;
+        const bool bound_met = !rs && std::isfinite(UB) && global_lb >= UB - gap_tol * std::fabs(UB);
+        if ((open.empty() && flight.empty()) || (bound_met && batch_pending)) {
+            // nothing else to wait for: settle the support evaluations first
+            if (!batch_pending) break;
+            double tm0 = elapsed();
+            rc = flush_supports();
+            t_flush += elapsed() - tm0;
+            if (rc) break;
+            continue;
+        }
+        if (bound_met && !support_pending) break;
         if (opt->time_limit_s > 0 && elapsed() > opt->time_limit_s) { status = 1; break; }
         if (opt->max_nodes > 0 && nodes >= opt->max_nodes) { status = 2; break; }
         if (opt->log_every_s > 0 && elapsed() - last_log >= opt->log_every_s) {
             last_log = elapsed();
-            fprintf(stderr, "[bnb] %.1fs nodes %lld open %zu in flight %zu UB %.10g LB %.10g%s\n",
-                    last_log, (long long)nodes, open.size(), flight.size(), UB,
-                    std::min(global_lb, leaf_lb), rs ? " (collecting)" : "");
+            fprintf(stderr,
+                    "[bnb] %.1fs nodes %lld open %zu in flight %zu UB %.10g LB %.10g%s "
+                    "(host s: poll %.2f supports %.2f fill %.2f results %.2f)\n",
+                    last_log, (long long)nodes, open.size(), flight.size(), UB, std::min(global_lb, leaf_lb),
+                    rs ? " (collecting)" : "", t_poll, t_flush, t_fill, t_res);
             fflush(stderr);
         }
 
         // fill the device
+        double tm = elapsed();
         batch.clear();
         warm_store.clear();
         set_store.clear();
@@ -361,8 +400,8 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             flight_lb.insert(o->lb);
             --room;
         }
-        rc = flush_supports();
-        if (rc) break;
+        t_fill += elapsed() - tm;
+        tm = elapsed();
         // warm-start and index pointers are set once the storage no longer moves
         {
             size_t wsi = 0;
@@ -376,11 +415,15 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             rc = submit_nodes(P, batch.data(), (int32_t)batch.size());
             if (rc) break;
         }
+        t_fill += elapsed() - tm;
         // collect results
+        tm = elapsed();
         int32_t got = 0;
         rc = poll_bounds(P, out.data(), m, &got, sup.data(), betas.data(), 200000);
+        t_poll += elapsed() - tm;
         if (rc < 0) break;
         rc = 0;
+        tm = elapsed();
         std::vector<kbnb_node_desc> evals;
         set_store.clear();
         for (int r = 0; r < got; ++r) {
@@ -421,6 +464,13 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 for (int q = 0; q < p && j < 0; ++q)
                     if (!dec[q]) j = q;
             }
+            std::vector<int32_t> wi;
+            std::vector<double> wv;
+            for (int q = 0; q < p; ++q)
+                if (beta[q] != 0.0) {
+                    wi.push_back(q);
+                    wv.push_back(beta[q]);
+                }
             for (int side = 0; side < 2; ++side) {
                 Open *c = new Open();
                 c->lb = lb;
@@ -432,17 +482,19 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 else c->in.push_back(j);
                 std::sort(c->in.begin(), c->in.end());
                 std::sort(c->out.begin(), c->out.end());
-                for (int q = 0; q < p; ++q) {
-                    if (beta[q] != 0.0 && !(side == 0 && q == j)) {
-                        c->wi.push_back(q);
-                        c->wv.push_back(beta[q]);
-                    }
+                for (size_t r = 0; r < wi.size(); ++r) {
+                    if (side == 0 && wi[r] == j) continue;  // z_j = 0 zeroes beta_j
+                    c->wi.push_back(wi[r]);
+                    c->wv.push_back(wv[r]);
                 }
                 push_open(c);
             }
             delete o;
         }
-        rc = flush_supports();
+        t_res += elapsed() - tm;
+        tm = elapsed();
+        rc = cycle_supports();
+        t_flush += elapsed() - tm;
         if (rc) break;
         if (!evals.empty()) {
             bind_sets(evals);
@@ -451,6 +503,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         }
     }
     if (!rc) rc = flush_supports();
+    else if (!inflight.empty()) (void)collect_supports();  // leave no batch on the device
     // drain in-flight work so the handle is reusable
     while (!flight.empty()) {
         int32_t got = 0;

@@ -153,6 +153,11 @@ struct kbnb_problem {
     hipStream_t sstream = nullptr;  // support re-optimisation (created on first use)
     void *sbuf = nullptr;           // its device buffers, grown on demand
     size_t sbuf_bytes = 0;
+    hipEvent_t sev = nullptr;       // end of the support batch in flight
+    int s_count = 0;                // that batch: supports and stored coefficients
+    int64_t s_coefs = 0;
+    double *s_val = nullptr, *s_low = nullptr, *s_coef = nullptr;
+    int32_t *s_st = nullptr, *s_it = nullptr;
     hipStream_t gstream = nullptr;  // gathers beside a round enqueued ahead (created on first use:
                                     // streams share the process's few hardware queues)
     hipEvent_t ev_round[2] = {nullptr, nullptr};
@@ -793,6 +798,7 @@ static void free_problem(kbnb_problem *P)
     for (void *q : pins)
         if (q) (void)hipHostFree(q);
     if (P->sstream) (void)hipStreamSynchronize(P->sstream);
+    if (P->sev) (void)hipEventDestroy(P->sev);
     if (P->sbuf) (void)hipFree(P->sbuf);
     if (P->sstream) (void)hipStreamDestroy(P->sstream);
     if (P->gstream) (void)hipStreamDestroy(P->gstream);
@@ -1222,17 +1228,20 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
 namespace kbnb {
 // Batched support re-optimisation on the problem's side stream (the engine's
 // rounds continue meanwhile).  Supports: lab[off[i] .. off[i + 1]), at most
-// SUPPORT_EVAL_MAX labels each, validated by the caller; coefs out in the
-// same layout.  Blocking.
-int eval_supports(kbnb_problem *P, const int32_t *lab, const int64_t *off, int count, int maxlen,
-                  const double *warm, double tol, int max_iter, double *values, double *lower, double *coefs,
-                  int32_t *status, int32_t *iters)
+// SUPPORT_EVAL_MAX labels each, validated by the caller.  eval_supports_launch
+// enqueues one batch (inputs are copied before it returns); the matching
+// eval_supports_collect waits for it and copies the results out (coefs in
+// the layout of lab).  One batch at a time per problem.
+int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off, int count, int maxlen,
+                         const double *warm, double tol, int max_iter)
 {
-    if (count <= 0) return KBNB_OK;
     if (maxlen > SUPPORT_EVAL_MAX)
         return fail(KBNB_E_INVALID_ARGUMENT, "support of %d features (at most %d)", maxlen, SUPPORT_EVAL_MAX);
     std::lock_guard<std::mutex> g(P->api_mu);
+    if (P->s_count > 0) return fail(KBNB_E_INVALID_ARGUMENT, "a support batch is already in flight");
+    if (count <= 0) return KBNB_OK;
     if (!P->sstream) HIP_TRY(hipStreamCreate(&P->sstream));
+    if (!P->sev) HIP_TRY(hipEventCreateWithFlags(&P->sev, hipEventDisableTiming));
     const size_t C = (size_t)off[count], Cn = std::max<size_t>(C, 1), N = (size_t)count;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t b_lab = al(Cn * 4), b_off = al((N + 1) * 8), b_warm = al(Cn * 8), b_coef = al(Cn * 8),
@@ -1251,27 +1260,54 @@ int eval_supports(kbnb_problem *P, const int32_t *lab, const int64_t *off, int c
     int32_t *dlab = (int32_t *)b; b += b_lab;
     int64_t *doff = (int64_t *)b; b += b_off;
     double *dwarm = (double *)b; b += b_warm;
-    double *dcoef = (double *)b; b += b_coef;
-    double *dval = (double *)b; b += b_val;
-    double *dlow = (double *)b; b += b_low;
-    int32_t *dst = (int32_t *)b; b += b_st;
-    int32_t *dit = (int32_t *)b;
+    P->s_coef = (double *)b; b += b_coef;
+    P->s_val = (double *)b; b += b_val;
+    P->s_low = (double *)b; b += b_low;
+    P->s_st = (int32_t *)b; b += b_st;
+    P->s_it = (int32_t *)b;
     hipStream_t s = P->sstream;
     HIP_TRY(hipMemcpyAsync(dlab, lab, 4 * C, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(doff, off, 8 * (N + 1), hipMemcpyHostToDevice, s));
     if (warm) HIP_TRY(hipMemcpyAsync(dwarm, warm, 8 * C, hipMemcpyHostToDevice, s));
     if (launch_support_eval(s, P->xtype, P->XT, P->npad, P->n, P->loss, P->y, dlab, doff, count, maxlen,
-                            warm ? dwarm : nullptr, P->lambda2, P->M, tol, max_iter, 10, dcoef, dval, dlow, dst,
-                            dit) != 0)
+                            warm ? dwarm : nullptr, P->lambda2, P->M, tol, max_iter, 10, P->s_coef, P->s_val,
+                            P->s_low, P->s_st, P->s_it) != 0)
         return fail(KBNB_E_INVALID_ARGUMENT, "support too long");
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(values, dval, 8 * N, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(lower, dlow, 8 * N, hipMemcpyDeviceToHost, s));
-    if (coefs) HIP_TRY(hipMemcpyAsync(coefs, dcoef, 8 * C, hipMemcpyDeviceToHost, s));
-    if (status) HIP_TRY(hipMemcpyAsync(status, dst, 4 * N, hipMemcpyDeviceToHost, s));
-    if (iters) HIP_TRY(hipMemcpyAsync(iters, dit, 4 * N, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(P->sev, s));
+    // the pageable-source copies above have consumed the inputs by now
+    P->s_count = count;
+    P->s_coefs = (int64_t)C;
+    return KBNB_OK;
+}
+
+int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double *coefs, int32_t *status,
+                          int32_t *iters)
+{
+    std::lock_guard<std::mutex> g(P->api_mu);
+    const size_t N = (size_t)P->s_count, C = (size_t)P->s_coefs;
+    if (N == 0) return KBNB_OK;
+    P->s_count = 0;
+    hipStream_t s = P->sstream;
+    HIP_TRY(hipEventSynchronize(P->sev));
+    HIP_TRY(hipMemcpyAsync(values, P->s_val, 8 * N, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(lower, P->s_low, 8 * N, hipMemcpyDeviceToHost, s));
+    if (coefs && C) HIP_TRY(hipMemcpyAsync(coefs, P->s_coef, 8 * C, hipMemcpyDeviceToHost, s));
+    if (status) HIP_TRY(hipMemcpyAsync(status, P->s_st, 4 * N, hipMemcpyDeviceToHost, s));
+    if (iters) HIP_TRY(hipMemcpyAsync(iters, P->s_it, 4 * N, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return KBNB_OK;
+}
+
+// Blocking: one batch, launched and collected.
+int eval_supports(kbnb_problem *P, const int32_t *lab, const int64_t *off, int count, int maxlen,
+                  const double *warm, double tol, int max_iter, double *values, double *lower, double *coefs,
+                  int32_t *status, int32_t *iters)
+{
+    if (count <= 0) return KBNB_OK;
+    int rc = eval_supports_launch(P, lab, off, count, maxlen, warm, tol, max_iter);
+    if (rc) return rc;
+    return eval_supports_collect(P, values, lower, coefs, status, iters);
 }
 }  // namespace kbnb
 
