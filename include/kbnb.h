@@ -84,6 +84,10 @@ extern "C" {
 #define KBNB_PRUNED 1    /* lower_bound >= upper_bound - 1e-6 * |upper_bound| */
 #define KBNB_MAXITER 2   /* iteration cap reached; the bound is still valid */
 #define KBNB_ERROR 3     /* non-finite iterate; the bound is the last valid one */
+#define KBNB_UNPRUNABLE 4 /* stopped early (stop_unprunable): primal_value < upper_bound -
+                             1e-6 |upper_bound|, so the node value is below the pruning
+                             threshold and no bound can prune it; lower_bound is
+                             certified but not tight */
 
 typedef struct kbnb_problem kbnb_problem;
 
@@ -114,6 +118,10 @@ typedef struct {
     double upper_bound;         /* incumbent for pruning; +inf = solve to rel_tol */
     double rel_tol;             /* 0 -> 1e-6 */
     int32_t max_iters;          /* 0 -> 20000 */
+    int32_t stop_unprunable;    /* nonzero: stop with KBNB_UNPRUNABLE as soon as a
+                                   certificate shows that the node cannot be pruned
+                                   by a finite upper_bound (branch and bound only
+                                   needs to branch it) */
 } kbnb_node_desc;
 
 typedef struct {
@@ -121,7 +129,7 @@ typedef struct {
     double lower_bound;   /* certified float64 dual value, <= the node optimum */
     double primal_value;  /* float64 primal value of the returned iterate */
     double rel_gap;       /* (primal_value - lower_bound) / max(|primal_value|, 1e-12) */
-    int32_t status;       /* KBNB_CONVERGED / PRUNED / MAXITER / ERROR */
+    int32_t status;       /* KBNB_CONVERGED / PRUNED / MAXITER / ERROR / UNPRUNABLE */
     int32_t iterations;
     int32_t branch_index; /* argmax of |beta_j| over free j (lowest index on ties); -1 if none */
     int32_t support_len;  /* |J1| + min(kbar, #free): length of the rounding support */

@@ -23,7 +23,7 @@ OK, TIMEOUT = 0, 1
 SQUARED, LOGISTIC = 0, 1
 DTYPE_F64, DTYPE_F32, DTYPE_BF16 = 0, 1, 2
 MEM_HOST_COPY, MEM_DEVICE_COPY, MEM_DEVICE_BORROW = 0, 1, 2
-CONVERGED, PRUNED, MAXITER, ERROR = 0, 1, 2, 3
+CONVERGED, PRUNED, MAXITER, ERROR, UNPRUNABLE = 0, 1, 2, 3, 4
 _DTYPES = {"f64": DTYPE_F64, "f32": DTYPE_F32, "bf16": DTYPE_BF16}
 ITER_AUTO, ITER_F32, ITER_F64, ITER_ANCHORED = 0, 1, 2, 3
 _ITERS = {0: ITER_AUTO, "auto": ITER_AUTO, "f32": ITER_F32, "f64": ITER_F64,
@@ -51,7 +51,7 @@ class NodeDesc(ctypes.Structure):
                 ("fixed_in", ctypes.c_void_p), ("n_out", ctypes.c_int32),
                 ("fixed_out", ctypes.c_void_p), ("warm_start", ctypes.c_void_p),
                 ("upper_bound", ctypes.c_double), ("rel_tol", ctypes.c_double),
-                ("max_iters", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("stop_unprunable", ctypes.c_int32)]
 
 
 class BoundResult(ctypes.Structure):
@@ -244,7 +244,7 @@ def destroy_problem(h: Handle):
         _check(load().destroy_problem(ptr))
 
 
-def _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts):
+def _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts, stop_unprunable=0):
     """Marshal node descriptors; returns (ctypes array, arrays to keep alive)."""
     count = len(nodes)
     arr = (NodeDesc * max(count, 1))()
@@ -266,7 +266,8 @@ def _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts):
                           fixed_out=_p(fout) if len(fout) else None,
                           warm_start=_p(w) if w is not None else None,
                           upper_bound=float(pick(upper_bound, i)),
-                          rel_tol=float(pick(rel_tol, i)), max_iters=int(pick(max_iters, i)))
+                          rel_tol=float(pick(rel_tol, i)), max_iters=int(pick(max_iters, i)),
+                          stop_unprunable=int(pick(stop_unprunable, i)))
     return arr, keep
 
 
@@ -295,11 +296,12 @@ def poll_raw(h: Handle, out, cap, timeout_us=-1):
 
 
 def submit_nodes(h: Handle, nodes, upper_bound=math.inf, rel_tol=0.0, max_iters=0, tags=None,
-                 warm_starts=None):
+                 warm_starts=None, stop_unprunable=0):
     """nodes: sequence of (fixed_in, fixed_out) index arrays (or objects with
-    .fixed_in / .fixed_out).  Per-node upper_bound / rel_tol / max_iters may be
-    scalars or sequences."""
-    arr, keep = _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts)
+    .fixed_in / .fixed_out).  Per-node upper_bound / rel_tol / max_iters /
+    stop_unprunable may be scalars or sequences."""
+    arr, keep = _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts,
+                            stop_unprunable)
     _check(load().submit_nodes(h.ptr, arr, len(nodes)))
     del keep
 

@@ -393,6 +393,14 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             d.upper_bound = rs ? tau() * (1.0 + 4e-6) : UB;
             d.rel_tol = node_tol;
             d.max_iters = max_it;
+            // a node that will be branched stops as soon as it cannot be
+            // pruned; one the driver closes (integral: kbar <= 0 or every free
+            // coordinate fits the budget) keeps its tight bound
+            {
+                const int kb = k - (int)o->in.size();
+                const int pf = p - (int)o->in.size() - (int)o->out.size();
+                d.stop_unprunable = (rs || (kb > 0 && pf > kb)) ? 1 : 0;
+            }
             batch.push_back(d);
             Flight f;
             f.node = o;
@@ -452,12 +460,14 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             const int kbar = k - (int)o->in.size();
             const int pf = p - (int)o->in.size() - (int)o->out.size();
             int j = br.branch_index;
-            if (!rs && (kbar <= 0 || pf <= kbar || j < 0)) {
+            // closed: integral, or every free coordinate is zero at a tight
+            // bound (a node stopped early as unprunable is branched instead)
+            if (!rs && (kbar <= 0 || pf <= kbar || (j < 0 && br.status != KBNB_UNPRUNABLE))) {
                 leaf_lb = std::min(leaf_lb, lb);
                 delete o;
                 continue;
             }
-            if (j < 0) {  // Rashomon mode: every free coordinate is zero
+            if (j < 0) {  // every free coordinate is zero: the first free index
                 std::vector<char> dec(p, 0);
                 for (int q : o->in) dec[q] = 1;
                 for (int q : o->out) dec[q] = 1;

@@ -87,6 +87,7 @@ struct PendingNode {
     int kbar, n0;
     double ub, tol;
     int max_iter;
+    int early;
 };
 
 struct DoneNode {
@@ -346,6 +347,7 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
     P->ss.kbar = ii + 3 * mp;
     P->ss.jstar = ii + 4 * mp;
     P->ss.slen = ii + 5 * mp;
+    P->ss.early = ii + 6 * mp;
     P->ss.sup = (int32_t *)(base + off[18]);
     P->Bbest = (double *)(base + off[19]);
     P->ss.perm = (int32_t *)(base + off[20]);
@@ -499,6 +501,7 @@ static int enqueue_round_async(kbnb_problem *P, std::unique_lock<std::mutex> &lk
         h.has_warm = nd.warm.empty() ? 0 : 1;
         h.ub = nd.ub;
         h.tol = nd.tol;
+        h.early = nd.early;
         memcpy(rec, &h, sizeof h);
         memcpy(rec + sizeof(AdmitRec), nd.st.data(), P->ldp);
         if (h.has_warm) {
@@ -1025,6 +1028,7 @@ static int submit_locked(kbnb_problem *P, const kbnb_node_desc *nodes, int count
         pn.ub = nd.upper_bound;
         pn.tol = nd.rel_tol > 0 ? nd.rel_tol : 1e-6;
         pn.max_iter = nd.max_iters > 0 ? nd.max_iters : 20000;
+        pn.early = nd.stop_unprunable != 0;
         staged.push_back(std::move(pn));
     }
     {

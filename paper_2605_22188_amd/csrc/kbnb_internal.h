@@ -56,6 +56,7 @@ struct SlotState {
     int32_t *max_iter;
     int32_t *kbar;    // k - |J1|
     int32_t *jstar;   // branching index
+    int32_t *early;   // nonzero: stop once the node cannot be pruned (primal < ub)
     int32_t *slen;    // rounding-support length
     int32_t *sup;     // [mpad][k] rounding support, ascending, -1 padded
     int32_t *perm;    // [mpad][pp] sorted order of the node's |u| at its last step
@@ -74,6 +75,7 @@ struct Consts {
 struct AdmitRec {
     int32_t slot, kbar, max_iter, has_warm;
     double ub, tol;
+    int32_t early, pad;
 };
 
 enum XType { XT_F64 = 0, XT_F32 = 1, XT_BF16 = 2 };

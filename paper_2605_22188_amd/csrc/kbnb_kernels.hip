@@ -1609,6 +1609,8 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
             if (nan) stt = 3;
             else if (LB >= ub - 1e-6 * fabs(ub)) stt = 1;
             else if (gap <= ss.tol[b]) stt = 0;
+            // the node value lies below PH < ub - 1e-6 |ub|: no bound can prune it
+            else if (ss.early[b] && isfinite(ub) && PH < ub - 1e-6 * fabs(ub)) stt = 4;
             else if (ss.iter[b] >= ss.max_iter[b]) stt = 2;
             ss.status[b] = stt;
         } else {
@@ -1659,6 +1661,7 @@ __global__ __launch_bounds__(64) void k_admit(const uint8_t *__restrict__ stage,
         ss.gap[b] = INFINITY;
         ss.ub[b] = h.ub;
         ss.tol[b] = h.tol;
+        ss.early[b] = h.early;
         ss.iter[b] = 0;
         ss.max_iter[b] = h.max_iter;
         ss.kbar[b] = h.kbar;

@@ -226,6 +226,34 @@ def test_warm_start_and_prune_decisions():
     K.destroy_problem(h)
 
 
+def test_stop_unprunable_decisions():
+    """With stop_unprunable, a node whose value lies 2% below its upper bound
+    stops as UNPRUNABLE (its certified primal value is below the pruning
+    threshold, so its value is too, and its bound is still valid); 2% above,
+    it is PRUNED as before; with no upper bound it converges."""
+    announce("stop_unprunable decisions logistic 2000x80")
+    inst = W.small_instance(2000, 80, 8, W.LOGISTIC, seed=12)
+    P = oracle.Problem.from_instance(inst)
+    nodes = W.random_nodes(80, 40, 4, 20, seed=15)
+    refs = [P.node_bound(W.node_state(80, nd), tol=1e-10) for nd in nodes]
+    r = rng(16)
+    side = r.choice([-1, 1], size=len(nodes))
+    ubs = np.array([ref["phi"] * (1 + 0.02 * s_) for ref, s_ in zip(refs, side)])
+    h = K.create_from_instance(inst, batch_width=64, cert_period=4)
+    res = K.bound_nodes(h, nodes, upper_bound=ubs, rel_tol=1e-6, stop_unprunable=1)
+    for ref, ub, s_, g in zip(refs, ubs, side, res):
+        assert g["lower_bound"] <= ref["phi"] * (1 + 1e-12)
+        if s_ > 0:  # value well below the threshold
+            assert g["status"] == K.UNPRUNABLE, g
+            assert g["primal_value"] < ub - 1e-6 * abs(ub)
+            assert g["primal_value"] >= ref["lb"] * (1 - 1e-12)
+        else:
+            assert g["status"] == K.PRUNED, g
+    res = K.bound_nodes(h, nodes[:8], rel_tol=1e-6, stop_unprunable=1)
+    assert all(g["status"] == K.CONVERGED for g in res)
+    K.destroy_problem(h)
+
+
 def test_invalid_nodes_are_rejected_atomically():
     announce("invalid submissions")
     inst = W.small_instance(100, 10, 3, W.SQUARED, seed=1)
