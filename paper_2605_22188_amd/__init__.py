@@ -108,6 +108,13 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2605_22188_amd.build`")
+        # PyTorch ships its own HIP runtime library under the same soname;
+        # loading torch first makes this process hold one runtime, whichever
+        # of the two the caller touches first
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
         lib.create_problem.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(vp)]

@@ -198,7 +198,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
 
     const int cap_flight = 2 * m;
     std::vector<kbnb_node_desc> batch;
-    std::vector<std::vector<double>> warm_store;
+    std::vector<double> warm_flat;  // dense warm starts of one fill, p entries each
     std::vector<std::vector<int32_t>> set_store;  // index lists of support evaluations
     std::vector<kbnb_bound_result> out(m);
     std::vector<int32_t> sup((size_t)m * k);
@@ -350,7 +350,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         // fill the device
         double tm = elapsed();
         batch.clear();
-        warm_store.clear();
+        size_t nwarm = 0;
         set_store.clear();
         int room = cap_flight - (int)flight.size();
         while (room > 0 && !open.empty()) {
@@ -385,8 +385,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             d.n_out = (int32_t)o->out.size();
             d.fixed_out = o->out.data();
             if (!o->wi.empty()) {
-                warm_store.emplace_back(p, 0.0);
-                for (size_t r = 0; r < o->wi.size(); ++r) warm_store.back()[o->wi[r]] = o->wv[r];
+                ++nwarm;
             }
             // the engine stops a node at bound >= ub - 1e-6 |ub|; in Rashomon
             // mode that must imply bound > tau
@@ -413,9 +412,14 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         // warm-start and index pointers are set once the storage no longer moves
         {
             size_t wsi = 0;
+            warm_flat.assign((size_t)p * nwarm, 0.0);
             for (auto &d : batch) {
                 Flight &f = flight[d.tag];
-                if (f.kind == FL_NODE && !f.node->wi.empty()) d.warm_start = warm_store[wsi++].data();
+                if (f.kind == FL_NODE && !f.node->wi.empty()) {
+                    double *w = warm_flat.data() + (size_t)p * wsi++;
+                    for (size_t r = 0; r < f.node->wi.size(); ++r) w[f.node->wi[r]] = f.node->wv[r];
+                    d.warm_start = w;
+                }
             }
             bind_sets(batch);
         }
@@ -488,10 +492,8 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 c->seq = seq++;
                 c->in = o->in;
                 c->out = o->out;
-                if (side == 0) c->out.push_back(j);
-                else c->in.push_back(j);
-                std::sort(c->in.begin(), c->in.end());
-                std::sort(c->out.begin(), c->out.end());
+                std::vector<int32_t> &grow = (side == 0) ? c->out : c->in;  // both stay sorted
+                grow.insert(std::upper_bound(grow.begin(), grow.end(), j), j);
                 for (size_t r = 0; r < wi.size(); ++r) {
                     if (side == 0 && wi[r] == j) continue;  // z_j = 0 zeroes beta_j
                     c->wi.push_back(wi[r]);
