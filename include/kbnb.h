@@ -101,7 +101,10 @@ typedef struct {
     const void *X;     /* n x p, row-major, leading dimension ldx (elements) */
     int64_t ldx;
     const double *y;   /* length n (logistic: entries -1 or +1) */
-    void *hip_stream;  /* reserved (the library runs on its own stream); NULL */
+    void *hip_stream;  /* NULL, or the caller's hipStream_t that produced X and y
+                          (DEVICE_COPY / DEVICE_BORROW): create_problem waits for
+                          the work queued on it before reading them.  The library
+                          then runs on its own streams. */
     uint64_t hbm_budget_bytes; /* device-memory budget of this problem; 0 = 8 GiB */
     int32_t batch_width;       /* node slots; 0 = chosen from the budget (max 1024) */
     int32_t cert_period;       /* iterations between float64 certificates; 0 = 8 */
@@ -192,6 +195,9 @@ typedef struct {
     double rashomon_eps;     /* set threshold (1 + eps) Phi*, eps >= 0 */
     int32_t node_order;      /* open-node order: 0 best bound (ties: deeper, then first in),
                                 1 depth first (ties: smaller bound, then first in) */
+    int32_t audit;           /* nonzero: record every leaf of the explored tree with the
+                                certificate of its bound (bnb_audit_leaf); costs host
+                                memory of p doubles per bounded node */
 } kbnb_bnb_options;
 
 typedef struct {
@@ -200,14 +206,29 @@ typedef struct {
                            pruned, closed or unexplored node, capped at objective */
     double rel_gap;
     int64_t nodes;      /* nodes bounded */
-    int32_t status;     /* 0 optimal (gap <= tol), 1 time limit, 2 node limit */
+    int32_t status;     /* 0 optimal (gap <= tol), 1 time limit, 2 node limit,
+                           3 tree exhausted with the gap above tol (nodes that hit
+                           their iteration cap leave loose, still valid, bounds) */
     int32_t support_len;
     int32_t *support;   /* caller buffer of k entries: incumbent support (ascending) */
     double *beta;       /* caller buffer of p entries (or NULL): incumbent coefficients */
     int64_t incumbent_updates;
     double seconds;
     int64_t rashomon_size; /* entries of the collected set (0 unless collecting) */
+    int64_t audit_leaves;  /* leaves recorded (0 unless opts->audit) */
 } kbnb_bnb_result;
+
+/*
+ * cancel_nodes -- drop every node of the problem that is queued, running, or
+ * completed but not yet polled: queued nodes are removed, running ones are
+ * stopped at the end of the engine's current round, and none of their
+ * results is ever returned by poll_bounds.  Blocks until every cancelled
+ * node has left its slot, so the handle is idle when it returns (nodes
+ * submitted by other threads meanwhile are not affected).  Passage: Sec. 4.1
+ * (the host owns the frontier and may discard open nodes at any time).
+ * KBNB_E_BAD_HANDLE on NULL; the engine's error if it has stopped.
+ */
+int cancel_nodes(kbnb_problem *prob);
 
 /*
  * branch_and_bound -- blocking branch and bound built on submit_nodes /
@@ -218,11 +239,40 @@ typedef struct {
  * when its bound reaches the incumbent; otherwise its rounding support is
  * re-optimised (Sec. 4.3) to update the incumbent, and the node is branched
  * on the free coordinate with the largest |beta_j| into z_j = 0 / z_j = 1
- * children warm-started from the parent iterate.  The problem's queue must be
- * empty.  result->support must point to k int32 entries.
+ * children warm-started from the parent iterate.  The problem must have no
+ * node queued, running or unpolled (KBNB_E_INVALID_ARGUMENT otherwise); nodes
+ * still in flight when the search stops are cancelled (cancel_nodes), so the
+ * handle is idle on return.  A node that reports KBNB_ERROR fails the call
+ * with KBNB_E_DEVICE.  result->support must point to k int32 entries.
  */
 int branch_and_bound(kbnb_problem *prob, const kbnb_bnb_options *opts,
                      kbnb_bnb_result *result);
+
+/*
+ * bnb_audit_leaf -- leaf i (0-based, in the order the search discarded them)
+ * of the last branch_and_bound on `prob` run with opts->audit.  The leaves
+ * partition the explored tree's discarded subtrees: every feasible support
+ * lies in exactly one leaf or was left in no open node (Sec. 4.1).  A leaf is
+ * the node (J1, J0) in leaf_state (p int8: 1 in, -1 out, 0 free) with
+ *   kind 0: pruned: its bound reached the pruning threshold (Sec. 3, "Safe
+ *           Lower Bound and Pruning"; Sec. 4.5 in Rashomon mode),
+ *   kind 1: closed: its relaxation needs no branching (budget cannot bind,
+ *           or every free coordinate is zero at a tight bound),
+ *   kind 2: Rashomon leaf: the support J1 (J0 = the rest), bounded by its
+ *           re-optimisation's certified bound,
+ *   kind 3: left unexplored when the search stopped,
+ * and *bound the value the search used for it.  Its certificate is a node
+ * (cert_state) that contains the leaf -- the leaf itself or an ancestor --
+ * and the float64 iterate cert_beta (p entries) whose dual point
+ * zeta = -l'(X cert_beta) has dual value *cert_bound = Psi_cert(zeta) >= *bound
+ * (eqs. prelim_fenchel_dual, dual_candidate_vector_form): replaying Psi at
+ * that point checks the bound independently of the device arithmetic.  A
+ * leaf with no certificate (bound -inf) gets zero arrays and -inf.  Any
+ * output pointer may be NULL.  KBNB_E_INVALID_ARGUMENT when nothing was
+ * audited or i is out of range.
+ */
+int bnb_audit_leaf(kbnb_problem *prob, int64_t i, int32_t *kind, double *bound, int8_t *leaf_state,
+                   int8_t *cert_state, double *cert_beta, double *cert_bound);
 
 /*
  * evaluate_supports -- batched re-optimisation of supports (Sec. 4.3): for

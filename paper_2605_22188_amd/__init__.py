@@ -66,7 +66,8 @@ class BnbOptions(ctypes.Structure):
                 ("node_rel_tol", ctypes.c_double), ("max_fista_iters", ctypes.c_int32),
                 ("max_nodes", ctypes.c_int64), ("log_every_s", ctypes.c_double),
                 ("rashomon", ctypes.c_int32), ("rashomon_n", ctypes.c_int32),
-                ("rashomon_eps", ctypes.c_double), ("node_order", ctypes.c_int32)]
+                ("rashomon_eps", ctypes.c_double), ("node_order", ctypes.c_int32),
+                ("audit", ctypes.c_int32)]
 
 
 class BnbResult(ctypes.Structure):
@@ -75,7 +76,7 @@ class BnbResult(ctypes.Structure):
                 ("status", ctypes.c_int32), ("support_len", ctypes.c_int32),
                 ("support", ctypes.c_void_p), ("beta", ctypes.c_void_p),
                 ("incumbent_updates", ctypes.c_int64), ("seconds", ctypes.c_double),
-                ("rashomon_size", ctypes.c_int64)]
+                ("rashomon_size", ctypes.c_int64), ("audit_leaves", ctypes.c_int64)]
 
 
 class TuneOptions(ctypes.Structure):
@@ -96,7 +97,8 @@ EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
            "branch_and_bound", "rashomon_entry", "autotune", "last_error", "prox_batch",
            "certify_batch", "problem_info", "kernel_stats", "pool_create", "pool_destroy",
            "pool_add", "pool_info", "pool_export", "pool_record", "rashomon_pool",
-           "rashomon_reliance", "pool_summary", "evaluate_supports"]
+           "rashomon_reliance", "pool_summary", "evaluate_supports", "cancel_nodes",
+           "bnb_audit_leaf"]
 
 _lib = None
 
@@ -139,6 +141,8 @@ def load():
         lib.rashomon_reliance.argtypes = [vp, vp, vp]
         lib.pool_summary.argtypes = [vp, i32, vp, vp]
         lib.evaluate_supports.argtypes = [vp, i32, vp, dbl, i32, vp, vp, vp, vp, vp]
+        lib.cancel_nodes.argtypes = [vp]
+        lib.bnb_audit_leaf.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
         for name in EXPORTS:
             if name != "last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -189,6 +193,9 @@ def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hb
         yc = y.contiguous().double()
         keep.append(yc)
         yptr = ctypes.c_void_p(yc.data_ptr())
+        # the library waits for the work queued on the producing stream
+        import torch
+        stream = ctypes.c_void_p(torch.cuda.current_stream(X.device).cuda_stream)
     else:
         want = {DTYPE_F64: np.float64, DTYPE_F32: np.float32, DTYPE_BF16: np.uint16}[xd]
         Xa = np.ascontiguousarray(X, dtype=want)
@@ -196,8 +203,9 @@ def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hb
         ya = np.ascontiguousarray(y, dtype=np.float64)
         keep += [Xa, ya]
         xptr, ldx, mem, yptr = _p(Xa), p, MEM_HOST_COPY, _p(ya)
+        stream = None
     d = ProblemDesc(n=n, p=p, k=int(k), loss=int(loss), lambda2=float(lambda2), M=float(M),
-                    x_dtype=xd, mem_flags=mem, X=xptr, ldx=ldx, y=yptr, hip_stream=None,
+                    x_dtype=xd, mem_flags=mem, X=xptr, ldx=ldx, y=yptr, hip_stream=stream,
                     hbm_budget_bytes=int(hbm_budget_bytes), batch_width=int(batch_width),
                     cert_period=int(cert_period),
                     iter_dtype=_ITERS[iter_dtype] if iter_dtype in _ITERS else int(iter_dtype))
@@ -336,6 +344,11 @@ def poll_bounds(h: Handle, cap=1024, timeout_us=-1, supports=True, betas=True):
     return res, rc
 
 
+def cancel_nodes(h: Handle):
+    """Drop every queued, running or unpolled node of h; returns when h is idle."""
+    _check(load().cancel_nodes(h.ptr))
+
+
 def bound_nodes(h: Handle, nodes, **kw):
     """Submit `nodes` and wait for all of them; results ordered like `nodes`."""
     submit_nodes(h, nodes, tags=list(range(len(nodes))), **kw)
@@ -351,11 +364,12 @@ def bound_nodes(h: Handle, nodes, **kw):
 
 def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=0.0,
                      max_fista_iters=0, max_nodes=0, log_every_s=0.0, rashomon_eps=None,
-                     rashomon_n=0, node_order=0):
+                     rashomon_n=0, node_order=0, audit=False):
     """rashomon_eps (>= 0): also collect the support-level Rashomon set (the
     best rashomon_n when nonzero), returned as "rashomon": a list of
     (support tuple, value, beta) ordered by value.  node_order: 0 best bound,
-    1 depth first."""
+    1 depth first.  audit: also return "leaves", the discarded subtrees with the
+    certificates of their bounds (see bnb_audit_leaf)."""
     sup = np.full(h.k, -1, np.int32)
     beta = np.zeros(h.p)
     o = BnbOptions(time_limit_s=time_limit_s, rel_gap_tol=rel_gap_tol,
@@ -363,7 +377,7 @@ def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=
                    max_nodes=max_nodes, log_every_s=log_every_s,
                    rashomon=0 if rashomon_eps is None else 1, rashomon_n=int(rashomon_n),
                    rashomon_eps=0.0 if rashomon_eps is None else float(rashomon_eps),
-                   node_order=int(node_order))
+                   node_order=int(node_order), audit=1 if audit else 0)
     r = BnbResult(support=_p(sup), beta=_p(beta))
     _check(load().branch_and_bound(h.ptr, ctypes.byref(o), ctypes.byref(r)))
     out = dict(objective=r.objective, lower_bound=r.lower_bound, rel_gap=r.rel_gap,
@@ -371,7 +385,24 @@ def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=
                beta=beta, incumbent_updates=r.incumbent_updates, seconds=r.seconds)
     if rashomon_eps is not None:
         out["rashomon"] = [rashomon_entry(h, i) for i in range(r.rashomon_size)]
+    if audit:
+        out["leaves"] = [bnb_audit_leaf(h, i) for i in range(r.audit_leaves)]
     return out
+
+
+def bnb_audit_leaf(h: Handle, i):
+    """Leaf i of the last audited search: dict(kind, bound, state, cert_state,
+    cert_beta, cert_bound)."""
+    kind = ctypes.c_int32(0)
+    bound = ctypes.c_double(0.0)
+    cb = ctypes.c_double(0.0)
+    st = np.zeros(h.p, np.int8)
+    cst = np.zeros(h.p, np.int8)
+    beta = np.zeros(h.p)
+    _check(load().bnb_audit_leaf(h.ptr, ctypes.c_int64(int(i)), ctypes.byref(kind),
+                                 ctypes.byref(bound), _p(st), _p(cst), _p(beta), ctypes.byref(cb)))
+    return dict(kind=kind.value, bound=bound.value, state=st, cert_state=cst, cert_beta=beta,
+                cert_bound=cb.value)
 
 
 def rashomon_entry(h: Handle, i):

@@ -46,6 +46,17 @@
 
 namespace {
 
+// Certificate of a bound (audit mode): the node (J1 = in, J0 = out) whose
+// dual function was evaluated, and the iterate beta whose dual point
+// zeta = -l'(X beta) gave the value `bound`.  A node's bound may be its own
+// certificate or one inherited from an ancestor (whose node contains it).
+struct Cert {
+    std::vector<int32_t> in, out;
+    std::vector<double> beta;
+    double bound;
+};
+typedef std::shared_ptr<const Cert> CertPtr;
+
 struct Open {
     double lb;
     int depth;
@@ -53,6 +64,7 @@ struct Open {
     std::vector<int32_t> in, out;
     std::vector<int32_t> wi;  // warm start, sparse
     std::vector<double> wv;
+    CertPtr cert;             // audit mode: the certificate of lb (null at the root)
 };
 
 // Queue order: best bound (smaller bound, then deeper, then first in), or
@@ -83,8 +95,31 @@ struct Candidate {
 
 }  // namespace
 
+namespace kbnb {
+// Leaves of the last audited search per problem (audit mode).  A leaf is a
+// subtree the search discarded, with the bound it used for it and that
+// bound's certificate.
+struct AuditLeaf {
+    int32_t kind;  // 0 pruned, 1 closed, 2 Rashomon leaf (its support's bound), 3 left unexplored
+    std::vector<int32_t> in, out;
+    double bound;
+    CertPtr cert;
+};
+static std::mutex g_audit_mu;
+static std::map<const kbnb_problem *, std::shared_ptr<std::vector<AuditLeaf>>> g_audit;
+void drop_audit(const kbnb_problem *P)
+{
+    std::lock_guard<std::mutex> g(g_audit_mu);
+    g_audit.erase(P);
+}
+}  // namespace kbnb
+
 extern "C" int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
 namespace kbnb {
+bool outstanding(kbnb_problem *P);
+int poll_with_lb_beta(kbnb_problem *P, kbnb_bound_result *out, int cap, int *n_out, int32_t *supports,
+                      double *betas, double *betas_lb, int timeout_us);
+void keep_lb_beta(kbnb_problem *P, bool on);
 int set_error(int code, const char *fmt, ...);
 // the collected set's storage (kbnb_pool.cpp)
 kbnb_pool *pool_new();
@@ -94,7 +129,7 @@ void store_rashomon(const kbnb_problem *P, kbnb_pool *pl);
 int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off, int count, int maxlen,
                          const double *warm, double tol, int max_iter);
 int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double *coefs, int32_t *status,
-                          int32_t *iters);
+                          int32_t *iters, double *coefs_lb);
 }  // namespace kbnb
 
 extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kbnb_bnb_result *res)
@@ -110,6 +145,10 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     double dinfo[4];
     int rc = problem_info(P, info, dinfo);
     if (rc) return rc;
+    // every result the loop polls must be one of its own nodes
+    if (kbnb::outstanding(P))
+        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT,
+                               "the problem has nodes queued, running or unpolled; poll or cancel them first");
     const int p = (int)info[1], k = (int)info[2], m = (int)info[3];
     const double gap_tol = opt->rel_gap_tol > 0 ? opt->rel_gap_tol : 1e-6;
     const double node_tol = opt->node_rel_tol > 0 ? opt->node_rel_tol : 1e-6;
@@ -124,6 +163,21 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     if (opt->node_order != 0 && opt->node_order != 1)
         return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "node_order must be 0 or 1");
     const bool dfs = opt->node_order == 1;
+    const bool audit = opt->audit != 0;
+    auto leaves = std::make_shared<std::vector<kbnb::AuditLeaf>>();
+    std::map<std::vector<int32_t>, CertPtr> support_cert;  // audit: certificate of each support's bound
+    auto complement = [&](const std::vector<int32_t> &S) {
+        std::vector<char> ins((size_t)p, 0);
+        for (int32_t j : S) ins[(size_t)j] = 1;
+        std::vector<int32_t> c;
+        for (int j = 0; j < p; ++j)
+            if (!ins[(size_t)j]) c.push_back(j);
+        return c;
+    };
+    auto add_leaf = [&](int kind, const std::vector<int32_t> &in, const std::vector<int32_t> &out, double bound,
+                        const CertPtr &cert) {
+        if (audit) leaves->push_back(kbnb::AuditLeaf{kind, in, out, bound, cert});
+    };
     std::priority_queue<Open *, std::vector<Open *>, OpenCmp> open(OpenCmp{dfs});
     std::multiset<double> open_lbs;  // bounds of the open nodes (the least is the queue's)
     auto push_open = [&](Open *o) {
@@ -145,7 +199,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     // bound; leaves whose support is still being evaluated wait for it
     // (with their parent's bound, which holds meanwhile)
     std::map<std::vector<int32_t>, double> support_lb;
-    std::map<std::vector<int32_t>, double> leaf_waiting;
+    std::map<std::vector<int32_t>, std::pair<double, CertPtr>> leaf_waiting;
     uint64_t seq = 0, next_tag = 1;
     double UB = INFINITY;
     std::vector<int32_t> best_support;
@@ -171,11 +225,19 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     };
     double leaf_lb = INFINITY;  // least bound of the discarded subtrees
     // evaluated support S: value v (attained at beta) and certified bound lb
-    auto take_support = [&](const std::vector<int32_t> &S, double v, double lb, const double *beta) {
+    // beta_lb (audit mode, nullable): the coefficients whose dual point gave lb
+    auto take_support = [&](const std::vector<int32_t> &S, double v, double lb, const double *beta,
+                            const double *beta_lb) {
         support_lb[S] = lb;
+        CertPtr sc;
+        if (audit && beta_lb) {
+            sc = std::make_shared<const Cert>(Cert{S, complement(S), std::vector<double>(beta_lb, beta_lb + p), lb});
+            support_cert[S] = sc;
+        }
         auto w = leaf_waiting.find(S);
         if (w != leaf_waiting.end()) {
             leaf_lb = std::min(leaf_lb, lb);
+            add_leaf(2, S, complement(S), lb, sc);
             leaf_waiting.erase(w);
         }
         if (std::isfinite(v) && v < UB) {
@@ -203,6 +265,13 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     std::vector<kbnb_bound_result> out(m);
     std::vector<int32_t> sup((size_t)m * k);
     std::vector<double> betas((size_t)m * p);
+    std::vector<double> betas_lb(audit ? (size_t)m * p : 0);
+    if (audit) kbnb::keep_lb_beta(P, true);
+    auto poll = [&](int32_t *got, int timeout_us) {
+        return audit ? kbnb::poll_with_lb_beta(P, out.data(), m, got, sup.data(), betas.data(), betas_lb.data(),
+                                               timeout_us)
+                     : poll_bounds(P, out.data(), m, got, sup.data(), betas.data(), timeout_us);
+    };
     double global_lb = -INFINITY;
     double last_log = 0.0;
     double t_poll = 0, t_flush = 0, t_fill = 0, t_res = 0;  // host time split (progress lines)
@@ -225,9 +294,11 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         if (inflight.empty()) return 0;
         const size_t cnt = inflight.size();
         std::vector<double> val(cnt), low(cnt), coef(std::max<size_t>(in_lab.size(), 1));
-        int erc = kbnb::eval_supports_collect(P, val.data(), low.data(), coef.data(), nullptr, nullptr);
+        std::vector<double> coef_lb(audit ? coef.size() : 0);
+        int erc = kbnb::eval_supports_collect(P, val.data(), low.data(), coef.data(), nullptr, nullptr,
+                                              audit ? coef_lb.data() : nullptr);
         if (erc) return erc;
-        std::vector<double> dense;
+        std::vector<double> dense, dense_lb;
         for (size_t i = 0; i < cnt; ++i) {
             const std::vector<int32_t> &S = inflight[i];
             const double v = val[i];
@@ -237,7 +308,11 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 dense.assign(p, 0.0);
                 for (size_t r = 0; r < S.size(); ++r) dense[(size_t)S[r]] = coef[(size_t)in_off[i] + r];
             }
-            take_support(S, v, low[i], keep ? dense.data() : nullptr);
+            if (audit) {
+                dense_lb.assign(p, 0.0);
+                for (size_t r = 0; r < S.size(); ++r) dense_lb[(size_t)S[r]] = coef_lb[(size_t)in_off[i] + r];
+            }
+            take_support(S, v, low[i], keep ? dense.data() : nullptr, audit ? dense_lb.data() : nullptr);
         }
         inflight.clear();
         return 0;
@@ -315,7 +390,11 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         // bound is prunable, every open node is
         if (!open_lbs.empty() && prunable(*open_lbs.begin())) {
             leaf_lb = std::min(leaf_lb, *open_lbs.begin());
-            while (!open.empty()) delete pop_open();
+            while (!open.empty()) {
+                Open *o = pop_open();
+                add_leaf(0, o->in, o->out, o->lb, o->cert);
+                delete o;
+            }
         }
         double lb_open = open_lbs.empty() ? INFINITY : *open_lbs.begin();
         double lb_fl = flight_lb.empty() ? INFINITY : *flight_lb.begin();
@@ -357,6 +436,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             Open *o = pop_open();
             if (prunable(o->lb)) {  // depth first: pruned at the pop
                 leaf_lb = std::min(leaf_lb, o->lb);
+                add_leaf(0, o->in, o->out, o->lb, o->cert);
                 delete o;
                 continue;
             }
@@ -365,10 +445,15 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 auto known = support_lb.find(o->in);
                 if (known != support_lb.end()) {
                     leaf_lb = std::min(leaf_lb, known->second);
+                    if (audit) {
+                        auto sc = support_cert.find(o->in);
+                        add_leaf(2, o->in, complement(o->in), known->second,
+                                 sc == support_cert.end() ? nullptr : sc->second);
+                    }
                 } else {
                     auto w = leaf_waiting.find(o->in);
-                    if (w == leaf_waiting.end()) leaf_waiting[o->in] = o->lb;
-                    else w->second = std::min(w->second, o->lb);
+                    if (w == leaf_waiting.end()) leaf_waiting[o->in] = {o->lb, o->cert};
+                    else if (o->lb < w->second.first) w->second = {o->lb, o->cert};
                     if (!evaluated.count(o->in)) {
                         support_desc(o->in, batch);
                         --room;
@@ -431,7 +516,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         // collect results
         tm = elapsed();
         int32_t got = 0;
-        rc = poll_bounds(P, out.data(), m, &got, sup.data(), betas.data(), 200000);
+        rc = poll(&got, 200000);
         t_poll += elapsed() - tm;
         if (rc < 0) break;
         rc = 0;
@@ -445,16 +530,31 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             Flight f = std::move(it->second);
             flight.erase(it);
             const double *beta = betas.data() + (size_t)r * p;
+            const double *beta_lb = audit ? betas_lb.data() + (size_t)r * p : nullptr;
             if (f.kind == FL_SUPPORT) {
-                take_support(f.support, br.primal_value, br.lower_bound, beta);
+                take_support(f.support, br.primal_value, br.lower_bound, beta, beta_lb);
                 continue;
             }
             Open *o = f.node;
             flight_lb.erase(flight_lb.find(o->lb));
             ++nodes;
+            if (br.status == KBNB_ERROR) {
+                // a non-finite iterate: neither closing nor pruning the node
+                // would be justified by its bound
+                global_lb = std::min(global_lb, o->lb);
+                delete o;
+                rc = kbnb::set_error(KBNB_E_DEVICE, "node %llu: non-finite iterate (status ERROR)",
+                                     (unsigned long long)br.tag);
+                break;
+            }
             const double lb = std::max(br.lower_bound, o->lb);
+            CertPtr cert = o->cert;
+            if (audit && br.lower_bound >= o->lb)
+                cert = std::make_shared<const Cert>(
+                    Cert{o->in, o->out, std::vector<double>(beta_lb, beta_lb + p), br.lower_bound});
             if (prunable(lb)) {
                 leaf_lb = std::min(leaf_lb, lb);
+                add_leaf(0, o->in, o->out, lb, cert);
                 delete o;
                 continue;
             }
@@ -468,6 +568,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             // bound (a node stopped early as unprunable is branched instead)
             if (!rs && (kbar <= 0 || pf <= kbar || (j < 0 && br.status != KBNB_UNPRUNABLE))) {
                 leaf_lb = std::min(leaf_lb, lb);
+                add_leaf(1, o->in, o->out, lb, cert);
                 delete o;
                 continue;
             }
@@ -488,6 +589,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             for (int side = 0; side < 2; ++side) {
                 Open *c = new Open();
                 c->lb = lb;
+                c->cert = cert;
                 c->depth = o->depth + 1;
                 c->seq = seq++;
                 c->in = o->in;
@@ -504,6 +606,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             delete o;
         }
         t_res += elapsed() - tm;
+        if (rc) break;
         tm = elapsed();
         rc = cycle_supports();
         t_flush += elapsed() - tm;
@@ -516,46 +619,75 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     }
     if (!rc) rc = flush_supports();
     else if (!inflight.empty()) (void)collect_supports();  // leave no batch on the device
-    // drain in-flight work so the handle is reusable
+    // Nodes still in flight: take what has already completed, then cancel
+    // the rest (the engine drops their results), so the handle is idle and
+    // reusable.  An unexplored node's parent bound holds for its subtree.
     while (!flight.empty()) {
         int32_t got = 0;
-        int prc = poll_bounds(P, out.data(), m, &got, sup.data(), betas.data(), 200000);
+        int prc = poll(&got, 0);
         if (prc < 0) {
             if (!rc) rc = prc;
             break;
         }
+        if (got == 0) break;
         for (int r = 0; r < got; ++r) {
             auto it = flight.find(out[r].tag);
             if (it == flight.end()) continue;
             if (it->second.kind == FL_SUPPORT) {
-                if (!rc)
+                if (!rc && out[r].status != KBNB_ERROR)
                     take_support(it->second.support, out[r].primal_value, out[r].lower_bound,
-                                 betas.data() + (size_t)r * p);
+                                 betas.data() + (size_t)r * p, audit ? betas_lb.data() + (size_t)r * p : nullptr);
             } else {
-                // unexplored: its parent's bound still holds for its subtree
-                global_lb = std::min(global_lb, it->second.node->lb);
-                delete it->second.node;
+                // bounded but not expanded: its parent's bound (certified by
+                // the parent's certificate) holds for its subtree
+                Open *o = it->second.node;
+                global_lb = std::min(global_lb, o->lb);
+                add_leaf(3, o->in, o->out, o->lb, o->cert);
+                delete o;
             }
             flight.erase(it);
         }
-        if (got == 0 && prc == KBNB_TIMEOUT) break;  // nothing is progressing
+    }
+    for (auto &f : flight)
+        if (f.second.kind == FL_NODE) {
+            global_lb = std::min(global_lb, f.second.node->lb);
+            add_leaf(3, f.second.node->in, f.second.node->out, f.second.node->lb, f.second.node->cert);
+            delete f.second.node;
+        }
+    if (!flight.empty()) {
+        flight.clear();
+        const int crc = cancel_nodes(P);
+        if (!rc) rc = crc;
     }
     while (!open.empty()) {
         Open *o = pop_open();
         global_lb = std::min(global_lb, o->lb);
+        add_leaf(3, o->in, o->out, o->lb, o->cert);
         delete o;
     }
-    for (auto &w : leaf_waiting) global_lb = std::min(global_lb, w.second);
+    for (auto &w : leaf_waiting) {
+        global_lb = std::min(global_lb, w.second.first);
+        add_leaf(2, w.first, complement(w.first), w.second.first, w.second.second);
+    }
+    if (audit) {
+        kbnb::keep_lb_beta(P, false);
+        std::lock_guard<std::mutex> g(kbnb::g_audit_mu);
+        kbnb::g_audit[P] = leaves;
+    }
     if (rc) return rc;
     res->objective = UB;
     res->lower_bound = std::min(std::min(global_lb, leaf_lb), UB);
     res->rel_gap = std::isfinite(UB) ? (UB - res->lower_bound) / std::max(std::fabs(UB), 1e-12) : INFINITY;
     res->nodes = nodes;
+    // a tree exhausted with a gap above the tolerance (nodes that hit their
+    // iteration cap keep loose bounds) is not reported optimal
+    if (status == 0 && !(res->rel_gap <= gap_tol)) status = 3;
     res->status = status;
     res->support_len = (int32_t)best_support.size();
     for (int r = 0; r < k; ++r) res->support[r] = r < (int)best_support.size() ? best_support[r] : -1;
     if (res->beta) memcpy(res->beta, best_beta.data(), sizeof(double) * p);
     res->incumbent_updates = updates;
+    res->audit_leaves = audit ? (int64_t)leaves->size() : 0;
     res->rashomon_size = 0;
     if (rs) {
         // the set: recorded supports within the final threshold, by value,
@@ -580,5 +712,43 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         kbnb::store_rashomon(P, pool);
     }
     res->seconds = elapsed();
+    return KBNB_OK;
+}
+
+extern "C" int bnb_audit_leaf(kbnb_problem *P, int64_t i, int32_t *kind, double *bound, int8_t *leaf_state,
+                              int8_t *cert_state, double *cert_beta, double *cert_bound)
+{
+    if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");
+    int64_t info[9];
+    int rc = problem_info(P, info, nullptr);
+    if (rc) return rc;
+    const int p = (int)info[1];
+    std::shared_ptr<std::vector<kbnb::AuditLeaf>> lv;
+    {
+        std::lock_guard<std::mutex> g(kbnb::g_audit_mu);
+        auto it = kbnb::g_audit.find(P);
+        if (it != kbnb::g_audit.end()) lv = it->second;
+    }
+    if (!lv) return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "no audited search on this problem");
+    if (i < 0 || i >= (int64_t)lv->size())
+        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "leaf %lld outside [0, %zu)", (long long)i, lv->size());
+    const kbnb::AuditLeaf &L = (*lv)[(size_t)i];
+    auto fill = [p](int8_t *st, const std::vector<int32_t> &in, const std::vector<int32_t> &out) {
+        for (int j = 0; j < p; ++j) st[j] = 0;
+        for (int32_t j : in) st[j] = 1;
+        for (int32_t j : out) st[j] = -1;
+    };
+    if (kind) *kind = L.kind;
+    if (bound) *bound = L.bound;
+    if (leaf_state) fill(leaf_state, L.in, L.out);
+    if (L.cert) {
+        if (cert_state) fill(cert_state, L.cert->in, L.cert->out);
+        if (cert_beta) memcpy(cert_beta, L.cert->beta.data(), sizeof(double) * (size_t)p);
+        if (cert_bound) *cert_bound = L.cert->bound;
+    } else {
+        if (cert_state) memset(cert_state, 0, (size_t)p);
+        if (cert_beta) memset(cert_beta, 0, sizeof(double) * (size_t)p);
+        if (cert_bound) *cert_bound = -INFINITY;
+    }
     return KBNB_OK;
 }

@@ -94,6 +94,7 @@ struct DoneNode {
     kbnb_bound_result r;
     std::vector<int32_t> sup;
     std::vector<double> beta;
+    std::vector<double> beta_lb;  // filled when the problem keeps them (audits)
 };
 
 // One launch configuration of a round: the launches cover the first `mact`
@@ -133,6 +134,9 @@ struct kbnb_problem {
     void *X = nullptr, *XT = nullptr, *Yi = nullptr, *R = nullptr, *Gp = nullptr;
     double *y = nullptr, *B = nullptr, *Bprev = nullptr, *Z = nullptr, *Qp = nullptr;
     double *lsum = nullptr, *csum = nullptr, *gbuf = nullptr;
+    double *gbuf_lb = nullptr;  // gathered Blb columns (only when results carry them)
+    double *h_gbuf_lb = nullptr;
+    bool want_lb_beta = false;  // results also carry the iterate of the certified bound
     double *Bbest = nullptr;   // iterate of the best certified primal value [mpad][ldp]
     bool anchored = false;     // anchored float32 iteration
     Anchor an{};               // its buffers (all NULL when off)
@@ -157,7 +161,7 @@ struct kbnb_problem {
     hipEvent_t sev = nullptr;       // end of the support batch in flight
     int s_count = 0;                // that batch: supports and stored coefficients
     int64_t s_coefs = 0;
-    double *s_val = nullptr, *s_low = nullptr, *s_coef = nullptr;
+    double *s_val = nullptr, *s_low = nullptr, *s_coef = nullptr, *s_coef_lb = nullptr;
     int32_t *s_st = nullptr, *s_it = nullptr;
     hipStream_t gstream = nullptr;  // gathers beside a round enqueued ahead (created on first use:
                                     // streams share the process's few hardware queues)
@@ -178,6 +182,8 @@ struct kbnb_problem {
     std::vector<uint64_t> slot_tag;
     std::set<int> free_slots;        // lowest index first, so running slots stay packed
     std::vector<char> occupied;      // slot holds an admitted, unretired node
+    std::vector<char> cancelled;     // slot's node was cancelled: its result is dropped
+    bool cancel_dev = false;         // cancelled slots still to be stopped on the device
     std::vector<Variant> var;        // launch widths 64, 128, ..., mpad
     int active = 0;
     bool shutdown = false;
@@ -215,12 +221,12 @@ static size_t per_slot_bytes(const kbnb_problem *P)
 {
     const size_t ti = P->ti_bytes;
     size_t b = 0;
-    b += (size_t)P->ldp * (ti + 8 + 8 + 8 + 1);        // Yi, B, Bprev, Bbest, st
+    b += (size_t)P->ldp * (ti + 8 + 8 + 8 + 8 + 1);    // Yi, B, Bprev, Bbest, Blb, st
     b += (size_t)P->npad * (ti + 8);                   // R, Z
     b += (size_t)P->gsplit_alloc * P->ldp * ti;        // Gp
     b += (size_t)P->qsplit_alloc * P->ldp * 8;         // Qp
     b += (size_t)P->tiles_n * 16;                      // lsum, csum
-    b += (size_t)P->ldp * 8 + 128 + P->k * 4;          // gather buffer, scalars, support
+    b += (size_t)P->ldp * 16 + 128 + P->k * 4;         // gather buffers, scalars, support
     b += (size_t)P->pp * 4;                            // sort permutation
     if (P->anchored) b += (size_t)P->npad * 8 + (size_t)P->ldp * 16;  // S_c, beta_c, grad F(beta_c)
     return b;
@@ -293,6 +299,8 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         P->anchored ? mp * P->ldp * 8 : 0,       // anchor beta_c
         P->anchored ? mp * P->ldp * 8 : 0,       // anchor grad F(beta_c)
         P->anchored ? (size_t)P->ldp * 8 : 0,    // grad F(0)
+        mp * P->ldp * 8,                         // Blb
+        mp * P->ldp * 8,                         // second gather buffer (Blb columns)
     };
     const int nitems = sizeof(sizes) / sizeof(sizes[0]);
     size_t off[32];
@@ -357,6 +365,8 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         P->an.gc = (double *)(base + off[23]);
         P->an.g0 = (const double *)(base + off[24]);
     }
+    P->ss.blb = (double *)(base + off[25]);
+    P->gbuf_lb = (double *)(base + off[26]);
     P->slot_dev = base + off[16];
     P->slot_bytes = off[18] + sizes[18] - off[16];
     return 0;
@@ -464,6 +474,17 @@ __global__ void k_gather_cols(const double *__restrict__ B, int ldp, int p,
     for (int j = threadIdx.x; j < p; j += blockDim.x) out[(int64_t)r * p + j] = B[src + j];
 }
 
+// Stops cancelled slots: a running slot in the mask gets a final status
+// (iteration cap), so the next rounds skip it and the host retires it.
+struct SlotMask {
+    uint32_t w[4096 / 32];
+};
+__global__ void k_cancel_slots(int32_t *__restrict__ status, int m, SlotMask mask)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < m && ((mask.w[b >> 5] >> (b & 31)) & 1u) && status[b] == SLOT_RUNNING) status[b] = KBNB_MAXITER;
+}
+
 // ---------------------------------------------------------------------------
 // engine worker
 // ---------------------------------------------------------------------------
@@ -485,6 +506,19 @@ static int enqueue_round_async(kbnb_problem *P, std::unique_lock<std::mutex> &lk
     enq = false;
     const int64_t rid = P->next_round;
     int nadm = 0;
+    // slots cancelled since the last round: stopped on the device before
+    // this round's admissions (a cancelled slot stays occupied until retired,
+    // so no admission can target it)
+    bool stop_cancelled = false;
+    SlotMask cmask{};
+    if (P->cancel_dev) {
+        P->cancel_dev = false;
+        for (int b = 0; b < P->m; ++b)
+            if (P->occupied[b] && P->cancelled[b]) {
+                cmask.w[b >> 5] |= 1u << (b & 31);
+                stop_cancelled = true;
+            }
+    }
     uint8_t *stage = P->stage_h + (size_t)buf * P->mpad * P->rec_bytes;
     while (!P->pending.empty() && !P->free_slots.empty()) {
         PendingNode nd = std::move(P->pending.front());
@@ -535,6 +569,10 @@ static int enqueue_round_async(kbnb_problem *P, std::unique_lock<std::mutex> &lk
     int rc = 0;
     P->round_kinds[buf].clear();
     do {
+        if (stop_cancelled) {
+            hipLaunchKernelGGL(k_cancel_slots, dim3((P->m + 255) / 256), dim3(256), 0, s, P->ss.status, P->m, cmask);
+            HIP_BREAK(hipGetLastError());
+        }
         if (nadm) {
             HIP_BREAK(hipMemcpyAsync(P->stage_d, stage, (size_t)nadm * P->rec_bytes, hipMemcpyHostToDevice, s));
             launch_admit(s, P->iter_f64, P->stage_d, nadm, P->rec_bytes, P->B, P->Bprev, P->Bbest, P->Yi,
@@ -573,6 +611,7 @@ static int process_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk, int 
     lk.unlock();
     const HostSlots &h = P->hs[buf];
     const int64_t rid = P->round_id[buf];
+    const bool want_lb = P->want_lb_beta;
     int rc = 0, nfin = 0;
     do {
         HIP_BREAK(hipEventSynchronize(P->ev_round[buf]));
@@ -596,6 +635,11 @@ static int process_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk, int 
             HIP_BREAK(hipMemcpyAsync(P->gslots_d, P->h_gslots, (size_t)nfin * 4, hipMemcpyHostToDevice, g));
             hipLaunchKernelGGL(k_gather_cols, dim3(nfin), dim3(256), 0, g, P->Bbest, P->ldp, P->p, P->gslots_d, P->gbuf);
             HIP_BREAK(hipMemcpyAsync(P->h_gbuf, P->gbuf, (size_t)nfin * P->p * 8, hipMemcpyDeviceToHost, g));
+            if (want_lb) {
+                hipLaunchKernelGGL(k_gather_cols, dim3(nfin), dim3(256), 0, g, P->ss.blb, P->ldp, P->p, P->gslots_d,
+                                   P->gbuf_lb);
+                HIP_BREAK(hipMemcpyAsync(P->h_gbuf_lb, P->gbuf_lb, (size_t)nfin * P->p * 8, hipMemcpyDeviceToHost, g));
+            }
             HIP_BREAK(hipStreamSynchronize(g));
         }
     } while (0);
@@ -603,6 +647,13 @@ static int process_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk, int 
     if (rc) return rc;
     for (int r = 0; r < nfin; ++r) {
         const int b = P->h_gslots[r];
+        if (P->cancelled[b]) {  // a cancelled node: its result is never returned
+            P->cancelled[b] = 0;
+            P->free_slots.insert(b);
+            P->occupied[b] = 0;
+            --P->active;
+            continue;
+        }
         DoneNode d;
         d.r.tag = P->slot_tag[b];
         d.r.lower_bound = h.lb[b];
@@ -614,6 +665,7 @@ static int process_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk, int 
         d.r.support_len = h.slen[b];
         d.sup.assign(h.sup + (size_t)b * P->k, h.sup + (size_t)(b + 1) * P->k);
         d.beta.assign(P->h_gbuf + (size_t)r * P->p, P->h_gbuf + (size_t)(r + 1) * P->p);
+        if (want_lb) d.beta_lb.assign(P->h_gbuf_lb + (size_t)r * P->p, P->h_gbuf_lb + (size_t)(r + 1) * P->p);
         P->done.push_back(std::move(d));
         // the slot's device status stays >= 0 (not running) until a node is
         // admitted into it again
@@ -797,7 +849,7 @@ static void free_problem(kbnb_problem *P)
     for (hipEvent_t e : P->ev_round)
         if (e) (void)hipEventDestroy(e);
     if (P->arena) (void)hipFree(P->arena);
-    void *pins[] = {P->stage_h, P->slot_host, P->h_gslots, P->h_gbuf};
+    void *pins[] = {P->stage_h, P->slot_host, P->h_gslots, P->h_gbuf, P->h_gbuf_lb};
     for (void *q : pins)
         if (q) (void)hipHostFree(q);
     if (P->sstream) (void)hipStreamSynchronize(P->sstream);
@@ -834,6 +886,12 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
         return fail(KBNB_E_INVALID_ARGUMENT, "a float32 iteration needs float32 or bfloat16 X");
     int rc = device_ok();
     if (rc) return rc;
+    // device inputs were produced on the caller's stream: wait for that work
+    // before any copy or kernel of this library reads them
+    if (d->mem_flags != KBNB_MEM_HOST_COPY && d->hip_stream) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)d->hip_stream);
+        if (e != hipSuccess) return fail(KBNB_E_DEVICE, "synchronising the caller's stream failed: %s", hipGetErrorString(e));
+    }
     if (d->mem_flags == KBNB_MEM_HOST_COPY) {
         for (int i = 0; i < d->n; ++i) {
             const double yi = d->y[i];
@@ -893,6 +951,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->slot_n0.assign(P->m, 0);
     for (int b = 0; b < P->m; ++b) P->free_slots.insert(b);
     P->occupied.assign(P->m, 0);
+    P->cancelled.assign(P->m, 0);
     P->slot_round.assign(P->m, 0);
 
     rc = alloc_arena(P, xbytes, xel);
@@ -924,7 +983,8 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
         bool okp = hipHostMalloc((void **)&P->stage_h, 2 * mb * P->rec_bytes, 0) == hipSuccess &&
                    hipHostMalloc((void **)&P->slot_host, 2 * P->slot_bytes, 0) == hipSuccess &&
                    hipHostMalloc((void **)&P->h_gslots, mb * 4, 0) == hipSuccess &&
-                   hipHostMalloc((void **)&P->h_gbuf, mb * P->p * 8, 0) == hipSuccess;
+                   hipHostMalloc((void **)&P->h_gbuf, mb * P->p * 8, 0) == hipSuccess &&
+                   hipHostMalloc((void **)&P->h_gbuf_lb, mb * P->p * 8, 0) == hipSuccess;
         if (okp) {
             for (int q = 0; q < 2; ++q) {
                 char *hb = P->slot_host + (size_t)q * P->slot_bytes;
@@ -970,12 +1030,14 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
 
 namespace kbnb {
 void drop_rashomon(const kbnb_problem *P);
+void drop_audit(const kbnb_problem *P);
 }
 
 extern "C" int destroy_problem(kbnb_problem *P)
 {
     if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
     kbnb::drop_rashomon(P);
+    kbnb::drop_audit(P);
     free_problem(P);
     return KBNB_OK;
 }
@@ -1048,7 +1110,7 @@ extern "C" int submit_nodes(kbnb_problem *P, const kbnb_node_desc *nodes, int32_
 }
 
 static int poll_impl(kbnb_problem *P, kbnb_bound_result *out, int cap, int *n_out, int32_t *supports,
-                     double *betas, int timeout_us)
+                     double *betas, int timeout_us, double *betas_lb = nullptr)
 {
     std::unique_lock<std::mutex> lk(P->mu);
     auto ready = [&] {
@@ -1064,6 +1126,10 @@ static int poll_impl(kbnb_problem *P, kbnb_bound_result *out, int cap, int *n_ou
         if (supports)
             for (int r = 0; r < P->k; ++r) supports[(size_t)cnt * P->k + r] = d.sup[r];
         if (betas) memcpy(betas + (size_t)cnt * P->p, d.beta.data(), sizeof(double) * P->p);
+        if (betas_lb) {
+            if (d.beta_lb.size() == (size_t)P->p) memcpy(betas_lb + (size_t)cnt * P->p, d.beta_lb.data(), sizeof(double) * P->p);
+            else for (int j = 0; j < P->p; ++j) betas_lb[(size_t)cnt * P->p + j] = NAN;
+        }
         P->done.pop_front();
         ++cnt;
     }
@@ -1071,6 +1137,53 @@ static int poll_impl(kbnb_problem *P, kbnb_bound_result *out, int cap, int *n_ou
     if (cnt == 0 && P->engine_error) return fail(P->engine_error, "engine stopped: %s", P->engine_msg.c_str());
     return cnt ? KBNB_OK : KBNB_TIMEOUT;
 }
+
+extern "C" int cancel_nodes(kbnb_problem *P)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    std::unique_lock<std::mutex> lk(P->mu);
+    P->pending.clear();
+    P->done.clear();
+    bool any = false;
+    for (int b = 0; b < P->m; ++b)
+        if (P->occupied[b]) {
+            P->cancelled[b] = 1;
+            any = true;
+        }
+    if (any) P->cancel_dev = true;
+    P->cv_work.notify_all();
+    // the cancelled slots are stopped at the next round and retired after it
+    P->cv_done.wait(lk, [&] {
+        if (P->engine_error) return true;
+        for (int b = 0; b < P->m; ++b)
+            if (P->occupied[b] && P->cancelled[b]) return false;
+        return true;
+    });
+    if (P->engine_error) return fail(P->engine_error, "engine stopped: %s", P->engine_msg.c_str());
+    return KBNB_OK;
+}
+
+namespace kbnb {
+// poll_bounds that also returns, per result, the iterate whose dual point
+// gave its certified bound (NaN rows for nodes finished before keep_lb_beta)
+int poll_with_lb_beta(kbnb_problem *P, kbnb_bound_result *out, int cap, int *n_out, int32_t *supports,
+                      double *betas, double *betas_lb, int timeout_us)
+{
+    return poll_impl(P, out, cap, n_out, supports, betas, timeout_us, betas_lb);
+}
+// results retired from now on carry the iterate of their certified bound
+void keep_lb_beta(kbnb_problem *P, bool on)
+{
+    std::lock_guard<std::mutex> g(P->mu);
+    P->want_lb_beta = on;
+}
+// nodes queued, running or completed but not yet polled
+bool outstanding(kbnb_problem *P)
+{
+    std::lock_guard<std::mutex> g(P->mu);
+    return !P->pending.empty() || P->active > 0 || !P->done.empty();
+}
+}  // namespace kbnb
 
 extern "C" int poll_bounds(kbnb_problem *P, kbnb_bound_result *out, int32_t cap, int32_t *n_out,
                            int32_t *supports, double *betas, int32_t timeout_us)
@@ -1249,8 +1362,8 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
     const size_t C = (size_t)off[count], Cn = std::max<size_t>(C, 1), N = (size_t)count;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t b_lab = al(Cn * 4), b_off = al((N + 1) * 8), b_warm = al(Cn * 8), b_coef = al(Cn * 8),
-                 b_val = al(N * 8), b_low = al(N * 8), b_st = al(N * 4), b_it = al(N * 4);
-    const size_t need = b_lab + b_off + b_warm + b_coef + b_val + b_low + b_st + b_it;
+                 b_val = al(N * 8), b_low = al(N * 8), b_st = al(N * 4), b_it = al(N * 4), b_clb = al(Cn * 8);
+    const size_t need = b_lab + b_off + b_warm + b_coef + b_val + b_low + b_st + b_it + b_clb;
     if (need > P->sbuf_bytes) {
         HIP_TRY(hipStreamSynchronize(P->sstream));
         if (P->sbuf) (void)hipFree(P->sbuf);
@@ -1268,14 +1381,15 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
     P->s_val = (double *)b; b += b_val;
     P->s_low = (double *)b; b += b_low;
     P->s_st = (int32_t *)b; b += b_st;
-    P->s_it = (int32_t *)b;
+    P->s_it = (int32_t *)b; b += b_it;
+    P->s_coef_lb = (double *)b;
     hipStream_t s = P->sstream;
     HIP_TRY(hipMemcpyAsync(dlab, lab, 4 * C, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(doff, off, 8 * (N + 1), hipMemcpyHostToDevice, s));
     if (warm) HIP_TRY(hipMemcpyAsync(dwarm, warm, 8 * C, hipMemcpyHostToDevice, s));
     if (launch_support_eval(s, P->xtype, P->XT, P->npad, P->n, P->loss, P->y, dlab, doff, count, maxlen,
                             warm ? dwarm : nullptr, P->lambda2, P->M, tol, max_iter, 10, P->s_coef, P->s_val,
-                            P->s_low, P->s_st, P->s_it) != 0)
+                            P->s_low, P->s_st, P->s_it, P->s_coef_lb) != 0)
         return fail(KBNB_E_INVALID_ARGUMENT, "support too long");
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(P->sev, s));
@@ -1286,7 +1400,7 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
 }
 
 int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double *coefs, int32_t *status,
-                          int32_t *iters)
+                          int32_t *iters, double *coefs_lb)
 {
     std::lock_guard<std::mutex> g(P->api_mu);
     const size_t N = (size_t)P->s_count, C = (size_t)P->s_coefs;
@@ -1299,6 +1413,7 @@ int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double
     if (coefs && C) HIP_TRY(hipMemcpyAsync(coefs, P->s_coef, 8 * C, hipMemcpyDeviceToHost, s));
     if (status) HIP_TRY(hipMemcpyAsync(status, P->s_st, 4 * N, hipMemcpyDeviceToHost, s));
     if (iters) HIP_TRY(hipMemcpyAsync(iters, P->s_it, 4 * N, hipMemcpyDeviceToHost, s));
+    if (coefs_lb && C) HIP_TRY(hipMemcpyAsync(coefs_lb, P->s_coef_lb, 8 * C, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return KBNB_OK;
 }
@@ -1311,7 +1426,7 @@ int eval_supports(kbnb_problem *P, const int32_t *lab, const int64_t *off, int c
     if (count <= 0) return KBNB_OK;
     int rc = eval_supports_launch(P, lab, off, count, maxlen, warm, tol, max_iter);
     if (rc) return rc;
-    return eval_supports_collect(P, values, lower, coefs, status, iters);
+    return eval_supports_collect(P, values, lower, coefs, status, iters, nullptr);
 }
 }  // namespace kbnb
 

@@ -60,6 +60,7 @@ struct SlotState {
     int32_t *slen;    // rounding-support length
     int32_t *sup;     // [mpad][k] rounding support, ascending, -1 padded
     int32_t *perm;    // [mpad][pp] sorted order of the node's |u| at its last step
+    double *blb;      // [mpad][ldp] iterate whose dual point gave the best certified bound
 };
 
 // Problem constants passed by value to kernels.
@@ -149,7 +150,7 @@ int launch_support_eval(hipStream_t s, int xtype, const void *XT, int64_t npad, 
                         const double *y, const int32_t *lab, const int64_t *off, int count, int maxlen,
                         const double *warm, double lambda2, double M, double tol, int max_iter,
                         int cert_every, double *beta_out, double *value, double *lower, int32_t *status,
-                        int32_t *iters);
+                        int32_t *iters, double *beta_lb_out = nullptr);
 // convert/transposed copies
 void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
                       int npad, int pm);

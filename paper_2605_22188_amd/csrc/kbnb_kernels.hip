@@ -1385,6 +1385,7 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
     const double inv2l = 1.0 / (2.0 * c.lambda2);
     const double slack = 1.0 + 1e-9;
     const double phi_prev = update_state ? ss.phi[b] : INFINITY;
+    const double lb_prev = update_state ? ss.lb[b] : -INFINITY;
 
     double qv[E], bv[E];
     int sv[E];
@@ -1511,7 +1512,16 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
         jstar = (v >= 0.0) ? vi : -1;
     }
 
-    // g on the free set
+    // g on the free set (Thm. 4.1): with the free magnitudes sorted
+    // descending, a_(0) >= a_(1) >= ..., the budget equation
+    // sum_j min(1, a_j / tau) = kbar has the solution tau = tail(s) / (kbar - s)
+    // for the s with a_(s-1) >= tau >= a_(s), where tail(s) = sum_{r >= s} a_(r);
+    // then g_free = (1/2) sum_{r < s} a_(r)^2 + (1/2) tau tail(s).  The tails
+    // are sums of non-negative terms (the entries outside the top kbar plus a
+    // suffix of the top kbar), so no cancellation enters tau.
+    double rest = 0.0;  // free magnitudes outside the selected top kbar
+    for (int j = t; j < PP; j += T) rest += fmax(L.a[j], 0.0);
+    rest = blk_sum<W>(rest);
     double gfree;
     if (bad) {
         gfree = INFINITY;
@@ -1520,25 +1530,50 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
     } else if (kbar <= 0 || sum_a > c.M * kbar * slack) {
         gfree = INFINITY;
     } else {
-        gfree = INFINITY;
-        double head = 0.0, head2 = 0.0;  // sums over the s capped entries
-        double best_viol = INFINITY, best_val = INFINITY;
-        for (int s = 0; s < kbar; ++s) {
-            const double tail = sum_a - head;
+        // the smallest s whose threshold lies in [a_(s), a_(s-1)] (relative
+        // slack 1e-10 for the rounding of the sums; at a tie both sides give
+        // the same value)
+        int sel = -1;
+        double tail = rest, tsel = 0.0;
+        for (int s = kbar - 1; s >= 0; --s) {
+            tail += L.topa[s];
             const double tau = tail / (double)(kbar - s);
             const double up = (s == 0) ? INFINITY : L.topa[s - 1];
-            const double lo = L.topa[s];
-            const double val = 0.5 * head2 + 0.5 * tau * tail;
-            if (up >= tau * (1.0 - 1e-12) && tau >= lo * (1.0 - 1e-12)) {
-                gfree = val;
-                break;
+            if (up >= tau * (1.0 - 1e-10) && tau >= L.topa[s] * (1.0 - 1e-10)) {
+                sel = s;
+                tsel = tail;
             }
-            const double viol = fmax(fmax(tau - up, lo - tau), 0.0) / tau;
-            if (viol < best_viol) { best_viol = viol; best_val = val; }
-            head += L.topa[s];
-            head2 += L.topa[s] * L.topa[s];
         }
-        if (!(gfree < INFINITY)) gfree = best_val;
+        if (sel >= 0) {
+            double head2 = 0.0;
+            for (int r = 0; r < sel; ++r) head2 += L.topa[r] * L.topa[r];
+            gfree = 0.5 * head2 + 0.5 * (tsel / (double)(kbar - sel)) * tsel;
+        } else {
+            // not reached in exact arithmetic (a solution exists whenever
+            // more than kbar entries are nonzero): solve the budget equation
+            // by bisection over tau instead
+            double tlo = 0.0, thi = fmax(L.topa[0], tail / (double)kbar);  // tail = every free magnitude
+            for (int it = 0; it < 200; ++it) {
+                const double tm = 0.5 * (tlo + thi);
+                double h = 0.0;
+                for (int r = t; r < kbar; r += T) h += fmin(1.0, L.topa[r] / tm);
+                for (int j = t; j < PP; j += T) h += (L.a[j] > 0.0) ? fmin(1.0, L.a[j] / tm) : 0.0;
+                h = blk_sum<W>(h);
+                if (h > (double)kbar) tlo = tm;
+                else thi = tm;
+            }
+            const double tau = 0.5 * (tlo + thi);
+            double v = 0.0;
+            for (int r = t; r < kbar; r += T) {
+                const double a = L.topa[r];
+                v += (a >= tau) ? 0.5 * a * a : 0.5 * tau * a;
+            }
+            for (int j = t; j < PP; j += T) {
+                const double a = L.a[j];
+                v += (a <= 0.0) ? 0.0 : ((a >= tau) ? 0.5 * a * a : 0.5 * tau * a);
+            }
+            gfree = blk_sum<W>(v);
+        }
     }
     const double phi = fl + 2.0 * c.lambda2 * (g1 + gfree);
     const double psi = -fc - 2.0 * c.lambda2 * (gin + topsum);
@@ -1574,6 +1609,14 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
         for (int q = 0; q < NQ; ++q) {
             const int j = j0 + 4 * q;
             if (j < c.ldp) st4(Bbest + off + j, &bv[4 * q]);
+        }
+    }
+    // the iterate whose dual point certifies the node's bound (audits replay it)
+    if (update_state && !nan && psi > lb_prev) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = j0 + 4 * q;
+            if (j < c.ldp) st4(ss.blb + off + j, &bv[4 * q]);
         }
     }
 
@@ -1643,6 +1686,7 @@ __global__ __launch_bounds__(64) void k_admit(const uint8_t *__restrict__ stage,
         B[off + j] = w;
         Bprev[off + j] = w;
         Bbest[off + j] = w;
+        ss.blb[off + j] = w;
         Yi[off + j] = (Ti)w;
         if (an.bc) {  // anchored at beta_c = 0 (D = w)
             an.bc[off + j] = 0.0;
@@ -1991,6 +2035,7 @@ struct SupportArgs {
     double lambda2, M, c_loss, tol;
     int max_iter, cert_every;
     double *beta_out;      // same layout as lab
+    double *beta_lb_out;   // nullable: coefficients whose dual point gave `lower`
     double *value, *lower;
     int32_t *status, *iters;
 };
@@ -2002,11 +2047,11 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
     constexpr int NPAIR = KB * (KB + 1) / 2;
     constexpr int PT = (NPAIR + 255) / 256;
     __shared__ int32_t L[KB];
-    __shared__ double Bv[KB], Bp[KB], Yv[KB], Bb[KB], Bn[KB];
+    __shared__ double Bv[KB], Bp[KB], Yv[KB], Bb[KB], Bn[KB], Bd[KB];
     __shared__ double G[KB][KB + 1];
     __shared__ double tile[TR][KB + 1];
     __shared__ double red[4][KB + 2];
-    __shared__ double sc[8];  // eta, theta, tmom, phi_best, psi_best, done, restart dot
+    __shared__ double sc[8];  // eta, theta, tmom, phi_best, psi_best, done, new best primal, new best dual
     const TA *XT = reinterpret_cast<const TA *>(a.XT);
     const int m = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -2020,6 +2065,7 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
         Bp[tid] = w;
         Yv[tid] = w;
         Bb[tid] = w;
+        Bd[tid] = w;
     }
     __syncthreads();
 
@@ -2183,6 +2229,7 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
                     } else {
                         sc[6] = 0.0;
                     }
+                    sc[7] = (psi > sc[4]) ? 1.0 : 0.0;
                     if (psi > sc[4]) sc[4] = psi;
                     const double den = fmax(fabs(sc[3]), 1e-12);
                     sc[5] = ((sc[3] - sc[4]) <= a.tol * den || it >= a.max_iter) ? 1.0 : 0.0;
@@ -2190,6 +2237,7 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
             }
             __syncthreads();
             if (tid < kl && sc[6] != 0.0) Bb[tid] = Bv[tid];
+            if (tid < kl && sc[7] != 0.0) Bd[tid] = Bv[tid];
             if (sc[5] != 0.0) break;
             __syncthreads();
             continue;  // the certificate pass takes no step
@@ -2227,6 +2275,7 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
         __syncthreads();
     }
     if (tid < kl) a.beta_out[o0 + tid] = Bb[tid];
+    if (tid < kl && a.beta_lb_out) a.beta_lb_out[o0 + tid] = Bd[tid];
     if (tid == 0) {
         a.value[m] = sc[3];
         a.lower[m] = fmin(sc[4], sc[3]);
@@ -2239,10 +2288,11 @@ int launch_support_eval(hipStream_t s, int xtype, const void *XT, int64_t npad, 
                         const double *y, const int32_t *lab, const int64_t *off, int count, int maxlen,
                         const double *warm, double lambda2, double M, double tol, int max_iter,
                         int cert_every, double *beta_out, double *value, double *lower, int32_t *status,
-                        int32_t *iters)
+                        int32_t *iters, double *beta_lb_out)
 {
     if (count <= 0) return 0;
     SupportArgs a{};
+    a.beta_lb_out = beta_lb_out;
     a.XT = XT; a.npad = npad; a.n = n; a.loss = loss; a.y = y; a.lab = lab; a.off = off; a.warm = warm;
     a.lambda2 = lambda2; a.M = M; a.c_loss = (loss == 0) ? 2.0 : 0.25; a.tol = tol;
     a.max_iter = max_iter; a.cert_every = cert_every;

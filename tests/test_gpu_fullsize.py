@@ -12,11 +12,18 @@ times, on sampled outputs the oracle can check one by one:
     at zero gap, with the incumbent's objective reproduced by the oracle at
     the returned coefficients and its bound below it.
 
-The oracle's own solves are too slow at these sizes; its certificate
+Both searches run in audit mode: every discarded subtree comes back with the
+certificate of its bound, and the oracle replays each certificate's dual
+value in float64 from the exact instance (tests/audit_replay.py), so every
+pruning decision and the reported global bound are checked independently of
+the device arithmetic.
+
+The oracle's own node solves are too slow at these sizes; its certificate
 arithmetic is compared element by element elsewhere."""
 import numpy as np
 import pytest
 
+import audit_replay
 import oracle
 import paper_2605_22188_amd as K
 import workloads as W
@@ -54,12 +61,15 @@ def test_large_logistic_100000x5000_sampled_nodes_and_rashomon():
         assert list(g["support"]) == list(s_o), i
         assert g["branch_index"] == br_o, i
     print("[gpu-test] 100000x5000: branch and bound, eps 0.01", flush=True)
-    out = K.branch_and_bound(h, time_limit_s=150, rashomon_eps=0.01)
+    out = K.branch_and_bound(h, time_limit_s=150, rashomon_eps=0.01, audit=True)
     K.destroy_problem(h)
     assert out["status"] == 0 and out["rel_gap"] <= 1e-6
     S = [int(j) for j in out["support"]]
     assert P.primal(_state_of_support(inst.p, S), out["beta"]) == pytest.approx(out["objective"], rel=1e-9)
     assert [tuple(S)] == [T for T, _, _ in out["rashomon"]]
+    print(f"[gpu-test] 100000x5000: replaying {len(out['leaves'])} leaf certificates", flush=True)
+    summary = audit_replay.replay(P, out, rashomon_eps=0.01)
+    print(f"[gpu-test] 100000x5000 audit: {summary}", flush=True)
 
 
 def test_bnb_squared_10000x1000_bf16_zero_gap():
@@ -67,7 +77,7 @@ def test_bnb_squared_10000x1000_bf16_zero_gap():
     inst = W.bnb_squared_10000x1000_bf16()
     P = oracle.Problem.from_instance(inst)
     h = K.create_from_instance(inst, batch_width=1024, cert_period=16)
-    out = K.branch_and_bound(h, time_limit_s=120)
+    out = K.branch_and_bound(h, time_limit_s=120, audit=True)
     K.destroy_problem(h)
     assert out["status"] == 0 and out["rel_gap"] <= 1e-6
     S = [int(j) for j in out["support"]]
@@ -75,3 +85,7 @@ def test_bnb_squared_10000x1000_bf16_zero_gap():
     phi = P.primal(_state_of_support(inst.p, S), out["beta"])
     assert phi == pytest.approx(out["objective"], rel=1e-9)
     assert out["lower_bound"] <= phi * (1 + 1e-12)
+    summary = audit_replay.replay(P, out)
+    print(f"[gpu-test] 10000x1000 audit: {summary}", flush=True)
+    # the replayed bounds alone certify the optimum to the gap tolerance
+    assert summary["min_replayed"] >= out["objective"] * (1 - 1e-6) - 1e-9 * abs(out["objective"])

@@ -136,6 +136,70 @@ def test_certify_batch_wide_nodes(n, p, k, loss):
     _certify_case(W.small_instance(n, p, k, loss, seed=p, lambda2=1.0), 24, 13)
 
 
+def _threshold_betas(r, states, k, M):
+    """Iterates whose free magnitudes put Thm. 4.1's threshold tau exactly on
+    an entry (several s satisfy the threshold condition), or many equal
+    entries, or a large head with a tail thousands of times smaller (where a
+    tail formed as total minus head would lose its digits)."""
+    m, p = states.shape
+    betas = np.zeros((m, p))
+    for b in range(m):
+        st = states[b]
+        fin = np.flatnonzero(st == 1)
+        free = r.permutation(np.flatnonzero(st == 0))
+        kbar = k - len(fin)
+        betas[b, fin] = r.uniform(-M, M, size=len(fin))
+        kind = b % 3
+        if kbar < 2 or len(free) < 3:
+            continue
+        if kind == 2:   # q > kbar equal entries: tau = q c / kbar
+            q = min(len(free), kbar + 1 + int(r.integers(0, kbar + 1)))
+            c = M * kbar / q * r.uniform(0.3, 1.0)
+            a = np.full(q, c)
+        else:
+            s0 = int(r.integers(0, kbar - 1))          # kbar - s0 >= 2
+            q = min(3 * (kbar - s0), len(free) - s0 - 1)
+            head = np.sort(M * r.uniform(0.6, 1.0, size=s0))[::-1]
+            x = (0.3 if kind == 0 else 1e-3) * (head[-1] if s0 else M)
+            # tail sum (kbar - s0) x: tau = x exactly, a tie between s0 and s0 + 1
+            y = np.full(q, (kbar - s0 - 1) * x / q)
+            a = np.concatenate([head, [x], y])
+        sg = r.choice([-1.0, 1.0], size=len(a))
+        betas[b, free[:len(a)]] = sg * a
+    return betas
+
+
+def test_certify_batch_threshold_ties():
+    """The primal value where the threshold of Thm. 4.1 ties with an entry,
+    where many entries are equal, and where the tail is tiny next to the
+    head: Phi against the oracle, which solves the budget equation by
+    bisection.  A large lambda2 makes 2 lambda2 g(beta) dominate Phi."""
+    announce("certify_batch threshold ties squared 300x64")
+    inst = W.small_instance(300, 64, 12, W.SQUARED, seed=21, lambda2=1e3, M=2.0)
+    h = K.create_from_instance(inst, batch_width=64)
+    P = oracle.Problem.from_instance(inst)
+    r = rng(22)
+    m = 60
+    states = np.zeros((m, 64), np.int8)
+    for b in range(m):
+        perm = r.permutation(64)
+        n1, n0 = int(r.integers(0, 4)), int(r.integers(0, 11))
+        states[b, perm[:n1]] = 1
+        states[b, perm[n1:n1 + n0]] = -1
+    betas = _threshold_betas(r, states, 12, 2.0)
+    phi, psi, sup, br = K.certify_batch(h, states, betas)
+    for b in range(m):
+        g_o = P.g(states[b], betas[b])
+        assert np.isfinite(g_o), b
+        phi_o = P.primal(states[b], betas[b])
+        assert phi[b] == pytest.approx(phi_o, rel=1e-11), (b, phi[b], phi_o)
+        assert psi[b] == pytest.approx(P.dual(states[b], P.dual_point(betas[b])), rel=1e-11), b
+        s_o, br_o = P.round_branch(states[b], betas[b])
+        assert list(sup[b][:len(s_o)]) == list(s_o), b
+        assert br[b] == br_o, b
+    K.destroy_problem(h)
+
+
 def _bound_parity(inst, nodes, batch_width, cert_period, warm=None, sample=None, iter_dtype=0):
     h = K.create_from_instance(inst, batch_width=batch_width, cert_period=cert_period,
                                iter_dtype=iter_dtype)
@@ -186,6 +250,36 @@ def test_node_bounds_logistic_5000x200_launch():
     sample = list(range(0, 256, 16))
     res = _bound_parity(inst, nodes, batch_width=256, cert_period=8, sample=sample)
     assert all(r["status"] == K.CONVERGED for r in res)
+
+
+def test_node_bounds_logistic_5000x200_bench_settings():
+    """The benchmark's launch exactly as timed: 256 nodes of launch 0, batch
+    width 256, certificate every 16 steps, float32 iteration; 64 of the 256
+    nodes (every fourth) against the oracle solved to a 1e-10 gap."""
+    from concurrent.futures import ThreadPoolExecutor
+    announce("node bounds logistic 5000x200 at the benchmark settings, 64 of 256 sampled")
+    inst = W.node_bounds_logistic_5000x200()
+    nodes = W.launch_nodes_5000x200(0)
+    h = K.create_from_instance(inst, batch_width=256, cert_period=16)
+    res = K.bound_nodes(h, nodes, rel_tol=1e-6)
+    K.destroy_problem(h)
+    assert all(g["status"] == K.CONVERGED for g in res)
+    P = oracle.Problem.from_instance(inst)
+    sample = list(range(0, 256, 4))
+
+    def ref(i):
+        return P.node_bound(W.node_state(inst.p, nodes[i]), tol=1e-10, max_iter=100000)
+    with ThreadPoolExecutor(16) as ex:
+        refs = list(ex.map(ref, sample))
+    worst = 0.0
+    for i, rf in zip(sample, refs):
+        g = res[i]
+        assert g["lower_bound"] <= rf["phi"] + 1e-12 * abs(rf["phi"]), (i, g["lower_bound"], rf)
+        assert g["lower_bound"] >= rf["lb"] - 1e-6 * abs(rf["lb"]), (i, g["lower_bound"], rf)
+        worst = max(worst, abs(g["lower_bound"] - rf["lb"]) / abs(rf["lb"]))
+        s_o, br_o = P.round_branch(W.node_state(inst.p, nodes[i]), g["beta"])
+        assert list(g["support"]) == list(s_o) and g["branch_index"] == br_o, i
+    print(f"[gpu-test] worst |LB_gpu - LB_oracle| / |LB_oracle| = {worst:.3e}", flush=True)
 
 
 def test_node_bounds_float64_instance():
