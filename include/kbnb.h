@@ -465,6 +465,29 @@ int certify_batch(kbnb_problem *prob, int32_t m, const int8_t *states,
                   const double *betas, double *phi, double *psi,
                   int32_t *supports, int32_t *branch);
 
+/*
+ * certify_batch_noalloc -- certify_batch for callers that cannot allocate
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The same float64 certificate kernels, with every
+ * intermediate buffer (padded iterates and states, the dual points zeta, the
+ * split-K partials of X^T zeta, the loss sums, per-node results) in a
+ * fixed-size device array of the library (64 MiB, one copy per device, held
+ * until the process ends); nothing is allocated, and no host-device copy or
+ * synchronisation is made: the work is enqueued on `hip_stream` (NULL: the
+ * problem's own stream) and the call returns.  All arrays are device arrays
+ * on the problem's device: states m x p int8 (1 in, -1 out, 0 free), betas
+ * m x p float64, outputs phi and psi (m float64), supports (nullable, m x k
+ * int32) and branch (nullable, m int32), with certify_batch's meaning.  A
+ * node whose states hold a value outside {-1, 0, 1} or more than k fixed-in
+ * entries gets phi = psi = NaN, supports -1 and branch -1.  Calls that
+ * overlap on one device race on the shared array: order them on one stream.
+ * KBNB_E_INVALID_ARGUMENT when the call needs more than the array holds
+ * (about 8 (n + (splits + 1) p) bytes per node, rounded up to 64 nodes) or
+ * the stream belongs to another device.
+ */
+int certify_batch_noalloc(kbnb_problem *prob, int32_t m, const int8_t *states, const double *betas,
+                          double *phi, double *psi, int32_t *supports, int32_t *branch, void *hip_stream);
+
 /* Problem facts: i_out[0..8] = n, p, k, batch width, cert period, loss,
  * split-K count at full width, engine rounds so far, iteration precision
  * (KBNB_ITER_F32 / F64 / ANCHORED as resolved); d_out[0..3] = smoothness

@@ -98,7 +98,7 @@ EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
            "certify_batch", "problem_info", "kernel_stats", "pool_create", "pool_destroy",
            "pool_add", "pool_info", "pool_export", "pool_record", "rashomon_pool",
            "rashomon_reliance", "pool_summary", "evaluate_supports", "cancel_nodes",
-           "bnb_audit_leaf"]
+           "bnb_audit_leaf", "certify_batch_noalloc"]
 
 _lib = None
 
@@ -143,6 +143,7 @@ def load():
         lib.evaluate_supports.argtypes = [vp, i32, vp, dbl, i32, vp, vp, vp, vp, vp]
         lib.cancel_nodes.argtypes = [vp]
         lib.bnb_audit_leaf.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+        lib.certify_batch_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         for name in EXPORTS:
             if name != "last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -544,6 +545,25 @@ def certify_batch(h: Handle, states, betas):
     br = np.empty(m, np.int32)
     _check(load().certify_batch(h.ptr, m, _p(st), _p(bb), _p(phi), _p(psi), _p(sup), _p(br)))
     return phi, psi, sup, br
+
+
+def certify_batch_noalloc(h: Handle, states, betas, phi, psi, supports=None, branch=None,
+                          stream=None):
+    """certify_batch on torch device tensors without any allocation: states
+    (m, p) int8, betas (m, p) float64; writes phi, psi (m,) float64 and, when
+    given, supports (m, k) int32 and branch (m,) int32.  Enqueued on `stream`
+    (a torch stream; None: the problem's own stream); the caller
+    synchronises."""
+    m = states.shape[0]
+    assert tuple(states.shape) == (m, h.p) and tuple(betas.shape) == (m, h.p)
+    for t in (states, betas, phi, psi, supports, branch):
+        assert t is None or t.is_contiguous()
+
+    def ptr(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(load().certify_batch_noalloc(h.ptr, int(m), ptr(states), ptr(betas), ptr(phi), ptr(psi),
+                                        ptr(supports), ptr(branch), st))
 
 
 def problem_info(h: Handle):

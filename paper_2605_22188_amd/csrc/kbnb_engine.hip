@@ -115,6 +115,8 @@ struct HostSlots {
 };
 
 struct kbnb_problem {
+    int device = 0;                  // the device current at create_problem
+    unsigned char *scratch = nullptr; // that device's copy of the allocation-free scratch array
     // instance
     int n = 0, p = 0, k = 0, loss = 0, xtype = 0;
     double lambda2 = 0, M = 0, L = 0, eta = 0;
@@ -813,6 +815,32 @@ static int anchor_grad0(kbnb_problem *P)
 }
 
 // ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point: a file-scope device array of
+// fixed size, one copy per device, its address looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char *> g_scratch_ptr;  // device -> address of its copy
+
+// Called with `dev` current (create_problem).
+static int scratch_for_device(int dev, unsigned char **out)
+{
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(KBNB_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, (unsigned char *)ptr).first;
+    }
+    *out = it->second;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
 // create / destroy
 // ---------------------------------------------------------------------------
 static int device_ok()
@@ -902,6 +930,9 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     }
 
     kbnb_problem *P = new kbnb_problem();
+    (void)hipGetDevice(&P->device);
+    rc = scratch_for_device(P->device, &P->scratch);
+    if (rc) { delete P; return rc; }
     P->n = d->n; P->p = d->p; P->k = d->k; P->loss = d->loss;
     P->lambda2 = d->lambda2; P->M = d->M;
     P->xtype = d->x_dtype;
@@ -1339,6 +1370,141 @@ extern "C" int certify_batch(kbnb_problem *P, int32_t m, const int8_t *states, c
     if (supports) HIP_TRY(hipMemcpyAsync(supports, dsup, (size_t)m * P->k * 4, hipMemcpyDeviceToHost, T.s));
     if (branch) HIP_TRY(hipMemcpyAsync(branch, djs, (size_t)m * 4, hipMemcpyDeviceToHost, T.s));
     HIP_TRY(hipStreamSynchronize(T.s));
+    return KBNB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// certify_batch_noalloc: the certificate of certify_batch on device arrays,
+// with every intermediate buffer in the problem device's scratch array.
+// ---------------------------------------------------------------------------
+// node b < mpad: pad the caller's [m][p] states and iterates into the
+// [mpad][ldp] layout of the certificate kernels, count J1 and flag invalid
+// states (a value outside {-1, 0, 1} or |J1| > k); clear the loss sums
+__global__ __launch_bounds__(256) void k_na_pack(const int8_t *__restrict__ states, const double *__restrict__ betas,
+                                                 int m, int p, int ldp, int k, int8_t *__restrict__ st,
+                                                 double *__restrict__ B, int32_t *__restrict__ kbar,
+                                                 int32_t *__restrict__ bad, double *__restrict__ lsum,
+                                                 double *__restrict__ csum, int tiles_n, int mpad)
+{
+    __shared__ int s_nin;
+    const int b = blockIdx.x;
+    if (threadIdx.x == 0) s_nin = 0;
+    __syncthreads();
+    int nin = 0, inval = 0;
+    for (int j = threadIdx.x; j < ldp; j += blockDim.x) {
+        const bool real = b < m && j < p;
+        const int s = real ? (int)states[(int64_t)b * p + j] : -1;
+        const bool ok = s >= -1 && s <= 1;
+        inval |= ok ? 0 : 1;
+        nin += (ok && s == 1) ? 1 : 0;
+        st[(int64_t)b * ldp + j] = (int8_t)(ok ? s : -1);
+        B[(int64_t)b * ldp + j] = real ? betas[(int64_t)b * p + j] : 0.0;
+    }
+    for (int q = threadIdx.x; q < tiles_n; q += blockDim.x) {
+        lsum[(int64_t)q * mpad + b] = 0.0;
+        csum[(int64_t)q * mpad + b] = 0.0;
+    }
+    if (nin) atomicAdd(&s_nin, nin);
+    inval = __syncthreads_or(inval);  // also orders the additions before the read below
+    nin = s_nin;
+    if (threadIdx.x == 0) {
+        const bool bd = inval || nin > k;
+        bad[b] = bd ? 1 : 0;
+        kbar[b] = bd ? 0 : k - nin;
+    }
+}
+
+// node b < m: results into the caller's arrays (NaN / -1 for an invalid node)
+__global__ void k_na_unpack(int m, int k, const int32_t *__restrict__ bad, const double *__restrict__ lb,
+                            const double *__restrict__ ph, const int32_t *__restrict__ sup,
+                            const int32_t *__restrict__ js, double *__restrict__ phi, double *__restrict__ psi,
+                            int32_t *__restrict__ sup_out, int32_t *__restrict__ br_out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= m) return;
+    const bool bd = bad[b] != 0;
+    phi[b] = bd ? NAN : ph[b];
+    psi[b] = bd ? NAN : lb[b];
+    if (sup_out)
+        for (int r = 0; r < k; ++r) sup_out[(int64_t)b * k + r] = bd ? -1 : sup[(int64_t)b * k + r];
+    if (br_out) br_out[b] = bd ? -1 : js[b];
+}
+
+// scratch bytes certify_batch_noalloc needs for m nodes (and the pieces' offsets)
+struct NaLayout {
+    size_t B, Z, Q, ls, cs, st, kb, lb, ph, sup, js, sl, bad, total;
+};
+static NaLayout na_layout(const kbnb_problem *P, int mpad, int qsplit)
+{
+    NaLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += round_up(bytes, 256);
+        return at;
+    };
+    L.B = take((size_t)mpad * P->ldp * 8);
+    L.Z = take((size_t)mpad * P->npad * 8);
+    L.Q = take((size_t)qsplit * mpad * P->ldp * 8);
+    L.ls = take((size_t)P->tiles_n * mpad * 8);
+    L.cs = take((size_t)P->tiles_n * mpad * 8);
+    L.st = take((size_t)mpad * P->ldp);
+    L.kb = take((size_t)mpad * 4);
+    L.lb = take((size_t)mpad * 8);
+    L.ph = take((size_t)mpad * 8);
+    L.sup = take((size_t)mpad * P->k * 4);
+    L.js = take((size_t)mpad * 4);
+    L.sl = take((size_t)mpad * 4);
+    L.bad = take((size_t)mpad * 4);
+    L.total = o;
+    return L;
+}
+
+extern "C" int certify_batch_noalloc(kbnb_problem *P, int32_t m, const int8_t *states, const double *betas,
+                                     double *phi, double *psi, int32_t *supports, int32_t *branch,
+                                     void *hip_stream)
+{
+    if (!P) return fail(KBNB_E_BAD_HANDLE, "NULL problem");
+    if (m <= 0 || !states || !betas || !phi || !psi)
+        return fail(KBNB_E_INVALID_ARGUMENT, "bad certify_batch_noalloc arguments");
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : P->stream;
+    {
+        hipDevice_t sd = 0;
+        HIP_TRY(hipStreamGetDevice(s, &sd));
+        if ((int)sd != P->device)
+            return fail(KBNB_E_INVALID_ARGUMENT, "the stream belongs to device %d, the problem to device %d", (int)sd,
+                        P->device);
+    }
+    const int mpad = (int)round_up(m, GEMM_BN);
+    Variant v;
+    splits_for(P, mpad, v);
+    const NaLayout L = na_layout(P, mpad, v.qsplit);
+    if (L.total > NOALLOC_SCRATCH_BYTES)
+        return fail(KBNB_E_INVALID_ARGUMENT,
+                    "m=%d needs %zu bytes of scratch at n=%d, p=%d; the maximum is %zu bytes (use fewer nodes per call)",
+                    m, L.total, P->n, P->p, NOALLOC_SCRATCH_BYTES);
+    std::lock_guard<std::mutex> g(P->api_mu);
+    unsigned char *base = P->scratch;
+    double *dB = (double *)(base + L.B), *dZ = (double *)(base + L.Z), *dQ = (double *)(base + L.Q);
+    double *dl = (double *)(base + L.ls), *dc = (double *)(base + L.cs);
+    int8_t *dst = (int8_t *)(base + L.st);
+    int32_t *dk = (int32_t *)(base + L.kb), *dsup = (int32_t *)(base + L.sup), *djs = (int32_t *)(base + L.js);
+    int32_t *dsl = (int32_t *)(base + L.sl), *dbad = (int32_t *)(base + L.bad);
+    double *dlb = (double *)(base + L.lb), *dph = (double *)(base + L.ph);
+    Consts c = P->c;
+    c.mpad = mpad;
+    c.m = m;
+    c.mact = mpad;
+    hipLaunchKernelGGL(k_na_pack, dim3(mpad), dim3(256), 0, s, states, betas, m, P->p, P->ldp, P->k, dst, dB, dk,
+                       dbad, dl, dc, P->tiles_n, mpad);
+    SlotState ss{};
+    ss.lb = dlb; ss.phi = dph; ss.kbar = dk; ss.sup = dsup; ss.jstar = djs; ss.slen = dsl;
+    launch_cert_fwd(s, P->xtype, P->X, dB, dZ, P->y, dl, dc, c, nullptr, nullptr);
+    launch_cert_bwd(s, P->xtype, P->XT, dZ, dQ, v.qsplit, v.qchunk, c, nullptr);
+    launch_cert_finish(s, dQ, v.qsplit, dl, dc, P->tiles_n, dB, nullptr, dst, ss, c, 0, Anchor{}, nullptr, nullptr);
+    hipLaunchKernelGGL(k_na_unpack, dim3((m + 255) / 256), dim3(256), 0, s, m, P->k, dbad, dlb, dph, dsup, djs, phi,
+                       psi, supports, branch);
+    HIP_TRY(hipGetLastError());
     return KBNB_OK;
 }
 
