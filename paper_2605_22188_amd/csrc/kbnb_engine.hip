@@ -122,6 +122,11 @@ struct kbnb_problem {
     double lambda2 = 0, M = 0, L = 0, eta = 0;
     bool iter_f64 = false;
     int ti_bytes = 4;
+    // plane mode (bfloat16 X, float32 or anchored iteration): tiled copies of
+    // X and X^T, and the point and R as nb bfloat16 planes
+    bool planes = false;
+    int nb = 0, nkb_x = 0, nkb_xt = 0;
+    uint16_t *xtile = nullptr, *xttile = nullptr, *yp = nullptr, *rp = nullptr;
     // sizes
     int ldp = 0, npad = 0, pm = 0, m = 0, mpad = 0, pp = 256;
     int tiles_n = 0;
@@ -221,11 +226,12 @@ struct Layout {
 
 static size_t per_slot_bytes(const kbnb_problem *P)
 {
-    const size_t ti = P->ti_bytes;
+    // the point and R: float / double, or nb bfloat16 planes
+    const size_t ti = P->planes ? 2 * (size_t)P->nb : (size_t)P->ti_bytes;
     size_t b = 0;
     b += (size_t)P->ldp * (ti + 8 + 8 + 8 + 8 + 1);    // Yi, B, Bprev, Bbest, Blb, st
     b += (size_t)P->npad * (ti + 8);                   // R, Z
-    b += (size_t)P->gsplit_alloc * P->ldp * ti;        // Gp
+    b += (size_t)P->gsplit_alloc * P->ldp * P->ti_bytes; // Gp
     b += (size_t)P->qsplit_alloc * P->ldp * 8;         // Qp
     b += (size_t)P->tiles_n * 16;                      // lsum, csum
     b += (size_t)P->ldp * 16 + 128 + P->k * 4;         // gather buffers, scalars, support
@@ -240,6 +246,15 @@ static size_t per_slot_bytes(const kbnb_problem *P)
 // partials, exactly the splits the same round's launch wrote).
 static void splits_for(const kbnb_problem *P, int mact, Variant &v)
 {
+    if (P->planes) {
+        // the streaming X^T R: 256-row tiles; about two workgroups per CU, at
+        // most 32 splits of a multiple of 128 rows (the tiled layout's k block)
+        const int st = ((P->pm + 255) / 256) * (mact / GEMM_BN);
+        int ws = std::min(32, std::max(1, (512 + st - 1) / st));
+        const int ch = (int)round_up((P->npad + ws - 1) / ws, 128);
+        v.gchunk = ch;
+        v.gsplit = (P->npad + ch - 1) / ch;
+    }
     const int tiles = (P->pm / GEMM_BM) * (mact / GEMM_BN);
     const int kt = P->npad / GEMM_BK;  // 16-wide k chunks
     int want = std::max(1, (256 + tiles - 1) / tiles);
@@ -248,10 +263,12 @@ static void splits_for(const kbnb_problem *P, int mact, Variant &v)
     want = std::min(want, 32);
     const int chunk = (int)round_up((P->npad + want - 1) / want, GEMM_BK);
     v.mact = mact;
-    v.gchunk = chunk;
-    v.gsplit = (P->npad + chunk - 1) / chunk;
+    if (!P->planes) {
+        v.gchunk = chunk;
+        v.gsplit = (P->npad + chunk - 1) / chunk;
+    }
     v.qchunk = chunk;
-    v.qsplit = v.gsplit;
+    v.qsplit = (P->npad + chunk - 1) / chunk;
 }
 
 static void choose_splits(kbnb_problem *P)
@@ -279,8 +296,8 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         P->own_x ? xbytes : 0,                   // X
         (size_t)P->pm * P->npad * xel,           // XT
         (size_t)P->npad * 8,                     // y
-        mp * P->ldp * ti,                        // Yi
-        mp * P->npad * ti,                       // R
+        P->planes ? 0 : mp * P->ldp * ti,        // Yi
+        P->planes ? 0 : mp * P->npad * ti,       // R
         (size_t)P->gsplit_alloc * mp * P->ldp * ti, // Gp
         mp * P->ldp * 8,                         // B
         mp * P->ldp * 8,                         // Bprev
@@ -303,6 +320,10 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
         P->anchored ? (size_t)P->ldp * 8 : 0,    // grad F(0)
         mp * P->ldp * 8,                         // Blb
         mp * P->ldp * 8,                         // second gather buffer (Blb columns)
+        P->planes ? (size_t)round_up(P->npad, 16) * P->nkb_x * 128 * 2 : 0,  // tiled X
+        P->planes ? (size_t)P->pm * P->nkb_xt * 128 * 2 : 0,                 // tiled X^T
+        P->planes ? (size_t)P->nb * mp * P->ldp * 2 : 0,                      // planes of Y
+        P->planes ? (size_t)P->nb * mp * P->npad * 2 : 0,                     // planes of R
     };
     const int nitems = sizeof(sizes) / sizeof(sizes[0]);
     size_t off[32];
@@ -369,6 +390,14 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
     }
     P->ss.blb = (double *)(base + off[25]);
     P->gbuf_lb = (double *)(base + off[26]);
+    if (P->planes) {
+        P->xtile = (uint16_t *)(base + off[27]);
+        P->xttile = (uint16_t *)(base + off[28]);
+        P->yp = (uint16_t *)(base + off[29]);
+        P->rp = (uint16_t *)(base + off[30]);
+        P->Yi = nullptr;
+        P->R = nullptr;
+    }
     P->slot_dev = base + off[16];
     P->slot_bytes = off[18] + sizes[18] - off[16];
     return 0;
@@ -945,6 +974,12 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     while (P->pp < P->p) P->pp *= 2;
     P->npad = (int)round_up(P->n, 64);
     P->pm = (int)round_up(P->ldp, 64);
+    P->planes = (d->x_dtype == KBNB_DTYPE_BF16) && !P->iter_f64;
+    if (P->planes) {
+        P->nb = P->anchored ? 2 : 3;
+        P->nkb_x = (P->ldp + 127) / 128;
+        P->nkb_xt = (P->npad + 127) / 128;
+    }
     // per-row-tile loss sums of the certificate: sized for 32-row tiles (the
     // arena is zeroed, so rows a 64-row launch does not write stay zero)
     P->tiles_n = P->npad / 32;
@@ -966,7 +1001,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     if (m == 0) {
         P->mpad = 64; P->m = 64;
         choose_splits(P);
-        const size_t fixed = 2 * xbytes + (size_t)P->npad * 8 + (1 << 20);
+        const size_t fixed = (P->planes ? 4 : 2) * xbytes + (size_t)P->npad * 8 + (1 << 20);
         const size_t per = per_slot_bytes(P) + P->rec_bytes;
         int64_t cap = (P->budget > fixed) ? (int64_t)((P->budget - fixed) / per) : 0;
         if (cap < 1) {
@@ -1007,6 +1042,12 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
         if (e != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "copying y failed: %s", hipGetErrorString(e)); }
     }
     launch_transpose(P->stream, P->xtype, P->X, P->XT, P->n, P->p, P->ldp, P->npad, P->pm);
+    if (P->planes) {
+        // rows of X past n are zero in the (cleared) arena; a borrowed X may
+        // hold only n rows
+        launch_tile_bf16(P->stream, (const uint16_t *)P->X, P->ldp, P->n, P->ldp, P->xtile);
+        launch_tile_bf16(P->stream, (const uint16_t *)P->XT, P->npad, P->pm, P->npad, P->xttile);
+    }
     if (hipStreamSynchronize(P->stream) != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "transpose failed"); }
     // pinned host mirrors
     {
@@ -1052,6 +1093,9 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->c.pp = P->pp;
     P->c.lambda2 = P->lambda2; P->c.M = P->M; P->c.eta = P->eta;
     P->c.mact = P->mpad;
+    P->c.xtile = P->xtile; P->c.xttile = P->xttile;
+    P->c.nkb_x = P->nkb_x; P->c.nkb_xt = P->nkb_xt;
+    P->c.yp = P->yp; P->c.rp = P->rp; P->c.nb = P->nb;
     for (Variant &v : P->var) build_graph(P, v);
     if (hipStreamSynchronize(P->stream) != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "setup failed"); }
     P->worker = std::thread(engine_main, P);

@@ -70,6 +70,16 @@ struct Consts {
     int mact;  // columns the launches cover (multiple of 64, <= mpad); slots beyond are empty
     int pp;  // per-node sort width: next power of two >= max(p, 256)
     double lambda2, M, eta;
+    // Plane mode (bfloat16 X with the float32 or anchored iteration): the
+    // iteration's contractions stream tiled copies of X and X^T (k_gemm_stream),
+    // and the point Y (or D) and R are kept as nb bfloat16 planes
+    // (nb = 3: float32-exact; nb = 2: a 16-bit significand, enough for the
+    // anchored iteration's increments).  yp is NULL outside plane mode.
+    const uint16_t *xtile, *xttile;  // k_tile_bf16 layouts of X and X^T
+    int nkb_x, nkb_xt;               // their 128-wide k blocks per 16-row block
+    uint16_t *yp;                    // [nb][mpad][ldp]
+    uint16_t *rp;                    // [nb][mpad][npad]
+    int nb;
 };
 
 // Staged node for admission into a slot (host -> device).
@@ -151,6 +161,48 @@ int launch_support_eval(hipStream_t s, int xtype, const void *XT, int64_t npad, 
                         const double *warm, double lambda2, double M, double tol, int max_iter,
                         int cert_every, double *beta_out, double *value, double *lower, int32_t *status,
                         int32_t *iters, double *beta_lb_out = nullptr);
+// Arguments of the MFMA contraction kernels (kbnb_kernels.hip):
+// C[col][row] = sum_k A[row][k] * B[col][k] over the workgroup's k split.
+enum { EPI_DLOSS = 0, EPI_STORE = 1, EPI_CERT = 2, EPI_DLOSS_ANCHOR = 3 };
+
+struct GemmArgs {
+    const void *A;
+    int64_t lda;
+    const void *B;
+    int64_t ldb;
+    void *C;
+    int64_t ldc;
+    int64_t split_stride;  // elements between split partial buffers
+    int k_len;             // total k extent (multiple of 16)
+    int k_chunk;           // k per split (multiple of 16)
+    int tiles_m;
+    int tiles_n;
+    int nsplit;
+    const int32_t *col_status;  // nullable: skip tiles with no running column
+    int rows_valid;        // store rows < rows_valid (EPI_STORE)
+    int n;                 // rows with data (EPI_DLOSS / EPI_CERT)
+    int loss;
+    const double *y;
+    double *lsum;          // [tiles_m][ldsum]
+    double *csum;
+    int64_t ldsum;
+    const double *sc;      // EPI_DLOSS_ANCHOR: S_c, same layout as C
+    double *sc_out;        // EPI_CERT (nullable): also store S = acc, same layout as C
+    // plane operands (k_gemm_stream): element distance between the bfloat16
+    // planes of A, of B and of a plane output C; row counts of A and C
+    int64_t a_plane, b_plane, c_plane;
+    int rows_a, rows_c;
+};
+// streaming contraction for bfloat16 A (one plane) and three B planes, tile
+// (4 wr) x 64 with wr = 32 or 64 rows per wave and nb = 2 or 3 planes of B
+// (k_gemm_stream); modes EPI_DLOSS, EPI_DLOSS_ANCHOR (C: nb bfloat16 planes)
+// or EPI_STORE (float32 split-K partials).  Returns -1 for an unsupported
+// combination.
+int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_n, int splits, int wr, int nb);
+// tiled copy of a rows x cols bfloat16 matrix for k_gemm_stream (whose A is
+// this layout, with GemmArgs::lda = ceil(cols / 128)); dst holds
+// ceil(rows / 16) * 16 x ceil(cols / 128) * 128 elements
+void launch_tile_bf16(hipStream_t s, const uint16_t *src, int64_t lds, int rows, int cols, uint16_t *dst);
 // convert/transposed copies
 void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
                       int npad, int pm);

@@ -13,6 +13,7 @@
 //         primal/dual values, status, rounding support and branching index.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -174,32 +175,7 @@ template <> __device__ __forceinline__ double dloss_t<double>(int loss, double s
 //   EPI_CERT   C = zeta = -l'(acc, y[row]) for row < n, plus per-column sums
 //              of l(acc) and l*(-zeta) over this tile's rows.
 // ---------------------------------------------------------------------------
-enum { EPI_DLOSS = 0, EPI_STORE = 1, EPI_CERT = 2, EPI_DLOSS_ANCHOR = 3 };
-
-struct GemmArgs {
-    const void *A;
-    int64_t lda;
-    const void *B;
-    int64_t ldb;
-    void *C;
-    int64_t ldc;
-    int64_t split_stride;  // elements between split partial buffers
-    int k_len;             // total k extent (multiple of 16)
-    int k_chunk;           // k per split (multiple of 16)
-    int tiles_m;
-    int tiles_n;
-    int nsplit;
-    const int32_t *col_status;  // nullable: skip tiles with no running column
-    int rows_valid;        // store rows < rows_valid (EPI_STORE)
-    int n;                 // rows with data (EPI_DLOSS / EPI_CERT)
-    int loss;
-    const double *y;
-    double *lsum;          // [tiles_m][ldsum]
-    double *csum;
-    int64_t ldsum;
-    const double *sc;      // EPI_DLOSS_ANCHOR: S_c, same layout as C
-    double *sc_out;        // EPI_CERT (nullable): also store S = acc, same layout as C
-};
+// (the epilogue modes and GemmArgs are declared in kbnb_internal.h)
 
 // XCD-aware tile order shared by the contraction kernels: workgroups are
 // dealt round-robin to the 8 XCDs (blockIdx % 8), each with its own L2.
@@ -682,6 +658,287 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
 }
 
 // ---------------------------------------------------------------------------
+// bfloat16 planes.  A float32 value v is stored as planes v1 = bf16(v),
+// v2 = bf16(v - v1), v3 = bf16(v - v1 - v2) (round to nearest even): three
+// planes carry v's 24-bit significand, two planes 16 bits.  Products of
+// planes are exact in float32, so a bfloat16 matrix times the planes of a
+// float32 one is a sum of exact bfloat16 MFMA products.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint2 pack4(const uint16_t (&v)[4])
+{
+    return make_uint2(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16));
+}
+
+// the first NP (2 or 3) planes of 4 consecutive float32 values at element
+// offset o (planes `plane` elements apart)
+template <int NP = 3>
+__device__ __forceinline__ void store_planes4(uint16_t *C, int64_t plane, int64_t o, const float (&d)[4])
+{
+    uint16_t h[4], m[4], l[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) split3(d[r], h[r], m[r], l[r]);
+    *reinterpret_cast<uint2 *>(C + o) = pack4(h);
+    *reinterpret_cast<uint2 *>(C + plane + o) = pack4(m);
+    if constexpr (NP > 2) *reinterpret_cast<uint2 *>(C + 2 * plane + o) = pack4(l);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming bfloat16 contraction for bfloat16 A against NB planes of B (the
+// bound of tall instances is the HBM stream of X).  Tile 4 WR x 64: wave w
+// owns rows row0 + WR w .. + WR - 1 and all 64 columns (WR/16 x 4 MFMA
+// blocks of 16 x 16, float32 accumulate).  The k loop runs in super-steps of
+// 128.  Each lane loads its A rows straight into registers in the MFMA
+// operand layout, from the tiled copy of k_tile_bf16 in which every load
+// instruction of a wave reads 1 KB of contiguous memory, one super-step
+// ahead of the MFMAs (no LDS traffic for A).  B is staged through LDS,
+// prefetched into registers one super-step ahead.  MFMA k-step h of a
+// super-step contracts, in lane group g, k = 32 g + 8 h .. + 7 of A and B
+// alike (a fixed permutation of the k order inside the super-step).
+// Epilogues: EPI_DLOSS (R = l'(S, y) written as NB planes), EPI_DLOSS_ANCHOR
+// (R = l'(S_c + S) - l'(S_c) formed in float64, NB planes), EPI_STORE
+// (split-K float32 partials).  Rows of A past rows_a repeat the last row
+// block and are not stored (rows_c / rows_valid).
+// ---------------------------------------------------------------------------
+template <int MODE, int WR, int NB>
+__global__ __launch_bounds__(256) void k_gemm_stream(GemmArgs g)
+{
+    constexpr int BM = 4 * WR, BN = GEMM_BN, SK = 128;
+    constexpr int FI = WR / 16, FJ = 4;
+    constexpr int LSB = SK + 8;                 // LDS row stride (bf16): 272 bytes
+    constexpr int CPR = SK / 8;                 // 16-byte chunks per B row and super-step
+    constexpr int LPB = (BN * CPR) / 256;       // B chunks per thread and plane (4)
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[NB][BN * LSB];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    int tm, tn, split;
+    if (!map_tile(g, tm, tn, split)) return;
+    const int row0 = tm * BM, col0 = tn * BN;
+    const int wrow = row0 + WR * wave;
+    const int kbeg = split * g.k_chunk;
+    const int kend = max(kbeg, min(g.k_len, kbeg + g.k_chunk));
+    const uint16_t *A = reinterpret_cast<const uint16_t *>(g.A);
+    const uint16_t *Bg = reinterpret_cast<const uint16_t *>(g.B);
+    const int run = (g.col_status && tid < BN) ? (g.col_status[col0 + tid] == SLOT_RUNNING) : 1;
+
+    f32x4 acc[FI][FJ];
+#pragma unroll
+    for (int i = 0; i < FI; ++i)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+    // A is in the tiled layout of k_tile_bf16 (g.lda = 128-wide k blocks per
+    // 16-row block): the 16 x 128 block of row block rb and k block kb is
+    // 2048 contiguous elements, in which instruction q of lane l reads the 16
+    // bytes at (64 q + l) * 8, i.e. row l % 16, k = 32 (l / 16) + 8 q: each
+    // load instruction of a wave reads 1 KB of contiguous memory.  A row
+    // block past the last one reads the last (its outputs are not stored);
+    // the layout is zero beyond the k extent, and B is zeroed past kend when
+    // staged, so split boundaries need no guard on A (they are multiples of
+    // 128).
+    const int nrb = (g.rows_a + 15) / 16;
+    const uint16_t *pa[FI];
+#pragma unroll
+    for (int f = 0; f < FI; ++f)
+        pa[f] = A + (int64_t)min(wrow / 16 + f, nrb - 1) * g.lda * 2048 + (int64_t)lane * 8;
+    uint4 ra0[FI][4], ra1[FI][4], rb0[NB][LPB], rb1[NB][LPB];
+    auto load = [&](int k0, uint4 (&ra)[FI][4], uint4 (&rb)[NB][LPB]) {
+        const int64_t kb = (int64_t)(k0 / 128) * 2048;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int f = 0; f < FI; ++f) ra[f][q] = *reinterpret_cast<const uint4 *>(pa[f] + kb + 512 * q);
+        }
+#pragma unroll
+        for (int v = 0; v < LPB; ++v) {
+            const int x = tid + 256 * v;
+            const int cl = x / CPR, k = k0 + 8 * (x % CPR);
+            const int64_t o = (int64_t)(col0 + cl) * g.ldb + ((k < kend) ? k : kbeg);
+#pragma unroll
+            for (int pb = 0; pb < NB; ++pb) rb[pb][v] = *reinterpret_cast<const uint4 *>(Bg + pb * g.b_plane + o);
+        }
+    };
+    auto stage_b = [&](const uint4 (&rb)[NB][LPB], int k0) {
+#pragma unroll
+        for (int v = 0; v < LPB; ++v) {
+            const int x = tid + 256 * v;
+            const int cl = x / CPR, kq = 8 * (x % CPR);
+            const bool ok = k0 + kq < kend;
+#pragma unroll
+            for (int pb = 0; pb < NB; ++pb)
+                *reinterpret_cast<uint4 *>(&Bs[pb][cl * LSB + kq]) = ok ? rb[pb][v] : make_uint4(0, 0, 0, 0);
+        }
+    };
+    // B operands of MFMA k-step h, read from LDS one k-step ahead of their use
+    auto read_b = [&](int h, bf16x8 (&bv)[NB][FJ]) {
+#pragma unroll
+        for (int pb = 0; pb < NB; ++pb)
+#pragma unroll
+            for (int j = 0; j < FJ; ++j)
+                bv[pb][j] = *reinterpret_cast<const bf16x8 *>(&Bs[pb][(16 * j + lr) * LSB + 32 * lg + 8 * h]);
+    };
+    auto mfmas = [&](const uint4 (&ra)[FI][4], int h, const bf16x8 (&bv)[NB][FJ]) {
+#pragma unroll
+        for (int t = NB - 1; t >= 0; --t)  // small terms first
+#pragma unroll
+            for (int f = 0; f < FI; ++f) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&ra[f][h]);
+#pragma unroll
+                for (int j = 0; j < FJ; ++j)
+                    acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[t][j], acc[f][j], 0, 0, 0);
+            }
+    };
+    auto compute = [&](const uint4 (&ra)[FI][4]) {
+        bf16x8 b0[NB][FJ], b1[NB][FJ];
+        read_b(0, b0);
+        read_b(1, b1);
+        mfmas(ra, 0, b0);
+        read_b(2, b0);
+        mfmas(ra, 1, b1);
+        read_b(3, b1);
+        mfmas(ra, 2, b0);
+        mfmas(ra, 3, b1);
+    };
+
+    const int nss = (kend - kbeg + SK - 1) / SK;
+    if (nss > 0) load(kbeg, ra0, rb0);
+    if (!__syncthreads_or(run)) return;  // every node of the tile has finished
+    // two super-steps per trip, so the register sets are fixed at compile time
+    for (int s = 0; s < nss; s += 2) {
+        __syncthreads();
+        stage_b(rb0, kbeg + s * SK);
+        __syncthreads();
+        if (s + 1 < nss) load(kbeg + (s + 1) * SK, ra1, rb1);
+        compute(ra0);
+        if (s + 1 >= nss) break;
+        __syncthreads();
+        stage_b(rb1, kbeg + (s + 1) * SK);
+        __syncthreads();
+        if (s + 2 < nss) load(kbeg + (s + 2) * SK, ra0, rb0);
+        compute(ra1);
+    }
+
+    // ---- epilogue: acc[f][j][r] holds C at row = wrow + 16 f + 4 lg + r,
+    //                col = col0 + 16 j + lr
+    if constexpr (MODE == EPI_STORE) {
+        float *C = reinterpret_cast<float *>(g.C) + (int64_t)split * g.split_stride;
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) {
+            const int col = col0 + 16 * j + lr;
+#pragma unroll
+            for (int f = 0; f < FI; ++f) {
+                const int rb = wrow + 16 * f + 4 * lg;
+                if (rb + 3 < g.rows_valid) {
+                    *reinterpret_cast<f32x4 *>(C + (int64_t)col * g.ldc + rb) = acc[f][j];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (rb + r < g.rows_valid) C[(int64_t)col * g.ldc + rb + r] = acc[f][j][r];
+                }
+            }
+        }
+    } else {
+        uint16_t *C = reinterpret_cast<uint16_t *>(g.C);
+#pragma unroll
+        for (int f = 0; f < FI; ++f) {
+            const int rb = wrow + 16 * f + 4 * lg;
+            if (rb >= g.rows_c) continue;  // rows_c is a multiple of 4
+            double yv[4];
+            ld4(g.y + rb, yv);
+#pragma unroll
+            for (int j = 0; j < FJ; ++j) {
+                const int col = col0 + 16 * j + lr;
+                float d[4];
+                if constexpr (MODE == EPI_DLOSS) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        d[r] = (rb + r < g.n) ? dloss_f(g.loss, acc[f][j][r], (float)yv[r]) : 0.0f;
+                } else {  // EPI_DLOSS_ANCHOR
+                    if (g.loss == 0) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) d[r] = (rb + r < g.n) ? 2.0f * acc[f][j][r] : 0.0f;
+                    } else {
+                        double sc[4];
+                        ld4(g.sc + (int64_t)col * g.ldc + rb, sc);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const double sv = sc[r] + (double)acc[f][j][r];
+                            const double dd = dloss_d(g.loss, sv, yv[r]) - dloss_d(g.loss, sc[r], yv[r]);
+                            d[r] = (rb + r < g.n) ? (float)dd : 0.0f;
+                        }
+                    }
+                }
+                store_planes4<NB>(C, g.c_plane, (int64_t)col * g.ldc + rb, d);
+            }
+        }
+    }
+}
+
+// Tiled copy of a row-major bfloat16 matrix for k_gemm_stream: 16-row by
+// 128-column blocks of 2048 contiguous elements (row block rb, column block
+// kb at (rb * nkb + kb) * 2048), inside a block element (r, k) at
+// ((4 (k % 32 / 8) + k / 32) * 16 + r) * 8 + k % 8; zero outside rows x cols.
+// One thread per 8-element chunk.
+__global__ __launch_bounds__(256) void k_tile_bf16(const uint16_t *__restrict__ src, int64_t lds, int rows, int cols,
+                                                   int nrb, int nkb, uint16_t *__restrict__ dst)
+{
+    const int64_t nch = (int64_t)nrb * nkb * 256;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = c / 256;
+        const int w = (int)(c % 256);
+        const int q = w / 64, l = w % 64;
+        const int rb = (int)(b / nkb), kb = (int)(b % nkb);
+        const int row = rb * 16 + (l & 15), k = kb * 128 + 32 * (l >> 4) + 8 * q;
+        uint16_t v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (row < rows && k + e < cols) ? src[(int64_t)row * lds + k + e] : (uint16_t)0;
+        uint4 o;
+        o.x = v[0] | ((uint32_t)v[1] << 16);
+        o.y = v[2] | ((uint32_t)v[3] << 16);
+        o.z = v[4] | ((uint32_t)v[5] << 16);
+        o.w = v[6] | ((uint32_t)v[7] << 16);
+        *reinterpret_cast<uint4 *>(dst + c * 8) = o;
+    }
+}
+
+void launch_tile_bf16(hipStream_t s, const uint16_t *src, int64_t lds, int rows, int cols, uint16_t *dst)
+{
+    const int nrb = (rows + 15) / 16, nkb = (cols + 127) / 128;
+    const int64_t nch = (int64_t)nrb * nkb * 256;
+    const int blocks = (int)std::min<int64_t>((nch + 255) / 256, 16384);
+    if (blocks > 0) KBNB_LAUNCH(k_tile_bf16, dim3(blocks), dim3(256), 0, s, src, lds, rows, cols, nrb, nkb, dst);
+}
+
+int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_n, int splits, int wr, int nb)
+{
+    const int bm = 4 * wr;
+    g.tiles_n = tiles_n;
+    g.nsplit = splits;
+    g.tiles_m = (rows + bm - 1) / bm;
+    int nblocks;
+    if (splits > 1) nblocks = 8 * g.tiles_m * tiles_n * ((splits + 7) / 8);
+    else if (g.tiles_m >= 8) nblocks = (g.tiles_m + 7) / 8 * 8 * tiles_n;
+    else nblocks = g.tiles_m * tiles_n;
+    const dim3 grid(nblocks, 1);
+    if ((wr != 32 && wr != 64) || (nb != 2 && nb != 3)) return -1;
+#define KBNB_STREAM(M)                                                                           \
+    do {                                                                                         \
+        if (wr == 64 && nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 64, 3>), grid, dim3(256), 0, s, g); \
+        else if (wr == 64) KBNB_LAUNCH((k_gemm_stream<M, 64, 2>), grid, dim3(256), 0, s, g);       \
+        else if (nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 32, 3>), grid, dim3(256), 0, s, g);        \
+        else KBNB_LAUNCH((k_gemm_stream<M, 32, 2>), grid, dim3(256), 0, s, g);                     \
+    } while (0)
+    if (mode == EPI_DLOSS) KBNB_STREAM(EPI_DLOSS);
+    else if (mode == EPI_DLOSS_ANCHOR) KBNB_STREAM(EPI_DLOSS_ANCHOR);
+    else if (mode == EPI_STORE) KBNB_STREAM(EPI_STORE);
+    else return -1;
+#undef KBNB_STREAM
+    return 0;
+}
+
+
+// ---------------------------------------------------------------------------
 // Wavefront and workgroup helpers.  A per-node workgroup has W waves; with
 // W = 1 the block-level helpers are the plain wave operations.  Every block
 // helper must be reached by all threads of the workgroup.
@@ -885,6 +1142,25 @@ __device__ __forceinline__ void st4(double *p, const double v[4])
 {
     *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
     *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+}
+
+// The next point of the iteration, 4 consecutive entries at element offset o
+// of a node-major [mpad][ldp] array: float32 / float64 Yi, or in plane mode
+// its nb bfloat16 planes.
+template <typename Ti>
+__device__ __forceinline__ void store_y4(const Consts &c, Ti *Yi, int64_t o, const double (&v)[4])
+{
+    if (c.yp) {
+        uint16_t hh[4], mm[4], ll[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) split3((float)v[r], hh[r], mm[r], ll[r]);
+        const int64_t pl = (int64_t)c.mpad * c.ldp;
+        *reinterpret_cast<uint2 *>(c.yp + o) = pack4(hh);
+        *reinterpret_cast<uint2 *>(c.yp + pl + o) = pack4(mm);
+        if (c.nb > 2) *reinterpret_cast<uint2 *>(c.yp + 2 * pl + o) = pack4(ll);
+    } else {
+        st4(Yi + o, v);
+    }
 }
 
 // Sum of split-K partials for a thread's chunk: acc[e] += sum_s col[s * stride + j0 + e].
@@ -1287,7 +1563,7 @@ __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp,
                 yn[e] = bet[4 * q + e] + thn * (bet[4 * q + e] - bo[4 * q + e]) - bcv[4 * q + e];
             st4(Bprev + off + j, &bo[4 * q]);
             st4(B + off + j, &bet[4 * q]);
-            st4(Yi + off + j, yn);
+            store_y4(c, Yi, off + j, yn);
         }
     }
     if (t == 0) {
@@ -1600,7 +1876,7 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
                 }
                 st4(an.bc + off + j, &bv[4 * q]);
                 st4(an.gc + off + j, gq);
-                st4(Yi + off + j, dq);
+                store_y4(c, Yi, off + j, dq);
             }
         }
     }
@@ -1687,7 +1963,16 @@ __global__ __launch_bounds__(64) void k_admit(const uint8_t *__restrict__ stage,
         Bprev[off + j] = w;
         Bbest[off + j] = w;
         ss.blb[off + j] = w;
-        Yi[off + j] = (Ti)w;
+        if (c.yp) {  // plane mode: the planes of w
+            uint16_t hh, mm, ll;
+            split3((float)w, hh, mm, ll);
+            const int64_t pl = (int64_t)c.mpad * c.ldp;
+            c.yp[off + j] = hh;
+            c.yp[pl + off + j] = mm;
+            if (c.nb > 2) c.yp[2 * pl + off + j] = ll;
+        } else {
+            Yi[off + j] = (Ti)w;
+        }
         if (an.bc) {  // anchored at beta_c = 0 (D = w)
             an.bc[off + j] = 0.0;
             an.gc[off + j] = an.g0[j];
@@ -1810,6 +2095,13 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
     g.n = c.n; g.loss = c.loss; g.y = y;
     g.sc = an.sc;
     const int tn = c.mact / GEMM_BN;
+    if (c.yp) {  // plane mode: stream the tiled X against the planes of Y
+        g.A = c.xtile; g.lda = c.nkb_x; g.rows_a = c.npad;
+        g.B = c.yp; g.b_plane = (int64_t)c.mpad * c.ldp;
+        g.C = c.rp; g.c_plane = (int64_t)c.mpad * c.npad; g.rows_c = c.npad;
+        (void)launch_gemm_stream(s, an.sc ? EPI_DLOSS_ANCHOR : EPI_DLOSS, g, c.npad, tn, 1, 64, c.nb);
+        return;
+    }
     if (an.sc && !iter_f64) {
         if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1);
         else gemm_bf16<EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1);
@@ -1830,6 +2122,12 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
     g.split_stride = (int64_t)c.mpad * c.ldp;
     g.k_len = c.npad; g.k_chunk = gchunk; g.rows_valid = c.ldp;
     const int tn = c.mact / GEMM_BN;
+    if (c.yp) {  // plane mode: stream the tiled X^T against the planes of R
+        g.A = c.xttile; g.lda = c.nkb_xt; g.rows_a = c.pm;
+        g.B = c.rp; g.b_plane = (int64_t)c.mpad * c.npad;
+        (void)launch_gemm_stream(s, EPI_STORE, g, c.pm, tn, gsplit, 64, c.nb);
+        return;
+    }
     if (iter_f64) {
         if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
         else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
