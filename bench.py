@@ -120,14 +120,41 @@ def bnb_leg(K, W, torch, args):
     t_tune = time.perf_counter() - t
     log(f"autotune {t_tune:.1f}s -> width {tune['batch_width']} period {tune['cert_period']}; "
         f"rates {np.round(tune['rates'], 1).tolist()}")
-    h = K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
-                         batch_width=tune["batch_width"], cert_period=tune["cert_period"])
-    torch.cuda.synchronize()
-    out = K.branch_and_bound(h, time_limit_s=args.bnb_time_limit, log_every_s=10.0)
-    K.destroy_problem(h)
-    log(f"bnb: {out['seconds']:.2f}s nodes {out['nodes']} gap {out['rel_gap']:.3g}")
+    runs = {}
+    for it in ("f64", "anchored"):
+        h = K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
+                             batch_width=tune["batch_width"], cert_period=tune["cert_period"],
+                             iter_dtype=it)
+        torch.cuda.synchronize()
+        runs[it] = K.branch_and_bound(h, time_limit_s=args.bnb_time_limit, log_every_s=10.0)
+        K.destroy_problem(h)
+        o = runs[it]
+        log(f"bnb ({it} products): {o['seconds']:.2f}s nodes {o['nodes']} gap {o['rel_gap']:.3g}")
+    auto = "anchored"  # the precision AUTO resolves to for the squared loss
+    out = runs[auto]
+    # the incumbent reproduced by the oracle: v(S) of the returned support
+    # solved independently in float64, and the objective at the returned beta
+    import oracle
+    P = oracle.Problem.from_instance(inst)
+    S = [int(j) for j in out["support"]]
+    st = np.full(inst.p, -1, np.int8)
+    st[S] = 1
+    v_o, _ = P.support_value(S)
+    phi_o = P.primal(st, out["beta"])
+    err = {"objective_vs_oracle_support_value": abs(out["objective"] - v_o) / abs(v_o),
+           "objective_vs_oracle_at_beta": abs(out["objective"] - phi_o) / abs(phi_o),
+           "measure": "relative; the oracle solves v(S) of the returned support to 1e-13 "
+                      "and evaluates the objective at the returned coefficients"}
+    log(f"bnb: oracle reproduction {err}")
     return {"workload": "squared_10000x1000_bf16_rho0.9_k10", "seconds": round(out["seconds"], 3),
-            "status": ["zero gap", "time limit", "node limit"][out["status"]],
+            "iteration_products": auto,
+            "by_iteration_products": {
+                it: {"seconds": round(o["seconds"], 3), "nodes": int(o["nodes"]),
+                     "rel_gap": o["rel_gap"], "status": int(o["status"]),
+                     "support": [int(v) for v in o["support"]], "objective": o["objective"]}
+                for it, o in runs.items()},
+            "error_vs_oracle": err,
+            "status": ["zero gap", "time limit", "node limit", "gap above tolerance"][out["status"]],
             "rel_gap": out["rel_gap"], "objective": out["objective"],
             "lower_bound": out["lower_bound"], "nodes": int(out["nodes"]),
             "support": [int(v) for v in out["support"]],
@@ -180,9 +207,10 @@ def large_leg(K, W, torch, args):
     dt = time.perf_counter() - t
     rate = len(res) / dt
     log(f"large: timed batch done in {dt:.2f}s")
-    # kernel-timed pass on 64 further nodes
+    # kernel-timed pass: a second batch of the timed width (its launches
+    # narrow as nodes finish, as in the timed batch)
     K.kernel_stats(h, 1)
-    K.bound_nodes(h, nodes[8 + args.large_batch:], rel_tol=1e-6)
+    K.bound_nodes(h, W.random_nodes(d["p"], args.large_batch, 7, 500, seed=3001), rel_tol=1e-6)
     ks = K.kernel_stats(h, 0)
     rash = None
     if args.large_rashomon > 0:
@@ -199,9 +227,11 @@ def large_leg(K, W, torch, args):
                 "values": [v for _, v, _ in ob["rashomon"][:10]]}
         log(f"large: rashomon {rash}")
     K.destroy_problem(h)
-    n = d["n"]
+    n, p = d["n"], d["p"]
     iters = [r["iterations"] for r in res]
-    useful = ks["useful_cols"] / max(1, ks["launches"]["fwd_xy"])
+    nl_it = max(1, ks["launches"]["fwd_xy"])
+    useful = ks["useful_cols"] / nl_it
+    m_run = ks["running_cols"] / nl_it  # nodes per iteration launch
     kern = {}
     for name in ("fwd_xy", "bwd_xtr", "prox", "cert_xb", "cert_xtz", "cert_finish"):
         nl = ks["launches"][name]
@@ -212,7 +242,15 @@ def large_leg(K, W, torch, args):
                 tf = 2.0 * n * useful / (us * 1e-6) / 1e12
                 pk = PEAK_TFLOPS["bf16"] if name in ("fwd_xy", "bwd_xtr") else PEAK_TFLOPS["f64"]
                 kern[name]["alg_tflops"] = round(tf, 2)
-                kern[name]["frac_of_peak"] = round(tf / pk, 4)
+                kern[name]["frac_of_mfma_peak"] = round(tf / pk, 4)
+            if name in ("fwd_xy", "bwd_xtr"):
+                # HBM roofline: X (bfloat16) read once, and per running node
+                # its length-n column of R (float32 values) and length-p
+                # iterate / gradient column
+                by = 2.0 * n * p + 4.0 * (n + p) * m_run
+                kern[name]["alg_bytes_per_launch"] = round(by)
+                kern[name]["hbm_gbs"] = round(by / (us * 1e-6) / 1e9, 1)
+                kern[name]["frac_of_hbm_peak"] = round(by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     log(f"large: {len(res)} nodes in {dt:.2f}s -> {rate:.1f} node bounds/s; kernels {kern}")
     return {"workload": "logistic_100000x5000_bf16_rho0.7_k15", "value": round(rate, 2),
             "unit": "node bounds/s", "nodes": len(res), "batch_width": args.large_batch,
@@ -220,8 +258,10 @@ def large_leg(K, W, torch, args):
             "iterations": {"mean": round(float(np.mean(iters)), 1), "max": int(np.max(iters))},
             "not_converged": int(sum(r["status"] != K.CONVERGED for r in res)),
             "max_rel_gap": float(max(r["rel_gap"] for r in res)),
-            "iteration_products": "bfloat16 MFMA (three-term split of the float32 operand) of "
-                                  "the change since each node's last float64 certificate",
+            "iteration_products": "bfloat16 MFMA streaming a tiled copy of X against two "
+                                  "bfloat16 planes of the change since each node's last "
+                                  "float64 certificate",
+            "kernel_pass": {"nodes": args.large_batch, "nodes_per_launch": round(m_run, 1)},
             "kernels": kern, "rashomon_bnb": rash}
 
 
@@ -412,7 +452,7 @@ def run_stream(K, h, preps, out, window):
         for i in range(cnt):
             r = out[i]
             b = r.tag // size - base
-            res.append((r.tag, r.status, r.iterations, r.rel_gap))
+            res.append((r.tag, r.status, r.iterations, r.rel_gap, r.lower_bound))
             lat.append(now - t_sub[b])
             left[b] -= 1
             if left[b] == 0 and nxt < nb:
@@ -442,6 +482,8 @@ def main():
                     help="oracle sample size for the CPU baseline (0 = skip)")
     ap.add_argument("--comparator-nodes", type=int, default=32,
                     help="nodes bounded one at a time at batch width 1 (0 = skip)")
+    ap.add_argument("--oracle-nodes", type=int, default=16,
+                    help="timed nodes checked against the float64 oracle (0 = skip)")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--bnb", type=int, default=1, help="run the time-to-zero-gap leg")
     ap.add_argument("--bnb-time-limit", type=float, default=150.0)
@@ -636,6 +678,31 @@ def main():
                 "sample": f"first {len(par)} nodes of batch seed 1000, {tpar:.1f}s"}
             log(f"cpu oracle node-parallel: {cpu['node_parallel']}")
 
+    # error of the timed bounds against the float64 oracle: every 16th node of
+    # the first timed batch, the oracle solved to a 1e-10 gap
+    err = None
+    if args.oracle_nodes > 0:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        P = oracle.Problem.from_instance(inst)
+        P.lipschitz()
+        first = args.warmup * args.batch
+        lb_of = {r[0]: r[4] for r in results}
+        idx = list(range(0, args.batch, max(1, args.batch // args.oracle_nodes)))[:args.oracle_nodes]
+        nodes_s = [batches[args.warmup][i] for i in idx]
+        with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+            refs = list(ex.map(lambda nd: P.node_bound(W.node_state(p, nd), tol=1e-10, max_iter=100000),
+                               nodes_s))
+        rel = [abs(lb_of[first + i] - rf["lb"]) / abs(rf["lb"]) for i, rf in zip(idx, refs)]
+        valid = all(lb_of[first + i] <= rf["phi"] * (1 + 1e-12) for i, rf in zip(idx, refs))
+        err = {"nodes": len(idx), "max_rel": max(rel), "mean_rel": float(np.mean(rel)),
+               "bounds_valid": bool(valid),
+               "measure": "|LB_gpu - LB_oracle| / |LB_oracle| over every "
+                          f"{args.batch // len(idx)}th node of the first timed batch; the oracle "
+                          "solves each node to a 1e-10 gap in float64; valid: LB_gpu <= the "
+                          "oracle's primal value"}
+        log(f"error vs oracle: {err}")
+
     ttz = bnb_leg(K, W, torch, args) if args.bnb else None
     serving = serving_leg(K, W, torch, args) if args.serving else None
     large = large_leg(K, W, torch, args) if args.large else None
@@ -671,6 +738,7 @@ def main():
         "max_rel_gap": float(np.max(gaps)),
         "useful_fraction": round(useful_per_launch / max(1.0, slots_per_launch * p), 4),
         "roofline": roofline,
+        "error_vs_oracle": err,
         "kernels": kern,
         "cpu_baseline": cpu,
         "comparator": comparator,

@@ -60,12 +60,13 @@ extern "C" {
 #define KBNB_DTYPE_BF16 2 /* uint16 bfloat16 bit patterns */
 
 /* precision of the iteration's products (certificates are float64 always) */
-#define KBNB_ITER_AUTO 0 /* F64 for float64 X or the squared loss; else ANCHORED when
+#define KBNB_ITER_AUTO 0 /* F64 for float64 X; else ANCHORED for the squared loss or
                             n > 10000, F32 otherwise.  Plain float32 iterations can stall
                             near a 1e-6 relative gap: with the squared loss the natural
                             dual point zeta = -l'(X beta) is first-order sensitive to
                             rounding in the iterate, and float32 gradient sums over many
-                            rows lose the accuracy the gap needs. */
+                            rows lose the accuracy the gap needs; the anchored iteration
+                            does not have that floor. */
 #define KBNB_ITER_F32 1  /* float32 (bfloat16 MFMA for bfloat16 X); needs F32 or BF16 X */
 #define KBNB_ITER_F64 2  /* float64 products on any X */
 #define KBNB_ITER_ANCHORED 3 /* float32 (bfloat16 MFMA for bfloat16 X) products of the change

@@ -965,10 +965,13 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->n = d->n; P->p = d->p; P->k = d->k; P->loss = d->loss;
     P->lambda2 = d->lambda2; P->M = d->M;
     P->xtype = d->x_dtype;
-    P->iter_f64 = (d->x_dtype == KBNB_DTYPE_F64) || (d->iter_dtype == KBNB_ITER_F64) ||
-                  (d->iter_dtype == KBNB_ITER_AUTO && d->loss == KBNB_LOSS_SQUARED);
+    // AUTO: float64 products for float64 X; otherwise anchored for the
+    // squared loss (plain float32 stalls near a 1e-6 gap there) and for tall
+    // instances, plain float32 for the rest
+    P->iter_f64 = (d->x_dtype == KBNB_DTYPE_F64) || (d->iter_dtype == KBNB_ITER_F64);
     P->anchored = !P->iter_f64 && (d->iter_dtype == KBNB_ITER_ANCHORED ||
-                                   (d->iter_dtype == KBNB_ITER_AUTO && d->n > 10000));
+                                   (d->iter_dtype == KBNB_ITER_AUTO &&
+                                    (d->loss == KBNB_LOSS_SQUARED || d->n > 10000)));
     P->ti_bytes = P->iter_f64 ? 8 : 4;
     P->ldp = (int)round_up(P->p, 16);
     while (P->pp < P->p) P->pp *= 2;

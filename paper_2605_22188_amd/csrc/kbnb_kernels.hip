@@ -320,12 +320,10 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     const int row0 = tm * BM, col0 = tn * BN;
     const int kbeg = split * g.k_chunk;
     const int kend = max(kbeg, min(g.k_len, kbeg + g.k_chunk));  // an empty split stores zeros
-    if (g.col_status) {
-        // nodes that finished keep their columns, but a tile whose 64 nodes
-        // are all finished (or empty) has nothing to compute
-        const int run = (tid < BN) ? (g.col_status[col0 + tid] == SLOT_RUNNING) : 0;
-        if (!__syncthreads_or(run)) return;
-    }
+    // nodes that finished keep their columns, but a tile whose 64 nodes are
+    // all finished (or empty) has nothing to compute; the check is read
+    // beside the first stage's loads, not before them
+    const int run = (g.col_status && tid < BN) ? (g.col_status[col0 + tid] == SLOT_RUNNING) : (g.col_status ? 0 : 1);
     const TA *A = reinterpret_cast<const TA *>(g.A);
     const TB *Bg = reinterpret_cast<const TB *>(g.B);
 
@@ -412,10 +410,9 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
     const int nfull = (kend - kbeg) / BK;
     const int ntail = ((kend - kbeg) % BK) / 16;
     const int nstage = nfull + (ntail > 0 ? 1 : 0);
-    if (nstage > 0) {
-        load_stage(kbeg);
-        store_stage(0);
-    }
+    if (nstage > 0) load_stage(kbeg);
+    if (!__syncthreads_or(run)) return;
+    if (nstage > 0) store_stage(0);
     __syncthreads();
     int buf = 0;
     for (int st = 0; st < nstage; ++st) {
@@ -494,16 +491,10 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmArgs g)
 }
 
 // ---------------------------------------------------------------------------
-// bfloat16 MFMA contraction for bfloat16-stored X in the float32 iteration:
-// C[col][row] = sum_k A[row][k] * Bm[col][k], A bfloat16 (exact instance
-// values), Bm float32.  Each Bm value b is split into three bfloat16 terms,
-// hi = bf16(b), mid = bf16(b - hi), lo = bf16(b - hi - mid) (round to nearest
-// even; both differences are exact in float32), so hi + mid + lo carries
-// b's 24-bit significand up to the last bit and three 16x16x32 bf16 MFMAs
-// into a float32 accumulator give float32-level accuracy at about 5x the
-// float32 MFMA rate.  Tile BM x 64, k stage 64 (two MFMA k-steps of 32);
-// lane l holds A row l % 16 / Bm column l % 16 at k = 8 (l / 16) .. + 7,
-// one 16-byte LDS read per operand.  Epilogues EPI_DLOSS / EPI_STORE.
+// bfloat16 helpers: round to nearest even, and the three-term split of a
+// float32 value b into bfloat16 hi = bf16(b), mid = bf16(b - hi),
+// lo = bf16(b - hi - mid) (both differences are exact in float32), whose sum
+// carries b's 24-bit significand.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -524,138 +515,6 @@ __device__ __forceinline__ void split3(float b, uint16_t &h, uint16_t &m, uint16
     l = (uint16_t)bf16_rne_bits(r2);
 }
 
-template <int MODE, int BM>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g)
-{
-    constexpr int BN = GEMM_BN;
-    constexpr int FI = BM / 32;
-    constexpr int BK = 64;
-    constexpr int LS = BK + 8;              // LDS row stride (bf16 elements, 144 bytes)
-    constexpr int LPA = (BM * BK / 8) / 256;  // 8-element A groups per thread per stage
-    constexpr int LPB = (BN * BK / 4) / 256;  // 4-element Bm groups per thread per stage
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LS];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][3][BN * LS];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int lr = lane & 15, lg = lane >> 4;
-    int tm, tn, split;
-    if (!map_tile(g, tm, tn, split)) return;
-    const int row0 = tm * BM, col0 = tn * BN;
-    const int kbeg = split * g.k_chunk;
-    const int kend = max(kbeg, min(g.k_len, kbeg + g.k_chunk));
-    if (g.col_status) {
-        const int run = (tid < BN) ? (g.col_status[col0 + tid] == SLOT_RUNNING) : 0;
-        if (!__syncthreads_or(run)) return;
-    }
-    const uint16_t *A = reinterpret_cast<const uint16_t *>(g.A);
-    const float *Bg = reinterpret_cast<const float *>(g.B);
-
-    f32x4 acc[FI][2];
-#pragma unroll
-    for (int i = 0; i < FI; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
-    double yv[FI][4];
-    if constexpr (MODE != EPI_STORE) {
-#pragma unroll
-        for (int i = 0; i < FI; ++i) ld4(g.y + row0 + wm * (BM / 2) + i * 16 + lg * 4, yv[i]);
-    }
-
-    // staging registers; a group at or past kend re-reads k = kbeg (valid
-    // memory) and is zeroed at the LDS store
-    uint4 ra[LPA];
-    float4 rb[LPB];
-    bool rka[LPA], rkb[LPB];
-    auto load_stage = [&](int k0) {
-#pragma unroll
-        for (int v = 0; v < LPA; ++v) {
-            const int x = tid + 256 * v;
-            const int r = x / (BK / 8), kq = 8 * (x % (BK / 8));
-            rka[v] = k0 + kq < kend;
-            ra[v] = *reinterpret_cast<const uint4 *>(A + (int64_t)(row0 + r) * g.lda + (rka[v] ? k0 + kq : kbeg));
-        }
-#pragma unroll
-        for (int v = 0; v < LPB; ++v) {
-            const int x = tid + 256 * v;
-            const int r = x / (BK / 4), kq = 4 * (x % (BK / 4));
-            rkb[v] = k0 + kq < kend;
-            rb[v] = *reinterpret_cast<const float4 *>(Bg + (int64_t)(col0 + r) * g.ldb + (rkb[v] ? k0 + kq : kbeg));
-        }
-    };
-    auto store_stage = [&](int bufi) {
-#pragma unroll
-        for (int v = 0; v < LPA; ++v) {
-            const int x = tid + 256 * v;
-            const int r = x / (BK / 8), kq = 8 * (x % (BK / 8));
-            *reinterpret_cast<uint4 *>(&As[bufi][r * LS + kq]) = rka[v] ? ra[v] : make_uint4(0, 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < LPB; ++v) {
-            const int x = tid + 256 * v;
-            const int r = x / (BK / 4), kq = 4 * (x % (BK / 4));
-            const float bv[4] = {rb[v].x, rb[v].y, rb[v].z, rb[v].w};
-            uint16_t h[4], m[4], l[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                split3(rkb[v] ? bv[e] : 0.0f, h[e], m[e], l[e]);
-            }
-            const int o = r * LS + kq;
-            *reinterpret_cast<uint2 *>(&Bs[bufi][0][o]) =
-                make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
-            *reinterpret_cast<uint2 *>(&Bs[bufi][1][o]) =
-                make_uint2(m[0] | ((uint32_t)m[1] << 16), m[2] | ((uint32_t)m[3] << 16));
-            *reinterpret_cast<uint2 *>(&Bs[bufi][2][o]) =
-                make_uint2(l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16));
-        }
-    };
-    // MFMA k-step h (k = 32 h .. 32 h + 31 of the stage)
-    auto compute = [&](int bi, int h) {
-        bf16x8 av[FI], bv[3][2];
-#pragma unroll
-        for (int f = 0; f < FI; ++f)
-            av[f] = *reinterpret_cast<const bf16x8 *>(&As[bi][(wm * (BM / 2) + f * 16 + lr) * LS + 32 * h + 8 * lg]);
-#pragma unroll
-        for (int t = 0; t < 3; ++t)
-#pragma unroll
-            for (int f = 0; f < 2; ++f)
-                bv[t][f] = *reinterpret_cast<const bf16x8 *>(&Bs[bi][t][(wn * 32 + f * 16 + lr) * LS + 32 * h + 8 * lg]);
-#pragma unroll
-        for (int t = 2; t >= 0; --t)  // small terms first
-#pragma unroll
-            for (int i = 0; i < FI; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[t][j], acc[i][j], 0, 0, 0);
-    };
-
-    // full stages, then a partial last stage of 1 or 2 k-steps (a k-step
-    // whose second half lies past kend reads zeros there)
-    const int nfull = (kend - kbeg) / BK;
-    const int ntail = (((kend - kbeg) % BK) + 31) / 32;
-    const int nstage = nfull + (ntail > 0 ? 1 : 0);
-    if (nstage > 0) {
-        load_stage(kbeg);
-        store_stage(0);
-    }
-    __syncthreads();
-    int buf = 0;
-    for (int st = 0; st < nstage; ++st) {
-        const bool more = st + 1 < nstage;
-        if (more) load_stage(kbeg + (st + 1) * BK);
-        if (st < nfull) {
-            compute(buf, 0);
-            compute(buf, 1);
-        } else {
-            for (int h = 0; h < ntail; ++h) compute(buf, h);
-        }
-        if (more) store_stage(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-    }
-    epi_store<float, MODE, FI>(g, acc, yv, row0, col0, wm, wn, lg, lr, split);
-}
 
 // ---------------------------------------------------------------------------
 // bfloat16 planes.  A float32 value v is stored as planes v1 = bf16(v),
@@ -707,7 +566,7 @@ __global__ __launch_bounds__(256) void k_gemm_stream(GemmArgs g)
     constexpr int LSB = SK + 8;                 // LDS row stride (bf16): 272 bytes
     constexpr int CPR = SK / 8;                 // 16-byte chunks per B row and super-step
     constexpr int LPB = (BN * CPR) / 256;       // B chunks per thread and plane (4)
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[NB][BN * LSB];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][NB][BN * LSB];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -742,14 +601,19 @@ __global__ __launch_bounds__(256) void k_gemm_stream(GemmArgs g)
 #pragma unroll
     for (int f = 0; f < FI; ++f)
         pa[f] = A + (int64_t)min(wrow / 16 + f, nrb - 1) * g.lda * 2048 + (int64_t)lane * 8;
-    uint4 ra0[FI][4], ra1[FI][4], rb0[NB][LPB], rb1[NB][LPB];
-    auto load = [&](int k0, uint4 (&ra)[FI][4], uint4 (&rb)[NB][LPB]) {
+    // A: two register sets (the super-step being contracted and the next);
+    // B: one register set, loaded two super-steps ahead and staged into the
+    // LDS buffer of the next super-step while the current one is contracted
+    uint4 ra0[FI][4], ra1[FI][4], rb[NB][LPB];
+    auto load_a = [&](int k0, uint4 (&ra)[FI][4]) {
         const int64_t kb = (int64_t)(k0 / 128) * 2048;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
 #pragma unroll
             for (int f = 0; f < FI; ++f) ra[f][q] = *reinterpret_cast<const uint4 *>(pa[f] + kb + 512 * q);
         }
+    };
+    auto load_b = [&](int k0) {
 #pragma unroll
         for (int v = 0; v < LPB; ++v) {
             const int x = tid + 256 * v;
@@ -759,7 +623,7 @@ __global__ __launch_bounds__(256) void k_gemm_stream(GemmArgs g)
             for (int pb = 0; pb < NB; ++pb) rb[pb][v] = *reinterpret_cast<const uint4 *>(Bg + pb * g.b_plane + o);
         }
     };
-    auto stage_b = [&](const uint4 (&rb)[NB][LPB], int k0) {
+    auto stage_b = [&](int bi, int k0) {
 #pragma unroll
         for (int v = 0; v < LPB; ++v) {
             const int x = tid + 256 * v;
@@ -767,16 +631,16 @@ __global__ __launch_bounds__(256) void k_gemm_stream(GemmArgs g)
             const bool ok = k0 + kq < kend;
 #pragma unroll
             for (int pb = 0; pb < NB; ++pb)
-                *reinterpret_cast<uint4 *>(&Bs[pb][cl * LSB + kq]) = ok ? rb[pb][v] : make_uint4(0, 0, 0, 0);
+                *reinterpret_cast<uint4 *>(&Bs[bi][pb][cl * LSB + kq]) = ok ? rb[pb][v] : make_uint4(0, 0, 0, 0);
         }
     };
     // B operands of MFMA k-step h, read from LDS one k-step ahead of their use
-    auto read_b = [&](int h, bf16x8 (&bv)[NB][FJ]) {
+    auto read_b = [&](int bi, int h, bf16x8 (&bv)[NB][FJ]) {
 #pragma unroll
         for (int pb = 0; pb < NB; ++pb)
 #pragma unroll
             for (int j = 0; j < FJ; ++j)
-                bv[pb][j] = *reinterpret_cast<const bf16x8 *>(&Bs[pb][(16 * j + lr) * LSB + 32 * lg + 8 * h]);
+                bv[pb][j] = *reinterpret_cast<const bf16x8 *>(&Bs[bi][pb][(16 * j + lr) * LSB + 32 * lg + 8 * h]);
     };
     auto mfmas = [&](const uint4 (&ra)[FI][4], int h, const bf16x8 (&bv)[NB][FJ]) {
 #pragma unroll
@@ -789,34 +653,44 @@ __global__ __launch_bounds__(256) void k_gemm_stream(GemmArgs g)
                     acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[t][j], acc[f][j], 0, 0, 0);
             }
     };
-    auto compute = [&](const uint4 (&ra)[FI][4]) {
+    auto compute = [&](const uint4 (&ra)[FI][4], int bi) {
         bf16x8 b0[NB][FJ], b1[NB][FJ];
-        read_b(0, b0);
-        read_b(1, b1);
+        read_b(bi, 0, b0);
+        read_b(bi, 1, b1);
         mfmas(ra, 0, b0);
-        read_b(2, b0);
+        read_b(bi, 2, b0);
         mfmas(ra, 1, b1);
-        read_b(3, b1);
+        read_b(bi, 3, b1);
         mfmas(ra, 2, b0);
         mfmas(ra, 3, b1);
     };
+    // super-step s contracts LDS buffer s & 1
+    auto step = [&](int s, const uint4 (&ra)[FI][4], uint4 (&ra_next)[FI][4], int nss) {
+        if (s + 1 < nss) load_a(kbeg + (s + 1) * SK, ra_next);
+        compute(ra, s & 1);
+        if (s + 1 < nss) {
+            stage_b((s + 1) & 1, kbeg + (s + 1) * SK);
+            if (s + 2 < nss) load_b(kbeg + (s + 2) * SK);
+        }
+        __syncthreads();
+    };
 
     const int nss = (kend - kbeg + SK - 1) / SK;
-    if (nss > 0) load(kbeg, ra0, rb0);
+    if (nss > 0) {
+        load_a(kbeg, ra0);
+        load_b(kbeg);
+    }
     if (!__syncthreads_or(run)) return;  // every node of the tile has finished
-    // two super-steps per trip, so the register sets are fixed at compile time
+    if (nss > 0) {
+        stage_b(0, kbeg);
+        if (nss > 1) load_b(kbeg + SK);
+    }
+    __syncthreads();
+    // two super-steps per trip, so the A register sets are fixed at compile time
     for (int s = 0; s < nss; s += 2) {
-        __syncthreads();
-        stage_b(rb0, kbeg + s * SK);
-        __syncthreads();
-        if (s + 1 < nss) load(kbeg + (s + 1) * SK, ra1, rb1);
-        compute(ra0);
+        step(s, ra0, ra1, nss);
         if (s + 1 >= nss) break;
-        __syncthreads();
-        stage_b(rb1, kbeg + (s + 1) * SK);
-        __syncthreads();
-        if (s + 2 < nss) load(kbeg + (s + 2) * SK, ra0, rb0);
-        compute(ra1);
+        step(s + 1, ra1, ra0, nss);
     }
 
     // ---- epilogue: acc[f][j][r] holds C at row = wrow + 16 f + 4 lg + r,
@@ -1293,7 +1167,7 @@ template <int PP, int W>
 __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / (64 * W)],
                             const int (&sv)[PP / (64 * W)], int p, int kbar, double eta,
                             double lambda2, double M, double (&bet)[PP / (64 * W)],
-                            int32_t *perm, bool have_prev)
+                            int32_t *perm, bool have_prev, const int (&pv)[PP / (64 * W)])
 {
     constexpr int E = PP / (64 * W);
     constexpr int T = 64 * W;
@@ -1317,14 +1191,9 @@ __device__ void masked_prox(ProxLds<PP> &L, const double (&u)[PP / (64 * W)],
     bool sorted = false;
     if (perm && have_prev) {
         // keys by coordinate into LDS, then gathered in the previous order
+        // (pv: this thread's entries of the previous order, loaded by the caller)
 #pragma unroll
         for (int e = 0; e < E; ++e) L.key[j0 + e] = key[e];
-        int pv[E];
-#pragma unroll
-        for (int q = 0; q < E / 4; ++q) {
-            const int4 v = *reinterpret_cast<const int4 *>(perm + j0 + 4 * q);
-            pv[4 * q] = v.x; pv[4 * q + 1] = v.y; pv[4 * q + 2] = v.z; pv[4 * q + 3] = v.w;
-        }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -1503,7 +1372,18 @@ __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp,
     const int64_t off = (int64_t)b * c.ldp;
     const int64_t gstride = (int64_t)c.mpad * c.ldp;
     const int j0 = t * E;
+    // every load of the step is issued here, before any result is needed
     const double th = ss.theta[b];
+    const double tm = ss.tmom[b];
+    const int itn = ss.iter[b];
+    const int kbar = ss.kbar[b];
+    int32_t *perm = ss.perm + (int64_t)b * c.pp;
+    int pv[E];
+#pragma unroll
+    for (int q = 0; q < E / 4; ++q) {
+        const int4 v = *reinterpret_cast<const int4 *>(perm + j0 + 4 * q);
+        pv[4 * q] = v.x; pv[4 * q + 1] = v.y; pv[4 * q + 2] = v.z; pv[4 * q + 3] = v.w;
+    }
 
     double g[E], bo[E], bp[E], u[E], y[E], bet[E], bcv[E];
     int sv[E];
@@ -1537,14 +1417,12 @@ __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp,
         y[e] = bo[e] + th * (bo[e] - bp[e]);
         u[e] = y[e] - c.eta * g[e];
     }
-    masked_prox<PP, W>(L, u, sv, c.p, ss.kbar[b], c.eta, c.lambda2, c.M, bet,
-                       ss.perm + (int64_t)b * c.pp, ss.iter[b] > 0);
+    masked_prox<PP, W>(L, u, sv, c.p, kbar, c.eta, c.lambda2, c.M, bet, perm, itn > 0, pv);
     // restart test (y - beta+)^T (beta+ - beta) > 0, then momentum
     double dot = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) dot += (y[e] - bet[e]) * (bet[e] - bo[e]);
     dot = blk_sum<W>(dot);
-    const double tm = ss.tmom[b];
     double tn, thn;
     if (dot > 0.0) {
         tn = 1.0;
@@ -1569,7 +1447,7 @@ __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp,
     if (t == 0) {
         ss.tmom[b] = tn;
         ss.theta[b] = thn;
-        ss.iter[b] = ss.iter[b] + 1;
+        ss.iter[b] = itn + 1;
     }
 }
 
@@ -1601,7 +1479,10 @@ __global__ __launch_bounds__(64 * W) void k_prox_batch(const double *__restrict_
             sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
         }
     }
-    masked_prox<PP, W>(L, u, sv, c.p, kbar[b], eta, c.lambda2, c.M, bet, nullptr, false);
+    int pv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) pv[e] = 0;  // no previous order
+    masked_prox<PP, W>(L, u, sv, c.p, kbar[b], eta, c.lambda2, c.M, bet, nullptr, false, pv);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int j = j0 + 4 * q;
@@ -2067,22 +1948,6 @@ static void gemm(hipStream_t s, GemmArgs g, int rows, int tiles_n, int splits)
     else KBNB_LAUNCH((k_gemm_tn<TA, TB, TC, MODE, 64>), grid, dim3(256), 0, s, g);
 }
 
-template <int MODE>
-static void gemm_bf16(hipStream_t s, GemmArgs g, int rows, int tiles_n, int splits)
-{
-    g.tiles_n = tiles_n;
-    g.nsplit = splits;
-    const bool small = (int64_t)(rows / 64) * tiles_n * splits < 512;
-    const int bm = small ? 32 : 64;
-    g.tiles_m = rows / bm;
-    int nblocks;
-    if (splits > 1) nblocks = 8 * g.tiles_m * tiles_n * ((splits + 7) / 8);
-    else if (g.tiles_m >= 8) nblocks = (g.tiles_m + 7) / 8 * 8 * tiles_n;
-    else nblocks = g.tiles_m * tiles_n;
-    dim3 grid(nblocks, 1);
-    if (small) KBNB_LAUNCH((k_gemm_bf16<MODE, 32>), grid, dim3(256), 0, s, g);
-    else KBNB_LAUNCH((k_gemm_bf16<MODE, 64>), grid, dim3(256), 0, s, g);
-}
 
 void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, const void *Yi,
                       void *R, const double *y, const Consts &c, const int32_t *status,
@@ -2102,15 +1967,16 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
         (void)launch_gemm_stream(s, an.sc ? EPI_DLOSS_ANCHOR : EPI_DLOSS, g, c.npad, tn, 1, 64, c.nb);
         return;
     }
+    // outside plane mode a float32 iteration has float32 X
     if (an.sc && !iter_f64) {
-        if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1);
-        else gemm_bf16<EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1);
+        gemm<float, float, float, EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1);
     } else if (iter_f64) {
         if (xtype == XT_F64) gemm<double, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
         else if (xtype == XT_F32) gemm<float, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
         else gemm<uint16_t, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
-    } else if (xtype == XT_F32) gemm<float, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
-    else gemm_bf16<EPI_DLOSS>(s, g, c.npad, tn, 1);
+    } else {
+        gemm<float, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
+    }
 }
 
 void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const void *R,
@@ -2132,8 +1998,9 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
         if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
         else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
         else gemm<uint16_t, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
-    } else if (xtype == XT_F32) gemm<float, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
-    else gemm_bf16<EPI_STORE>(s, g, c.pm, tn, gsplit);
+    } else {
+        gemm<float, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
+    }
 }
 
 void launch_cert_fwd(hipStream_t s, int xtype, const void *X, const double *B, double *Z,

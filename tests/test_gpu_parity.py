@@ -226,17 +226,20 @@ def _bound_parity(inst, nodes, batch_width, cert_period, warm=None, sample=None,
                                             (W.SQUARED, "f32", 0), (W.LOGISTIC, "f32", 0),
                                             (W.SQUARED, "bf16", 0), (W.LOGISTIC, "bf16", 0),
                                             (W.LOGISTIC, "f32", "f64"),
+                                            (W.SQUARED, "f32", "f64"),
+                                            (W.SQUARED, "bf16", "f64"),
                                             (W.SQUARED, "f32", "anchored"),
                                             (W.LOGISTIC, "f32", "anchored"),
                                             (W.SQUARED, "bf16", "anchored"),
                                             (W.LOGISTIC, "bf16", "anchored")])
 def test_node_bounds_small_all_nodes(loss, dtype, it):
-    """Iteration precision "auto" (0): float64 for the squared loss on any X,
-    float32 for the logistic loss on float32 / bfloat16 X (bfloat16 X: the
-    products run on bfloat16 MFMA with a three-term split of the float32
-    operand).  "f64": float64 iteration forced on float32 X.  "anchored":
+    """Iteration precision "auto" (0): float64 for float64 X; anchored for the
+    squared loss on float32 / bfloat16 X; float32 for the logistic loss on
+    float32 / bfloat16 X (bfloat16 X: the products stream a tiled copy of X
+    on bfloat16 MFMA against three bfloat16 planes of the float32 operand).
+    "f64": float64 iteration forced on float32 / bfloat16 X.  "anchored":
     float32 / bfloat16 products of the change since each node's last float64
-    certificate."""
+    certificate (two planes on bfloat16 X)."""
     announce(f"node bounds 700x50 loss={loss} X {dtype} iteration {it}, 100 nodes on 64 slots")
     inst = W.small_instance(700, 50, 6, loss, seed=5 + loss, rho=0.6, dtype=dtype)
     nodes = W.random_nodes(50, 100, 3, 15, seed=77)

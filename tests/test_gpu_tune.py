@@ -43,7 +43,9 @@ def test_autotune_with_given_nodes_and_budget():
 def test_iteration_precision_resolution():
     print("[gpu-test] iteration precision: auto resolution", flush=True)
     cases = [((300, 20, W.SQUARED, "f64"), 0, "f64"),
-             ((300, 20, W.SQUARED, "f32"), 0, "f64"),
+             ((300, 20, W.SQUARED, "f32"), 0, "anchored"),
+             ((300, 20, W.SQUARED, "bf16"), 0, "anchored"),
+             ((300, 20, W.SQUARED, "f32"), "f64", "f64"),
              ((300, 20, W.LOGISTIC, "f32"), 0, "f32"),
              ((300, 20, W.LOGISTIC, "bf16"), 0, "f32"),
              ((12000, 20, W.LOGISTIC, "f32"), 0, "anchored"),
