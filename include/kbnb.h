@@ -110,6 +110,10 @@ typedef struct {
     int32_t batch_width;       /* node slots; 0 = chosen from the budget (max 1024) */
     int32_t cert_period;       /* iterations between float64 certificates; 0 = 8 */
     int32_t iter_dtype;        /* KBNB_ITER_*: precision of the iteration's products */
+    int32_t admit_timeout_ms;  /* when the process-wide device budget (device_budget) cannot
+                                  hold the problem: how long create_problem waits for other
+                                  problems to release memory before KBNB_E_BUDGET_EXCEEDED
+                                  (0: refuse at once) */
 } kbnb_problem_desc;
 
 typedef struct {
@@ -137,7 +141,28 @@ typedef struct {
     int32_t iterations;
     int32_t branch_index; /* argmax of |beta_j| over free j (lowest index on ties); -1 if none */
     int32_t support_len;  /* |J1| + min(kbar, #free): length of the rounding support */
+    double queue_seconds; /* submit_nodes to admission into a slot (waiting for a free slot) */
+    double solve_seconds; /* admission to the end of the round that finished the node */
 } kbnb_bound_result;
+
+/*
+ * device_budget -- the process-wide budget of device memory for the arenas of
+ * all problems on the current device (App. E.4's memory model applied across
+ * problems): bytes >= 0 sets it (0 = unlimited, the default), bytes < 0 only
+ * reads.  *used (nullable) receives the bytes currently charged.  Each
+ * create_problem charges its arena; destroy_problem releases it.  A problem
+ * with an automatic batch width takes the widest power-of-two width that
+ * fits what is left (its own hbm_budget_bytes still caps it); one that cannot
+ * fit even then, or a fixed width that does not fit, waits up to its
+ * admit_timeout_ms for releases and is then refused with
+ * KBNB_E_BUDGET_EXCEEDED.  Lowering the budget does not evict problems.
+ *
+ * engine_streams -- problems created afterwards on the current device share
+ * `count` streams (assigned round-robin) instead of one stream each (count
+ * 0, the default): their rounds queue on fewer hardware queues.  At most 64.
+ */
+int device_budget(int64_t bytes, int64_t *used);
+int engine_streams(int32_t count);
 
 /*
  * create_problem -- validate the instance, copy X and y to the device in the

@@ -43,7 +43,7 @@ class ProblemDesc(ctypes.Structure):
                 ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p),
                 ("hip_stream", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_uint64),
                 ("batch_width", ctypes.c_int32), ("cert_period", ctypes.c_int32),
-                ("iter_dtype", ctypes.c_int32)]
+                ("iter_dtype", ctypes.c_int32), ("admit_timeout_ms", ctypes.c_int32)]
 
 
 class NodeDesc(ctypes.Structure):
@@ -58,7 +58,8 @@ class BoundResult(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("lower_bound", ctypes.c_double),
                 ("primal_value", ctypes.c_double), ("rel_gap", ctypes.c_double),
                 ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
-                ("branch_index", ctypes.c_int32), ("support_len", ctypes.c_int32)]
+                ("branch_index", ctypes.c_int32), ("support_len", ctypes.c_int32),
+                ("queue_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double)]
 
 
 class BnbOptions(ctypes.Structure):
@@ -98,7 +99,8 @@ EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
            "certify_batch", "problem_info", "kernel_stats", "pool_create", "pool_destroy",
            "pool_add", "pool_info", "pool_export", "pool_record", "rashomon_pool",
            "rashomon_reliance", "pool_summary", "evaluate_supports", "cancel_nodes",
-           "bnb_audit_leaf", "certify_batch_noalloc"]
+           "bnb_audit_leaf", "certify_batch_noalloc", "device_budget",
+           "engine_streams"]
 
 _lib = None
 
@@ -144,6 +146,8 @@ def load():
         lib.cancel_nodes.argtypes = [vp]
         lib.bnb_audit_leaf.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
         lib.certify_batch_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        lib.device_budget.argtypes = [ctypes.c_int64, vp]
+        lib.engine_streams.argtypes = [i32]
         for name in EXPORTS:
             if name != "last_error":
                 getattr(lib, name).restype = ctypes.c_int
@@ -182,7 +186,7 @@ class Handle:
 
 
 def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hbm_budget_bytes,
-                  iter_dtype=0):
+                  iter_dtype=0, admit_timeout_ms=0):
     """Marshal a problem description; returns (desc, arrays to keep alive, mem flag)."""
     xd = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     keep = []
@@ -209,18 +213,20 @@ def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hb
                     x_dtype=xd, mem_flags=mem, X=xptr, ldx=ldx, y=yptr, hip_stream=stream,
                     hbm_budget_bytes=int(hbm_budget_bytes), batch_width=int(batch_width),
                     cert_period=int(cert_period),
-                    iter_dtype=_ITERS[iter_dtype] if iter_dtype in _ITERS else int(iter_dtype))
+                    iter_dtype=_ITERS[iter_dtype] if iter_dtype in _ITERS else int(iter_dtype),
+                    admit_timeout_ms=int(admit_timeout_ms))
     return d, keep, mem
 
 
 def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_period=0,
-                   hbm_budget_bytes=0, iter_dtype=0):
+                   hbm_budget_bytes=0, iter_dtype=0, admit_timeout_ms=0):
     """X: host array holding the stored entries (float64 / float32 / uint16
     bfloat16 bits), or a torch CUDA tensor (copied on the device).
-    iter_dtype: "auto" (0), "f32" or "f64" (precision of the iteration)."""
+    iter_dtype: "auto" (0), "f32", "f64" or "anchored" (precision of the
+    iteration).  admit_timeout_ms: wait for the process-wide device budget."""
     lib = load()
     d, keep, mem = _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period,
-                                 hbm_budget_bytes, iter_dtype)
+                                 hbm_budget_bytes, iter_dtype, admit_timeout_ms)
     out = ctypes.c_void_p()
     _check(lib.create_problem(ctypes.byref(d), ctypes.byref(out)))
     return Handle(out, d.n, d.p, int(k), keep if mem != MEM_HOST_COPY else [])
@@ -336,13 +342,27 @@ def poll_bounds(h: Handle, cap=1024, timeout_us=-1, supports=True, betas=True):
         r = out[i]
         d = dict(tag=r.tag, lower_bound=r.lower_bound, primal_value=r.primal_value,
                  rel_gap=r.rel_gap, status=r.status, iterations=r.iterations,
-                 branch_index=r.branch_index, support_len=r.support_len)
+                 branch_index=r.branch_index, support_len=r.support_len,
+                 queue_seconds=r.queue_seconds, solve_seconds=r.solve_seconds)
         if supports:
             d["support"] = sup[i, :r.support_len].copy()
         if betas:
             d["beta"] = bet[i].copy()
         res.append(d)
     return res, rc
+
+
+def device_budget(bytes_=-1):
+    """Set (bytes_ >= 0; 0 = unlimited) or read (-1) the process-wide device
+    budget of problem arenas on the current device; returns the bytes in use."""
+    used = ctypes.c_int64(0)
+    _check(load().device_budget(int(bytes_), ctypes.byref(used)))
+    return used.value
+
+
+def engine_streams(count):
+    """Problems created afterwards share `count` streams (0: one each)."""
+    _check(load().engine_streams(int(count)))
 
 
 def cancel_nodes(h: Handle):

@@ -63,6 +63,11 @@ static int fail(int code, const char *fmt, ...)
 
 extern "C" const char *last_error(void) { return g_last_error.c_str(); }
 
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 namespace kbnb {
 // error reporting for the host-side drivers built on the C ABI
 int set_error(int code, const char *fmt, ...)
@@ -82,6 +87,7 @@ int set_error(int code, const char *fmt, ...)
 // ---------------------------------------------------------------------------
 struct PendingNode {
     uint64_t tag;
+    double t_submit = 0;      // steady-clock seconds at submit_nodes
     std::vector<int8_t> st;  // ldp entries
     std::vector<double> warm; // empty or p entries
     int kbar, n0;
@@ -116,6 +122,8 @@ struct HostSlots {
 
 struct kbnb_problem {
     int device = 0;                  // the device current at create_problem
+    uint64_t charged = 0;            // bytes charged to the process-wide device budget
+    bool own_stream = true;          // false: the stream belongs to the shared pool
     unsigned char *scratch = nullptr; // that device's copy of the allocation-free scratch array
     // instance
     int n = 0, p = 0, k = 0, loss = 0, xtype = 0;
@@ -190,6 +198,7 @@ struct kbnb_problem {
     std::set<int> free_slots;        // lowest index first, so running slots stay packed
     std::vector<char> occupied;      // slot holds an admitted, unretired node
     std::vector<char> cancelled;     // slot's node was cancelled: its result is dropped
+    std::vector<double> slot_t_submit, slot_t_admit;  // per slot: its node's submit / admission time
     bool cancel_dev = false;         // cancelled slots still to be stopped on the device
     std::vector<Variant> var;        // launch widths 64, 128, ..., mpad
     int active = 0;
@@ -287,7 +296,8 @@ static void choose_splits(kbnb_problem *P)
     }
 }
 
-static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
+// total_out != NULL: only compute the arena's size into *total_out
+static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel, size_t *total_out = nullptr)
 {
     const size_t ti = P->ti_bytes;
     const size_t mp = P->mpad;
@@ -331,6 +341,10 @@ static int alloc_arena(kbnb_problem *P, size_t xbytes, size_t xel)
     for (int i = 0; i < nitems; ++i) {
         off[i] = total;
         total += round_up(sizes[i], 256);
+    }
+    if (total_out) {
+        *total_out = total;
+        return 0;
     }
     if (P->budget && total > P->budget)
         return fail(KBNB_E_BUDGET_EXCEEDED, "problem needs %zu bytes, budget %llu", total,
@@ -575,6 +589,8 @@ static int enqueue_round_async(kbnb_problem *P, std::unique_lock<std::mutex> &lk
         }
         P->slot_tag[slot] = nd.tag;
         P->slot_n0[slot] = nd.n0;
+        P->slot_t_submit[slot] = nd.t_submit;
+        P->slot_t_admit[slot] = now_s();
         ++P->active;
         ++nadm;
     }
@@ -676,6 +692,7 @@ static int process_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk, int 
     } while (0);
     lk.lock();
     if (rc) return rc;
+    const double t_done = now_s();
     for (int r = 0; r < nfin; ++r) {
         const int b = P->h_gslots[r];
         if (P->cancelled[b]) {  // a cancelled node: its result is never returned
@@ -694,6 +711,8 @@ static int process_round(kbnb_problem *P, std::unique_lock<std::mutex> &lk, int 
         d.r.iterations = h.iter[b];
         d.r.branch_index = h.jstar[b];
         d.r.support_len = h.slen[b];
+        d.r.queue_seconds = P->slot_t_admit[b] - P->slot_t_submit[b];
+        d.r.solve_seconds = t_done - P->slot_t_admit[b];
         d.sup.assign(h.sup + (size_t)b * P->k, h.sup + (size_t)(b + 1) * P->k);
         d.beta.assign(P->h_gbuf + (size_t)r * P->p, P->h_gbuf + (size_t)(r + 1) * P->p);
         if (want_lb) d.beta_lb.assign(P->h_gbuf_lb + (size_t)r * P->p, P->h_gbuf_lb + (size_t)(r + 1) * P->p);
@@ -870,6 +889,74 @@ static int scratch_for_device(int dev, unsigned char **out)
 }
 
 // ---------------------------------------------------------------------------
+// Process-wide device budget and shared stream pool (per device).  Every
+// problem's arena is charged against its device's budget at create_problem
+// and released at destroy_problem; a problem that does not fit shrinks its
+// automatic batch width, waits for releases (admit_timeout_ms) or is refused.
+// ---------------------------------------------------------------------------
+struct DeviceShare {
+    uint64_t budget = 0;  // 0: unlimited
+    uint64_t used = 0;
+    int pool_size = 0;    // 0: one stream per problem
+    std::vector<hipStream_t> pool;
+    int pool_next = 0;
+};
+static std::mutex g_dev_mu;
+static std::condition_variable g_dev_cv;
+static std::map<int, DeviceShare> g_dev;
+
+extern "C" int device_budget(int64_t bytes, int64_t *used)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(KBNB_E_NO_DEVICE, "no HIP device is visible");
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DeviceShare &D = g_dev[dev];
+    if (bytes >= 0) D.budget = (uint64_t)bytes;
+    if (used) *used = (int64_t)D.used;
+    g_dev_cv.notify_all();  // a larger budget may admit waiting problems
+    return KBNB_OK;
+}
+
+extern "C" int engine_streams(int32_t count)
+{
+    if (count < 0 || count > 64) return fail(KBNB_E_INVALID_ARGUMENT, "stream count %d outside [0, 64]", count);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(KBNB_E_NO_DEVICE, "no HIP device is visible");
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    g_dev[dev].pool_size = count;
+    return KBNB_OK;
+}
+
+// The problem's stream: its own, or the next of the device's shared pool.
+static int take_stream(kbnb_problem *P)
+{
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DeviceShare &D = g_dev[P->device];
+    if (D.pool_size <= 0) {
+        P->own_stream = true;
+        return hipStreamCreate(&P->stream) == hipSuccess ? 0 : -1;
+    }
+    while ((int)D.pool.size() < D.pool_size) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreate(&st) != hipSuccess) return -1;
+        D.pool.push_back(st);  // pool streams live until the process ends
+    }
+    P->stream = D.pool[(size_t)(D.pool_next++ % D.pool_size)];
+    P->own_stream = false;
+    return 0;
+}
+
+static void release_charge(kbnb_problem *P)
+{
+    if (!P->charged) return;
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DeviceShare &D = g_dev[P->device];
+    D.used -= std::min<uint64_t>(D.used, P->charged);
+    P->charged = 0;
+    g_dev_cv.notify_all();
+}
+
+// ---------------------------------------------------------------------------
 // create / destroy
 // ---------------------------------------------------------------------------
 static int device_ok()
@@ -914,7 +1001,8 @@ static void free_problem(kbnb_problem *P)
     if (P->sbuf) (void)hipFree(P->sbuf);
     if (P->sstream) (void)hipStreamDestroy(P->sstream);
     if (P->gstream) (void)hipStreamDestroy(P->gstream);
-    if (P->stream) (void)hipStreamDestroy(P->stream);
+    if (P->stream && P->own_stream) (void)hipStreamDestroy(P->stream);
+    release_charge(P);
     delete P;
 }
 
@@ -993,7 +1081,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     const size_t xbytes = (size_t)P->npad * P->ldp * xel;
     P->rec_bytes = (int)round_up(round_up(sizeof(AdmitRec) + P->ldp, 8) + 8 * (size_t)P->ldp, 256);
 
-    if (hipStreamCreate(&P->stream) != hipSuccess ||
+    if (take_stream(P) != 0 ||
         hipEventCreateWithFlags(&P->ev_round[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&P->ev_round[1], hipEventDisableTiming) != hipSuccess) {
         free_problem(P);
@@ -1013,14 +1101,56 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
         }
         m = std::min<int64_t>(1024, round_pow2_down(cap));
     }
-    P->m = m;
-    P->mpad = (int)round_up(m, GEMM_BN);
-    choose_splits(P);
+    // charge the arena to the device's process-wide budget: an automatic
+    // width shrinks (powers of two) to what is left; otherwise wait for
+    // releases up to admit_timeout_ms, then refuse
+    {
+        const bool auto_width = d->batch_width == 0;
+        auto set_width = [&](int mm) {
+            P->m = mm;
+            P->mpad = (int)round_up(mm, GEMM_BN);
+            choose_splits(P);
+        };
+        const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(d->admit_timeout_ms);
+        std::unique_lock<std::mutex> lk(g_dev_mu);
+        size_t total = 0;
+        // the widest width that fits (only the given one for a fixed width)
+        auto try_admit = [&]() {
+            DeviceShare &D = g_dev[P->device];
+            for (int mm = m;; mm = round_pow2_down(mm - 1)) {
+                set_width(mm);
+                alloc_arena(P, xbytes, xel, &total);
+                if (D.budget == 0 || D.used + total <= D.budget) {
+                    D.used += total;
+                    P->charged = total;
+                    return true;
+                }
+                if (!auto_width || mm <= 1) return false;
+            }
+        };
+        bool admitted = try_admit();
+        while (!admitted) {
+            const bool timed_out = g_dev_cv.wait_until(lk, deadline) == std::cv_status::timeout;
+            admitted = try_admit();
+            if (!admitted && timed_out) {
+                set_width(m);
+                alloc_arena(P, xbytes, xel, &total);
+                const unsigned long long used = g_dev[P->device].used, bud = g_dev[P->device].budget;
+                lk.unlock();
+                free_problem(P);
+                return fail(KBNB_E_BUDGET_EXCEEDED,
+                            "the device budget has %llu of %llu bytes in use; the problem needs %zu "
+                            "(waited %d ms)", used, bud, total, d->admit_timeout_ms);
+            }
+        }
+    }
     P->slot_tag.assign(P->m, 0);
     P->slot_n0.assign(P->m, 0);
     for (int b = 0; b < P->m; ++b) P->free_slots.insert(b);
     P->occupied.assign(P->m, 0);
     P->cancelled.assign(P->m, 0);
+    P->slot_t_submit.assign(P->m, 0.0);
+    P->slot_t_admit.assign(P->m, 0.0);
     P->slot_round.assign(P->m, 0);
 
     rc = alloc_arena(P, xbytes, xel);
@@ -1164,6 +1294,7 @@ static int submit_locked(kbnb_problem *P, const kbnb_node_desc *nodes, int count
         if (nd.rel_tol < 0 || std::isnan(nd.rel_tol)) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: bad rel_tol", i);
         if (nd.max_iters < 0) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: negative max_iters", i);
         pn.tag = nd.tag;
+        pn.t_submit = now_s();
         pn.n0 = nd.n_out;
         pn.ub = nd.upper_bound;
         pn.tol = nd.rel_tol > 0 ? nd.rel_tol : 1e-6;
