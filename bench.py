@@ -323,6 +323,10 @@ def serving_leg(K, W, torch, args):
         insts.append(SimpleNamespace(**_draw("mix", q)))
         if i % 8 == 7:
             log(f"serving: {i + 1} instances drawn ({time.perf_counter() - t:.1f}s)")
+    # one process-wide device budget for every problem's arena (64 GB), and
+    # optionally a shared pool of streams
+    K.device_budget(64 << 30)
+    K.engine_streams(args.serve_streams)
     handles = []
     for inst in insts:
         X = torch.from_numpy(inst.X_store).cuda()
@@ -361,6 +365,7 @@ def serving_leg(K, W, torch, args):
         lam = load * sat_rate / 32
         dur = args.serve_seconds
         lat, converged, done = [], [0], [0]
+        qs, ss = [], []
         lock = threading.Lock()
         rng_i = [np.random.Generator(np.random.PCG64(seed0 + i)) for i in range(32)]
         requests_i = [requests(i, int(lam * dur * 2) + 16) for i in range(32)]
@@ -392,6 +397,8 @@ def serving_leg(K, W, torch, args):
                     for r in res:
                         a = sub.pop(r["tag"])
                         lat.append(tnow - a)
+                        qs.append(r["queue_seconds"])
+                        ss.append(r["solve_seconds"])
                         done[0] += 1
                         converged[0] += r["status"] == K.CONVERGED
 
@@ -405,21 +412,30 @@ def serving_leg(K, W, torch, args):
         lat_ms = np.array(lat) * 1e3
         log(f"serving: load {load}: {done[0]} requests in {wall:.1f}s, "
             f"p50 {np.percentile(lat_ms, 50):.2f} ms, p99 {np.percentile(lat_ms, 99):.2f} ms")
+        q_ms, s_ms = np.array(qs) * 1e3, np.array(ss) * 1e3
         return {"offered_load": load, "requests": int(done[0]), "seconds": round(wall, 2),
                 "bounds_per_s": round(done[0] / wall, 1),
                 "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                                "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+                "queue_ms": {"p50": round(float(np.percentile(q_ms, 50)), 3),
+                             "p99": round(float(np.percentile(q_ms, 99)), 3)},
+                "solve_ms": {"p50": round(float(np.percentile(s_ms, 50)), 3),
+                             "p99": round(float(np.percentile(s_ms, 99)), 3)},
                 "converged_fraction": round(converged[0] / max(1, done[0]), 4)}
 
     main = stream(args.serve_load, 900)
     sweep = None
     if args.serve_sweep:
         sweep = [stream(float(x), 2000 + 100 * j) for j, x in enumerate(args.serve_sweep.split(","))]
+    in_use = K.device_budget(-1)
     for h in handles:
         K.destroy_problem(h)
+    K.device_budget(0)
+    K.engine_streams(0)
     res = {"workload": "serving_mix_32_problems_f32", "problems": 32,
            "saturated_rate": round(sat_rate, 1), "max_iters": it_cap, "batch_widths": widths,
-           "budget_bytes_per_problem": 2 << 30}
+           "budget_bytes_per_problem": 2 << 30, "device_budget_bytes": 64 << 30,
+           "device_bytes_in_use": int(in_use), "shared_streams": args.serve_streams}
     res.update(main)
     if sweep is not None:
         res["sweep"] = sweep
@@ -492,6 +508,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.5)
     ap.add_argument("--serve-seconds", type=float, default=15.0)
     ap.add_argument("--serve-iters", type=int, default=2000)
+    ap.add_argument("--serve-streams", type=int, default=0,
+                    help="problems share this many streams (0: one each)")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated offered loads to sweep after the main point")
     ap.add_argument("--large", type=int, default=1,
