@@ -116,15 +116,19 @@ def bnb_leg(K, W, torch, args):
     t = time.perf_counter()
     tune = K.autotune(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
                       widths=[64, 128, 256, 512, 1024, 2048], periods=[8, 16],
-                      max_iters=args.tune_iters, rel_tol=1e-6, time_limit_s=90.0, seed=2000)
+                      max_iters=args.tune_iters, rel_tol=1e-6, time_limit_s=90.0, seed=2000,
+                      tune_tiles=True, refresh=True)
     t_tune = time.perf_counter() - t
-    log(f"autotune {t_tune:.1f}s -> width {tune['batch_width']} period {tune['cert_period']}; "
+    log(f"autotune {t_tune:.1f}s -> width {tune['batch_width']} period {tune['cert_period']} "
+        f"tile rows {tune['tile_rows']} split rows {tune['split_rows']}; "
         f"rates {np.round(tune['rates'], 1).tolist()}")
     runs = {}
     for it in ("f64", "anchored"):
+        # the tuned tiles were measured with AUTO products (anchored here)
+        tiles = dict(tile_rows=tune["tile_rows"], split_rows=tune["split_rows"]) if it == "anchored" else {}
         h = K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
                              batch_width=tune["batch_width"], cert_period=tune["cert_period"],
-                             iter_dtype=it)
+                             iter_dtype=it, **tiles)
         torch.cuda.synchronize()
         runs[it] = K.branch_and_bound(h, time_limit_s=args.bnb_time_limit, log_every_s=10.0)
         K.destroy_problem(h)
@@ -160,6 +164,8 @@ def bnb_leg(K, W, torch, args):
             "support": [int(v) for v in out["support"]],
             "incumbent_updates": int(out["incumbent_updates"]),
             "autotune": {"batch_width": tune["batch_width"], "cert_period": tune["cert_period"],
+                         "tile_rows": tune["tile_rows"], "split_rows": tune["split_rows"],
+                         "tile_trials": tune["tile_trials"], "rate": round(tune["rate"], 2),
                          "seconds": round(t_tune, 2), "widths": tune["widths"],
                          "periods": tune["periods"],
                          "rates": np.round(tune["rates"], 2).tolist(),

@@ -114,6 +114,12 @@ typedef struct {
                                   hold the problem: how long create_problem waits for other
                                   problems to release memory before KBNB_E_BUDGET_EXCEEDED
                                   (0: refuse at once) */
+    int32_t tile_rows;         /* row height of the iteration's contraction tiles: 0 = chosen
+                                  by launch size; 32 or 64 for the per-tile MFMA kernels, 128 or
+                                  256 for the streaming kernel of bfloat16 X with a float32 or
+                                  anchored iteration (autotune chooses it) */
+    int32_t split_rows;        /* rows of X per split-K part of X^T R: 0 = chosen by launch
+                                  size; raised where it would give more than 32 parts */
 } kbnb_problem_desc;
 
 typedef struct {
@@ -431,6 +437,9 @@ typedef struct {
     double time_limit_s;    /* no further candidate is started after this; 0 -> 60 */
     double tie_frac;        /* rates within this fraction of the best tie; 0 -> 0.03 */
     uint64_t seed;          /* generator seed of the sample nodes */
+    int32_t tune_tiles;     /* nonzero: a second stage at the chosen width and period over
+                               the tile height and the split depth of the contractions */
+    int32_t refresh;        /* nonzero: measure even if a choice for this shape is cached */
 } kbnb_tune_options;
 
 typedef struct {
@@ -440,6 +449,10 @@ typedef struct {
     int32_t trials;         /* candidates measured */
     int32_t sample_nodes;   /* nodes bounded per candidate */
     double seconds;         /* total tuning time */
+    int32_t tile_rows;      /* the choice of tile height (0: the launch-size rule) */
+    int32_t split_rows;     /* the choice of split depth (0: the launch-size rule) */
+    int32_t cached;         /* 1: returned from the cache without measuring */
+    int32_t tile_trials;    /* second-stage candidates measured */
 } kbnb_tune_result;
 
 /*
@@ -454,7 +467,14 @@ typedef struct {
  * smallest width whose best rate is within tie_frac of the overall best, at
  * its fastest period.  rates (nullable) receives n_widths x n_periods rates,
  * row-major by width (0 where skipped or not reached).  desc->batch_width and
- * desc->cert_period are ignored.
+ * desc->cert_period are ignored.  With opts->tune_tiles a second stage runs
+ * at the chosen width and period over the tile height (the launch-size rule
+ * and its two alternatives: 32 / 64 rows, or 128 / 256 for the streaming
+ * kernel) and the split depth (the rule, half and twice its rows), and picks
+ * the fastest (the rule on ties within tie_frac).  The choice is cached per
+ * device and shape bucket (ceil(log2 n), ceil(log2 p), X dtype, loss,
+ * iteration precision) for the life of the process; a later call for the same
+ * bucket returns it with cached = 1 unless opts->refresh is set.
  */
 int autotune(const kbnb_problem_desc *desc, const kbnb_node_desc *nodes, int32_t count,
              const kbnb_tune_options *opts, kbnb_tune_result *result, double *rates);
@@ -514,10 +534,11 @@ int certify_batch(kbnb_problem *prob, int32_t m, const int8_t *states,
 int certify_batch_noalloc(kbnb_problem *prob, int32_t m, const int8_t *states, const double *betas,
                           double *phi, double *psi, int32_t *supports, int32_t *branch, void *hip_stream);
 
-/* Problem facts: i_out[0..8] = n, p, k, batch width, cert period, loss,
+/* Problem facts: i_out[0..10] = n, p, k, batch width, cert period, loss,
  * split-K count at full width, engine rounds so far, iteration precision
- * (KBNB_ITER_F32 / F64 / ANCHORED as resolved); d_out[0..3] = smoothness
- * constant L, lambda2, M, device bytes in use. */
+ * (KBNB_ITER_F32 / F64 / ANCHORED as resolved), tile rows and split rows of
+ * the full-width iteration contractions (as resolved); d_out[0..3] =
+ * smoothness constant L, lambda2, M, device bytes in use. */
 int problem_info(kbnb_problem *prob, int64_t *i_out, double *d_out);
 
 /*

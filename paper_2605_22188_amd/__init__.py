@@ -43,7 +43,8 @@ class ProblemDesc(ctypes.Structure):
                 ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p),
                 ("hip_stream", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_uint64),
                 ("batch_width", ctypes.c_int32), ("cert_period", ctypes.c_int32),
-                ("iter_dtype", ctypes.c_int32), ("admit_timeout_ms", ctypes.c_int32)]
+                ("iter_dtype", ctypes.c_int32), ("admit_timeout_ms", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("split_rows", ctypes.c_int32)]
 
 
 class NodeDesc(ctypes.Structure):
@@ -85,13 +86,16 @@ class TuneOptions(ctypes.Structure):
                 ("periods", ctypes.c_void_p), ("n_periods", ctypes.c_int32),
                 ("sample_nodes", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("rel_tol", ctypes.c_double), ("time_limit_s", ctypes.c_double),
-                ("tie_frac", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("tie_frac", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("tune_tiles", ctypes.c_int32), ("refresh", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("batch_width", ctypes.c_int32), ("cert_period", ctypes.c_int32),
                 ("rate", ctypes.c_double), ("trials", ctypes.c_int32),
-                ("sample_nodes", ctypes.c_int32), ("seconds", ctypes.c_double)]
+                ("sample_nodes", ctypes.c_int32), ("seconds", ctypes.c_double),
+                ("tile_rows", ctypes.c_int32), ("split_rows", ctypes.c_int32),
+                ("cached", ctypes.c_int32), ("tile_trials", ctypes.c_int32)]
 
 
 EXPORTS = ["create_problem", "destroy_problem", "submit_nodes", "poll_bounds",
@@ -186,7 +190,7 @@ class Handle:
 
 
 def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hbm_budget_bytes,
-                  iter_dtype=0, admit_timeout_ms=0):
+                  iter_dtype=0, admit_timeout_ms=0, tile_rows=0, split_rows=0):
     """Marshal a problem description; returns (desc, arrays to keep alive, mem flag)."""
     xd = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     keep = []
@@ -214,19 +218,21 @@ def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hb
                     hbm_budget_bytes=int(hbm_budget_bytes), batch_width=int(batch_width),
                     cert_period=int(cert_period),
                     iter_dtype=_ITERS[iter_dtype] if iter_dtype in _ITERS else int(iter_dtype),
-                    admit_timeout_ms=int(admit_timeout_ms))
+                    admit_timeout_ms=int(admit_timeout_ms), tile_rows=int(tile_rows),
+                    split_rows=int(split_rows))
     return d, keep, mem
 
 
 def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_period=0,
-                   hbm_budget_bytes=0, iter_dtype=0, admit_timeout_ms=0):
+                   hbm_budget_bytes=0, iter_dtype=0, admit_timeout_ms=0, tile_rows=0, split_rows=0):
     """X: host array holding the stored entries (float64 / float32 / uint16
     bfloat16 bits), or a torch CUDA tensor (copied on the device).
     iter_dtype: "auto" (0), "f32", "f64" or "anchored" (precision of the
     iteration).  admit_timeout_ms: wait for the process-wide device budget."""
     lib = load()
     d, keep, mem = _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period,
-                                 hbm_budget_bytes, iter_dtype, admit_timeout_ms)
+                                 hbm_budget_bytes, iter_dtype, admit_timeout_ms, tile_rows,
+                                 split_rows)
     out = ctypes.c_void_p()
     _check(lib.create_problem(ctypes.byref(d), ctypes.byref(out)))
     return Handle(out, d.n, d.p, int(k), keep if mem != MEM_HOST_COPY else [])
@@ -234,7 +240,7 @@ def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_p
 
 def autotune(X, y, k, loss, lambda2, M, dtype="f32", nodes=None, widths=None, periods=None,
              sample_nodes=0, max_iters=0, rel_tol=0.0, time_limit_s=0.0, tie_frac=0.0, seed=0,
-             hbm_budget_bytes=0, iter_dtype=0):
+             hbm_budget_bytes=0, iter_dtype=0, tune_tiles=False, refresh=False):
     """Measure every (batch width, certificate period) candidate on a node
     sample and return the choice plus the table of rates (node bounds/s)."""
     lib = load()
@@ -246,7 +252,8 @@ def autotune(X, y, k, loss, lambda2, M, dtype="f32", nodes=None, widths=None, pe
     o = TuneOptions(widths=_p(w), n_widths=len(w), periods=_p(pr), n_periods=len(pr),
                     sample_nodes=int(sample_nodes), max_iters=int(max_iters),
                     rel_tol=float(rel_tol), time_limit_s=float(time_limit_s),
-                    tie_frac=float(tie_frac), seed=int(seed))
+                    tie_frac=float(tie_frac), seed=int(seed), tune_tiles=1 if tune_tiles else 0,
+                    refresh=1 if refresh else 0)
     arr, count = None, 0
     if nodes is not None:
         arr, nkeep = _node_array(nodes, math.inf, 0.0, 0, None, None)
@@ -257,7 +264,8 @@ def autotune(X, y, k, loss, lambda2, M, dtype="f32", nodes=None, widths=None, pe
     _check(lib.autotune(ctypes.byref(d), arr, count, ctypes.byref(o), ctypes.byref(r), _p(rates)))
     return dict(batch_width=r.batch_width, cert_period=r.cert_period, rate=r.rate,
                 trials=r.trials, sample_nodes=r.sample_nodes, seconds=r.seconds,
-                widths=w.tolist(), periods=pr.tolist(), rates=rates)
+                tile_rows=r.tile_rows, split_rows=r.split_rows, cached=bool(r.cached),
+                tile_trials=r.tile_trials, widths=w.tolist(), periods=pr.tolist(), rates=rates)
 
 
 def destroy_problem(h: Handle):
@@ -587,12 +595,13 @@ def certify_batch_noalloc(h: Handle, states, betas, phi, psi, supports=None, bra
 
 
 def problem_info(h: Handle):
-    i = np.zeros(9, np.int64)
+    i = np.zeros(11, np.int64)
     d = np.zeros(4)
     _check(load().problem_info(h.ptr, _p(i), _p(d)))
     return dict(n=int(i[0]), p=int(i[1]), k=int(i[2]), batch_width=int(i[3]),
                 cert_period=int(i[4]), loss=int(i[5]), gsplit=int(i[6]), rounds=int(i[7]),
                 iteration={1: "f32", 2: "f64", 3: "anchored"}.get(int(i[8]), "?"),
+                tile_rows=int(i[9]), split_rows=int(i[10]),
                 L=float(d[0]), lambda2=float(d[1]), M=float(d[2]), device_bytes=float(d[3]))
 
 

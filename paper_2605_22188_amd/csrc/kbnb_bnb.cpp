@@ -141,7 +141,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     if (rs && !(opt->rashomon_eps >= 0 && std::isfinite(opt->rashomon_eps)))
         return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "rashomon_eps must be finite and >= 0");
     if (rs && opt->rashomon_n < 0) return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "rashomon_n must be >= 0");
-    int64_t info[9];
+    int64_t info[11];
     double dinfo[4];
     int rc = problem_info(P, info, dinfo);
     if (rc) return rc;
@@ -719,7 +719,7 @@ extern "C" int bnb_audit_leaf(kbnb_problem *P, int64_t i, int32_t *kind, double 
                               int8_t *cert_state, double *cert_beta, double *cert_bound)
 {
     if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");
-    int64_t info[9];
+    int64_t info[11];
     int rc = problem_info(P, info, nullptr);
     if (rc) return rc;
     const int p = (int)info[1];

@@ -134,6 +134,8 @@ struct kbnb_problem {
     // X and X^T, and the point and R as nb bfloat16 planes
     bool planes = false;
     int nb = 0, nkb_x = 0, nkb_xt = 0;
+    int tile_rows = 0;   // tile height of the iteration's contractions (0: rule)
+    int split_rows = 0;  // rows of X per split of X^T R (0: rule)
     uint16_t *xtile = nullptr, *xttile = nullptr, *yp = nullptr, *rp = nullptr;
     // sizes
     int ldp = 0, npad = 0, pm = 0, m = 0, mpad = 0, pp = 256;
@@ -260,7 +262,8 @@ static void splits_for(const kbnb_problem *P, int mact, Variant &v)
         // most 32 splits of a multiple of 128 rows (the tiled layout's k block)
         const int st = ((P->pm + 255) / 256) * (mact / GEMM_BN);
         int ws = std::min(32, std::max(1, (512 + st - 1) / st));
-        const int ch = (int)round_up((P->npad + ws - 1) / ws, 128);
+        int ch = (int)round_up((P->npad + ws - 1) / ws, 128);
+        if (P->split_rows > 0) ch = (int)round_up(std::max(P->split_rows, (P->npad + 31) / 32), 128);
         v.gchunk = ch;
         v.gsplit = (P->npad + ch - 1) / ch;
     }
@@ -273,8 +276,12 @@ static void splits_for(const kbnb_problem *P, int mact, Variant &v)
     const int chunk = (int)round_up((P->npad + want - 1) / want, GEMM_BK);
     v.mact = mact;
     if (!P->planes) {
-        v.gchunk = chunk;
-        v.gsplit = (P->npad + chunk - 1) / chunk;
+        // a given split depth, kept to at most 32 splits
+        const int gch = (P->split_rows > 0)
+                            ? (int)round_up(std::max(P->split_rows, (P->npad + 31) / 32), GEMM_BK)
+                            : chunk;
+        v.gchunk = gch;
+        v.gsplit = (P->npad + gch - 1) / gch;
     }
     v.qchunk = chunk;
     v.qsplit = (P->npad + chunk - 1) / chunk;
@@ -1029,6 +1036,9 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     if ((d->iter_dtype == KBNB_ITER_F32 || d->iter_dtype == KBNB_ITER_ANCHORED) &&
         d->x_dtype == KBNB_DTYPE_F64)
         return fail(KBNB_E_INVALID_ARGUMENT, "a float32 iteration needs float32 or bfloat16 X");
+    if (d->tile_rows != 0 && d->tile_rows != 32 && d->tile_rows != 64 && d->tile_rows != 128 && d->tile_rows != 256)
+        return fail(KBNB_E_INVALID_ARGUMENT, "tile_rows %d is not 0, 32, 64, 128 or 256", d->tile_rows);
+    if (d->split_rows < 0) return fail(KBNB_E_INVALID_ARGUMENT, "negative split_rows");
     int rc = device_ok();
     if (rc) return rc;
     // device inputs were produced on the caller's stream: wait for that work
@@ -1066,6 +1076,15 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->npad = (int)round_up(P->n, 64);
     P->pm = (int)round_up(P->ldp, 64);
     P->planes = (d->x_dtype == KBNB_DTYPE_BF16) && !P->iter_f64;
+    if (d->tile_rows && ((d->tile_rows >= 128) != P->planes)) {
+        const int tr = d->tile_rows;
+        delete P;
+        return fail(KBNB_E_INVALID_ARGUMENT,
+                    "tile_rows %d does not apply: 32 or 64 for the per-tile contractions, 128 or 256 "
+                    "for the streaming ones (bfloat16 X with a float32 or anchored iteration)", tr);
+    }
+    P->tile_rows = d->tile_rows;
+    P->split_rows = d->split_rows;
     if (P->planes) {
         P->nb = P->anchored ? 2 : 3;
         P->nkb_x = (P->ldp + 127) / 128;
@@ -1229,6 +1248,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->c.xtile = P->xtile; P->c.xttile = P->xttile;
     P->c.nkb_x = P->nkb_x; P->c.nkb_xt = P->nkb_xt;
     P->c.yp = P->yp; P->c.rp = P->rp; P->c.nb = P->nb;
+    P->c.tile_rows = P->tile_rows;
     for (Variant &v : P->var) build_graph(P, v);
     if (hipStreamSynchronize(P->stream) != hipSuccess) { free_problem(P); return fail(KBNB_E_DEVICE, "setup failed"); }
     P->worker = std::thread(engine_main, P);
@@ -1410,6 +1430,15 @@ extern "C" int problem_info(kbnb_problem *P, int64_t *i_out, double *d_out)
         i_out[4] = P->cert_period; i_out[5] = P->loss;
         i_out[6] = P->var.back().gsplit; i_out[7] = P->rounds.load();
         i_out[8] = P->iter_f64 ? KBNB_ITER_F64 : (P->anchored ? KBNB_ITER_ANCHORED : KBNB_ITER_F32);
+        // resolved tile height and split depth of the full-width launches
+        const Variant &v = P->var.back();
+        int tr = P->tile_rows;
+        if (!tr) {
+            if (P->planes) tr = 256;
+            else tr = ((int64_t)(P->npad / 64) * (v.mact / GEMM_BN) < 512) ? 32 : 64;  // the forward launch's rule
+        }
+        i_out[9] = tr;
+        i_out[10] = v.gchunk;
     }
     if (d_out) {
         d_out[0] = P->L; d_out[1] = P->lambda2; d_out[2] = P->M; d_out[3] = (double)P->bytes;

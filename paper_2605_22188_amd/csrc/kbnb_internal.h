@@ -80,6 +80,9 @@ struct Consts {
     uint16_t *yp;                    // [nb][mpad][ldp]
     uint16_t *rp;                    // [nb][mpad][npad]
     int nb;
+    // tile height of the iteration's contractions (0: the launch-size rule;
+    // 32 / 64 for the per-tile kernels, 128 / 256 for the streaming kernel)
+    int tile_rows;
 };
 
 // Staged node for admission into a slot (host -> device).

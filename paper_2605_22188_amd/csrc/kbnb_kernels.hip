@@ -1932,19 +1932,19 @@ __global__ __launch_bounds__(256) void k_transpose(const TA *__restrict__ X, TA 
 // 64-row tiles would leave fewer than two workgroups per CU (256 CUs), so
 // that resident workgroups hide each other's load latency.
 template <typename TA, typename TB, typename TC, int MODE>
-static void gemm(hipStream_t s, GemmArgs g, int rows, int tiles_n, int splits)
+static void gemm(hipStream_t s, GemmArgs g, int rows, int tiles_n, int splits, int bm_force = 0)
 {
     g.tiles_n = tiles_n;
     g.nsplit = splits;
     const bool small = (int64_t)(rows / 64) * tiles_n * splits < 512;
-    const int bm = small ? 32 : 64;
+    const int bm = (bm_force == 32 || bm_force == 64) ? bm_force : (small ? 32 : 64);
     g.tiles_m = rows / bm;
     int nblocks;
     if (splits > 1) nblocks = 8 * g.tiles_m * tiles_n * ((splits + 7) / 8);
     else if (g.tiles_m >= 8) nblocks = (g.tiles_m + 7) / 8 * 8 * tiles_n;
     else nblocks = g.tiles_m * tiles_n;
     dim3 grid(nblocks, 1);
-    if (small) KBNB_LAUNCH((k_gemm_tn<TA, TB, TC, MODE, 32>), grid, dim3(256), 0, s, g);
+    if (bm == 32) KBNB_LAUNCH((k_gemm_tn<TA, TB, TC, MODE, 32>), grid, dim3(256), 0, s, g);
     else KBNB_LAUNCH((k_gemm_tn<TA, TB, TC, MODE, 64>), grid, dim3(256), 0, s, g);
 }
 
@@ -1964,18 +1964,19 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
         g.A = c.xtile; g.lda = c.nkb_x; g.rows_a = c.npad;
         g.B = c.yp; g.b_plane = (int64_t)c.mpad * c.ldp;
         g.C = c.rp; g.c_plane = (int64_t)c.mpad * c.npad; g.rows_c = c.npad;
-        (void)launch_gemm_stream(s, an.sc ? EPI_DLOSS_ANCHOR : EPI_DLOSS, g, c.npad, tn, 1, 64, c.nb);
+        (void)launch_gemm_stream(s, an.sc ? EPI_DLOSS_ANCHOR : EPI_DLOSS, g, c.npad, tn, 1,
+                                 c.tile_rows == 128 ? 32 : 64, c.nb);
         return;
     }
     // outside plane mode a float32 iteration has float32 X
     if (an.sc && !iter_f64) {
-        gemm<float, float, float, EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1);
+        gemm<float, float, float, EPI_DLOSS_ANCHOR>(s, g, c.npad, tn, 1, c.tile_rows);
     } else if (iter_f64) {
-        if (xtype == XT_F64) gemm<double, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
-        else if (xtype == XT_F32) gemm<float, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
-        else gemm<uint16_t, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1);
+        if (xtype == XT_F64) gemm<double, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1, c.tile_rows);
+        else if (xtype == XT_F32) gemm<float, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1, c.tile_rows);
+        else gemm<uint16_t, double, double, EPI_DLOSS>(s, g, c.npad, tn, 1, c.tile_rows);
     } else {
-        gemm<float, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1);
+        gemm<float, float, float, EPI_DLOSS>(s, g, c.npad, tn, 1, c.tile_rows);
     }
 }
 
@@ -1991,15 +1992,15 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
     if (c.yp) {  // plane mode: stream the tiled X^T against the planes of R
         g.A = c.xttile; g.lda = c.nkb_xt; g.rows_a = c.pm;
         g.B = c.rp; g.b_plane = (int64_t)c.mpad * c.npad;
-        (void)launch_gemm_stream(s, EPI_STORE, g, c.pm, tn, gsplit, 64, c.nb);
+        (void)launch_gemm_stream(s, EPI_STORE, g, c.pm, tn, gsplit, c.tile_rows == 128 ? 32 : 64, c.nb);
         return;
     }
     if (iter_f64) {
-        if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
-        else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
-        else gemm<uint16_t, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit);
+        if (xtype == XT_F64) gemm<double, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit, c.tile_rows);
+        else if (xtype == XT_F32) gemm<float, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit, c.tile_rows);
+        else gemm<uint16_t, double, double, EPI_STORE>(s, g, c.pm, tn, gsplit, c.tile_rows);
     } else {
-        gemm<float, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit);
+        gemm<float, float, float, EPI_STORE>(s, g, c.pm, tn, gsplit, c.tile_rows);
     }
 }
 

@@ -228,7 +228,7 @@ extern "C" int rashomon_entry(kbnb_problem *P, int64_t i, int32_t *support, int3
     if (!P) return kbnb::set_error(KBNB_E_BAD_HANDLE, "NULL problem");
     if (!support || !support_len || !value)
         return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "support, support_len and value are required");
-    int64_t info[9];
+    int64_t info[11];
     double dinfo[4];
     int rc = problem_info(P, info, dinfo);
     if (rc) return rc;

@@ -11,7 +11,12 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "../../include/kbnb.h"
 
@@ -82,6 +87,18 @@ double run_sample(kbnb_problem *P, std::vector<kbnb_node_desc> &nodes, int cap, 
     return now_s() - t0;
 }
 
+// Cache of choices per device and shape bucket.
+typedef std::tuple<int, int, int, int, int, int> TuneKey;  // device, log2 n, log2 p, dtype, loss, iteration
+std::mutex g_tune_mu;
+std::map<TuneKey, kbnb_tune_result> g_tune_cache;
+
+int ceil_log2(int64_t v)
+{
+    int r = 0;
+    while ((int64_t)1 << r < v) ++r;
+    return r;
+}
+
 }  // namespace
 
 extern "C" int autotune(const kbnb_problem_desc *desc, const kbnb_node_desc *nodes, int32_t count,
@@ -110,6 +127,21 @@ extern "C" int autotune(const kbnb_problem_desc *desc, const kbnb_node_desc *nod
     const double tol = o.rel_tol > 0 ? o.rel_tol : 1e-6;
     const double tlim = o.time_limit_s > 0 ? o.time_limit_s : 60.0;
     const double tie = o.tie_frac > 0 ? o.tie_frac : 0.03;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const int iter_key = desc->iter_dtype;
+    const TuneKey key{dev, ceil_log2(desc->n), ceil_log2(desc->p), desc->x_dtype, desc->loss, iter_key};
+    if (!o.refresh) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end() && (it->second.tile_trials > 0 || !o.tune_tiles)) {
+            *result = it->second;
+            result->cached = 1;
+            result->seconds = 0.0;
+            if (rates) std::fill(rates, rates + (size_t)nw * np, 0.0);
+            return KBNB_OK;
+        }
+    }
 
     // the sample
     std::vector<SampleNode> gen;
@@ -185,6 +217,67 @@ extern "C" int autotune(const kbnb_problem_desc *desc, const kbnb_node_desc *nod
     result->rate = rate[(size_t)cw * np + cp];
     result->trials = trials;
     result->sample_nodes = (int32_t)sample.size();
+    result->tile_rows = 0;
+    result->split_rows = 0;
+    result->cached = 0;
+    result->tile_trials = 0;
+
+    // second stage: tile height and split depth at the chosen width and period
+    if (o.tune_tiles) {
+        kbnb_problem_desc d = *desc;
+        d.batch_width = widths[cw];
+        d.cert_period = periods[cp];
+        d.tile_rows = 0;
+        d.split_rows = 0;
+        // the rule's resolution, from a problem of the chosen configuration
+        kbnb_problem *P = nullptr;
+        int rc = create_problem(&d, &P);
+        if (rc) return rc;
+        int64_t info[11];
+        rc = problem_info(P, info, nullptr);
+        destroy_problem(P);
+        if (rc) return rc;
+        const int tr_rule = (int)info[9], sr_rule = (int)info[10];
+        const bool streaming = tr_rule >= 128;
+        const int tiles[3] = {0, streaming ? 128 : 32, streaming ? 256 : 64};
+        const int splits[3] = {0, std::max(64, sr_rule / 2), 2 * sr_rule};
+        double best_r = result->rate;  // the rule's rate from the first stage
+        int bt = 0, bs = 0, t2 = 0;
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) {
+                if (a == 0 && b == 0) continue;  // the first stage measured the rule
+                if (a > 0 && tiles[a] == tr_rule) continue;  // the rule under another name
+                if (now_s() - t_start > tlim) break;
+                d.tile_rows = tiles[a];
+                d.split_rows = splits[b];
+                P = nullptr;
+                rc = create_problem(&d, &P);
+                if (rc == KBNB_E_BUDGET_EXCEEDED) continue;
+                if (rc) return rc;
+                std::vector<kbnb_node_desc> warm(sample.begin(), sample.begin() + std::min<size_t>(8, sample.size()));
+                run_sample(P, warm, d.batch_width, rc);
+                double dt = rc ? -1.0 : run_sample(P, sample, d.batch_width, rc);
+                destroy_problem(P);
+                if (rc) return rc;
+                const double r = (double)sample.size() / dt;
+                ++t2;
+                // a candidate must beat the incumbent by more than the tie margin
+                if (r > best_r * (1.0 + tie)) {
+                    best_r = r;
+                    bt = tiles[a];
+                    bs = splits[b];
+                }
+            }
+        }
+        result->tile_rows = bt;
+        result->split_rows = bs;
+        result->tile_trials = t2;
+        if (bt || bs) result->rate = best_r;
+    }
     result->seconds = now_s() - t_start;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = *result;
+    }
     return KBNB_OK;
 }

@@ -61,3 +61,61 @@ def test_iteration_precision_resolution():
         with pytest.raises(K.KbnbError) as e:
             K.create_from_instance(inst, iter_dtype=it)
         assert e.value.code == -1
+
+
+def test_autotune_tile_height_split_depth_and_cache():
+    """Second stage: tile height and split depth at the chosen width and
+    period; a candidate replaces the launch-size rule only when it is faster by
+    more than the tie margin.  The choice is cached per shape bucket and
+    returned without measuring; refresh measures again."""
+    print("[gpu-test] autotune tiles and split depth, cache", flush=True)
+    inst = W.small_instance(2000, 150, 6, W.LOGISTIC, seed=60, dtype="f32")
+    kw = dict(widths=[64, 256], periods=[8], max_iters=300, seed=3, tie_frac=0.03)
+    out = K.autotune(inst.X_store, inst.y, inst.k, inst.loss, inst.lambda2, inst.M, dtype="f32",
+                     tune_tiles=True, refresh=True, **kw)
+    assert not out["cached"] and out["tile_trials"] > 0
+    assert out["tile_rows"] in (0, 32, 64)
+    cw = out["widths"].index(out["batch_width"])
+    rule_rate = out["rates"][cw, 0]
+    if out["tile_rows"] or out["split_rows"]:
+        assert out["rate"] > rule_rate * 1.03
+    else:
+        assert out["rate"] == rule_rate
+    again = K.autotune(inst.X_store, inst.y, inst.k, inst.loss, inst.lambda2, inst.M, dtype="f32",
+                       tune_tiles=True, **kw)
+    assert again["cached"] and again["seconds"] == 0.0
+    for key in ("batch_width", "cert_period", "tile_rows", "split_rows"):
+        assert again[key] == out[key]
+    # the choice applied, and the explicit controls give valid bounds
+    nodes = W.random_nodes(150, 30, 3, 15, seed=61)
+    h0 = K.create_from_instance(inst, batch_width=64)
+    ref = K.bound_nodes(h0, nodes, rel_tol=1e-6)
+    K.destroy_problem(h0)
+    for tr, sr in ((out["tile_rows"], out["split_rows"]), (64, 128), (32, 1024)):
+        h = K.create_from_instance(inst, batch_width=64, tile_rows=tr, split_rows=sr)
+        info = K.problem_info(h)
+        if tr:
+            assert info["tile_rows"] == tr
+        if sr:
+            assert info["split_rows"] >= sr
+        res = K.bound_nodes(h, nodes, rel_tol=1e-6)
+        for a, g in zip(ref, res):
+            assert g["status"] == K.CONVERGED
+            scale = max(abs(a["primal_value"]), abs(g["primal_value"]))
+            assert abs(g["lower_bound"] - a["lower_bound"]) <= 1e-6 * scale
+        K.destroy_problem(h)
+
+
+def test_tile_rows_apply_to_their_kernel_only():
+    print("[gpu-test] tile_rows validation", flush=True)
+    f32 = W.small_instance(300, 20, 4, W.LOGISTIC, seed=3, dtype="f32")
+    bf = W.small_instance(300, 20, 4, W.LOGISTIC, seed=3, dtype="bf16")
+    for inst, bad in ((f32, 128), (bf, 32), (f32, 48)):
+        with pytest.raises(K.KbnbError) as e:
+            K.create_from_instance(inst, batch_width=8, tile_rows=bad)
+        assert e.value.code == -1
+    h = K.create_from_instance(bf, batch_width=8, tile_rows=128)
+    assert K.problem_info(h)["tile_rows"] == 128
+    res = K.bound_nodes(h, W.random_nodes(20, 8, 2, 5, seed=4), rel_tol=1e-6)
+    assert all(r["status"] == K.CONVERGED for r in res)
+    K.destroy_problem(h)
