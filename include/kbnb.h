@@ -120,6 +120,11 @@ typedef struct {
                                   anchored iteration (autotune chooses it) */
     int32_t split_rows;        /* rows of X per split-K part of X^T R: 0 = chosen by launch
                                   size; raised where it would give more than 32 parts */
+    int32_t reopt_groups;      /* workgroups per support in the support re-optimisation
+                                  (evaluate_supports, branch_and_bound), at most 1024: 0 =
+                                  chosen from n and the batch size; 1 = one workgroup per
+                                  support; g >= 2 = g workgroups (at most n) sharing the
+                                  support's rows, one launch per step */
 } kbnb_problem_desc;
 
 typedef struct {
@@ -230,6 +235,11 @@ typedef struct {
     int32_t audit;           /* nonzero: record every leaf of the explored tree with the
                                 certificate of its bound (bnb_audit_leaf); costs host
                                 memory of p doubles per bounded node */
+    int32_t support_path;    /* how supports are re-optimised (k <= 64): 0 automatic, 1 the
+                                batched re-optimisation kernel (evaluate_supports), 2 the
+                                node J1 = S, J0 = rest in the node engine.  Automatic takes
+                                the kernel, except on tall instances where the device
+                                cannot split a support's rows over several workgroups */
 } kbnb_bnb_options;
 
 typedef struct {
@@ -313,9 +323,10 @@ int bnb_audit_leaf(kbnb_problem *prob, int64_t i, int32_t *kind, double *bound, 
  *   v(S_i) = min { F(X beta) + lambda2 ||beta||^2 : supp beta in S_i,
  *                  |beta_j| <= M },
  * the relaxation of the node J1 = S_i, J0 = the rest, which is exact.  On
- * the device in float64 from the stored instance values, one workgroup per
- * support (gathered columns, accelerated proximal gradient, the dual bound
- * of the restricted problem every 10 steps), blocking.  Outputs per
+ * the device in float64 from the stored instance values (gathered columns,
+ * accelerated proximal gradient, the dual bound of the restricted problem
+ * every 10 steps; on tall instances each support's rows are split over
+ * several workgroups, see reopt_groups), blocking.  Outputs per
  * support: values[i] = the objective at the returned coefficients (attained
  * there), lower_bounds[i] = a certified lower bound of v(S_i) (weak
  * duality, <= values[i]), betas (NULL or count x p: the coefficients, 0 off

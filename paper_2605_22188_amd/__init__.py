@@ -44,7 +44,8 @@ class ProblemDesc(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_uint64),
                 ("batch_width", ctypes.c_int32), ("cert_period", ctypes.c_int32),
                 ("iter_dtype", ctypes.c_int32), ("admit_timeout_ms", ctypes.c_int32),
-                ("tile_rows", ctypes.c_int32), ("split_rows", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("split_rows", ctypes.c_int32),
+                ("reopt_groups", ctypes.c_int32)]
 
 
 class NodeDesc(ctypes.Structure):
@@ -69,7 +70,7 @@ class BnbOptions(ctypes.Structure):
                 ("max_nodes", ctypes.c_int64), ("log_every_s", ctypes.c_double),
                 ("rashomon", ctypes.c_int32), ("rashomon_n", ctypes.c_int32),
                 ("rashomon_eps", ctypes.c_double), ("node_order", ctypes.c_int32),
-                ("audit", ctypes.c_int32)]
+                ("audit", ctypes.c_int32), ("support_path", ctypes.c_int32)]
 
 
 class BnbResult(ctypes.Structure):
@@ -190,7 +191,7 @@ class Handle:
 
 
 def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hbm_budget_bytes,
-                  iter_dtype=0, admit_timeout_ms=0, tile_rows=0, split_rows=0):
+                  iter_dtype=0, admit_timeout_ms=0, tile_rows=0, split_rows=0, reopt_groups=0):
     """Marshal a problem description; returns (desc, arrays to keep alive, mem flag)."""
     xd = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     keep = []
@@ -219,20 +220,23 @@ def _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period, hb
                     cert_period=int(cert_period),
                     iter_dtype=_ITERS[iter_dtype] if iter_dtype in _ITERS else int(iter_dtype),
                     admit_timeout_ms=int(admit_timeout_ms), tile_rows=int(tile_rows),
-                    split_rows=int(split_rows))
+                    split_rows=int(split_rows), reopt_groups=int(reopt_groups))
     return d, keep, mem
 
 
 def create_problem(X, y, k, loss, lambda2, M, dtype="f32", batch_width=0, cert_period=0,
-                   hbm_budget_bytes=0, iter_dtype=0, admit_timeout_ms=0, tile_rows=0, split_rows=0):
+                   hbm_budget_bytes=0, iter_dtype=0, admit_timeout_ms=0, tile_rows=0, split_rows=0,
+                   reopt_groups=0):
     """X: host array holding the stored entries (float64 / float32 / uint16
     bfloat16 bits), or a torch CUDA tensor (copied on the device).
     iter_dtype: "auto" (0), "f32", "f64" or "anchored" (precision of the
-    iteration).  admit_timeout_ms: wait for the process-wide device budget."""
+    iteration).  admit_timeout_ms: wait for the process-wide device budget.
+    reopt_groups: workgroups per support in the support re-optimisation (0:
+    automatic, 1: one)."""
     lib = load()
     d, keep, mem = _problem_desc(X, y, k, loss, lambda2, M, dtype, batch_width, cert_period,
                                  hbm_budget_bytes, iter_dtype, admit_timeout_ms, tile_rows,
-                                 split_rows)
+                                 split_rows, reopt_groups)
     out = ctypes.c_void_p()
     _check(lib.create_problem(ctypes.byref(d), ctypes.byref(out)))
     return Handle(out, d.n, d.p, int(k), keep if mem != MEM_HOST_COPY else [])
@@ -393,12 +397,13 @@ def bound_nodes(h: Handle, nodes, **kw):
 
 def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=0.0,
                      max_fista_iters=0, max_nodes=0, log_every_s=0.0, rashomon_eps=None,
-                     rashomon_n=0, node_order=0, audit=False):
+                     rashomon_n=0, node_order=0, audit=False, support_path=0):
     """rashomon_eps (>= 0): also collect the support-level Rashomon set (the
     best rashomon_n when nonzero), returned as "rashomon": a list of
     (support tuple, value, beta) ordered by value.  node_order: 0 best bound,
     1 depth first.  audit: also return "leaves", the discarded subtrees with the
-    certificates of their bounds (see bnb_audit_leaf)."""
+    certificates of their bounds (see bnb_audit_leaf).  support_path: 0
+    automatic, 1 the re-optimisation kernel, 2 the node engine."""
     sup = np.full(h.k, -1, np.int32)
     beta = np.zeros(h.p)
     o = BnbOptions(time_limit_s=time_limit_s, rel_gap_tol=rel_gap_tol,
@@ -406,7 +411,8 @@ def branch_and_bound(h: Handle, time_limit_s=0.0, rel_gap_tol=0.0, node_rel_tol=
                    max_nodes=max_nodes, log_every_s=log_every_s,
                    rashomon=0 if rashomon_eps is None else 1, rashomon_n=int(rashomon_n),
                    rashomon_eps=0.0 if rashomon_eps is None else float(rashomon_eps),
-                   node_order=int(node_order), audit=1 if audit else 0)
+                   node_order=int(node_order), audit=1 if audit else 0,
+                   support_path=int(support_path))
     r = BnbResult(support=_p(sup), beta=_p(beta))
     _check(load().branch_and_bound(h.ptr, ctypes.byref(o), ctypes.byref(r)))
     out = dict(objective=r.objective, lower_bound=r.lower_bound, rel_gap=r.rel_gap,

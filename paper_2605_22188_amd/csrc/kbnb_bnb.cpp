@@ -130,6 +130,7 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
                          const double *warm, double tol, int max_iter);
 int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double *coefs, int32_t *status,
                           int32_t *iters, double *coefs_lb);
+int support_groups(kbnb_problem *P, int count, int maxlen);
 }  // namespace kbnb
 
 extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kbnb_bnb_result *res)
@@ -162,6 +163,8 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
 
     if (opt->node_order != 0 && opt->node_order != 1)
         return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "node_order must be 0 or 1");
+    if (opt->support_path < 0 || opt->support_path > 2)
+        return kbnb::set_error(KBNB_E_INVALID_ARGUMENT, "support_path must be 0, 1 or 2");
     const bool dfs = opt->node_order == 1;
     const bool audit = opt->audit != 0;
     auto leaves = std::make_shared<std::vector<kbnb::AuditLeaf>>();
@@ -276,13 +279,15 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     double last_log = 0.0;
     double t_poll = 0, t_flush = 0, t_fill = 0, t_res = 0;  // host time split (progress lines)
 
-    // Support evaluations: with k <= 64 and n <= 32768 they are batched into
-    // the dedicated re-optimisation kernel (one batch on the device at a
-    // time, beside the node rounds); otherwise each is the node J1 = S, J0 =
-    // complement.  The kernel walks all n rows of a support in one workgroup
-    // per step, which stops paying off on tall instances, where the batched
-    // node contractions are faster.
-    const bool dev_reopt = k <= 64 && info[0] <= 32768;
+    // Support evaluations: with k <= 64 they are batched into the dedicated
+    // re-optimisation kernel (one batch on the device at a time, beside the
+    // node rounds); otherwise each is the node J1 = S, J0 = complement.  On
+    // tall instances the kernel needs a support's rows split over several
+    // workgroups to keep up with the batched node contractions: without
+    // that split (a device that cannot hold two workgroups per support of a
+    // batch of 16) the automatic choice is the node path there.
+    bool dev_reopt = k <= 64 && opt->support_path != 2;
+    if (dev_reopt && opt->support_path == 0 && info[0] > 32768) dev_reopt = kbnb::support_groups(P, 16, k) >= 2;
     // One batch of support evaluations is on the device at a time: each pass
     // of the loop collects the batch launched in the previous pass (it ran
     // while the host filled and processed nodes) and launches the pending

@@ -136,6 +136,7 @@ struct kbnb_problem {
     int nb = 0, nkb_x = 0, nkb_xt = 0;
     int tile_rows = 0;   // tile height of the iteration's contractions (0: rule)
     int split_rows = 0;  // rows of X per split of X^T R (0: rule)
+    int reopt_groups = 0; // workgroups per support in the re-optimisation (0: automatic)
     uint16_t *xtile = nullptr, *xttile = nullptr, *yp = nullptr, *rp = nullptr;
     // sizes
     int ldp = 0, npad = 0, pm = 0, m = 0, mpad = 0, pp = 256;
@@ -180,6 +181,9 @@ struct kbnb_problem {
     int64_t s_coefs = 0;
     double *s_val = nullptr, *s_low = nullptr, *s_coef = nullptr, *s_coef_lb = nullptr;
     int32_t *s_st = nullptr, *s_it = nullptr;
+    SupportLaunch s_launch;         // that batch's launch (split rows: steps launched so far)
+    int s_steps = 0;
+    int s_steps_hint = 128;         // step launches the last split batch needed
     hipStream_t gstream = nullptr;  // gathers beside a round enqueued ahead (created on first use:
                                     // streams share the process's few hardware queues)
     hipEvent_t ev_round[2] = {nullptr, nullptr};
@@ -1039,6 +1043,8 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     if (d->tile_rows != 0 && d->tile_rows != 32 && d->tile_rows != 64 && d->tile_rows != 128 && d->tile_rows != 256)
         return fail(KBNB_E_INVALID_ARGUMENT, "tile_rows %d is not 0, 32, 64, 128 or 256", d->tile_rows);
     if (d->split_rows < 0) return fail(KBNB_E_INVALID_ARGUMENT, "negative split_rows");
+    if (d->reopt_groups < 0 || d->reopt_groups > 1024)
+        return fail(KBNB_E_INVALID_ARGUMENT, "reopt_groups %d is not in [0, 1024]", d->reopt_groups);
     int rc = device_ok();
     if (rc) return rc;
     // device inputs were produced on the caller's stream: wait for that work
@@ -1085,6 +1091,7 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     }
     P->tile_rows = d->tile_rows;
     P->split_rows = d->split_rows;
+    P->reopt_groups = d->reopt_groups;
     if (P->planes) {
         P->nb = P->anchored ? 2 : 3;
         P->nkb_x = (P->ldp + 127) / 128;
@@ -1736,7 +1743,11 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t b_lab = al(Cn * 4), b_off = al((N + 1) * 8), b_warm = al(Cn * 8), b_coef = al(Cn * 8),
                  b_val = al(N * 8), b_low = al(N * 8), b_st = al(N * 4), b_it = al(N * 4), b_clb = al(Cn * 8);
-    const size_t need = b_lab + b_off + b_warm + b_coef + b_val + b_low + b_st + b_it + b_clb;
+    // work area of the split-row re-optimisation (0 bytes for one workgroup per support)
+    size_t b_work = 0;
+    const int groups = support_eval_plan(P->xtype, P->n, count, maxlen, P->reopt_groups, &b_work);
+    b_work = al(b_work);
+    const size_t need = b_lab + b_off + b_warm + b_coef + b_val + b_low + b_st + b_it + b_clb + b_work;
     if (need > P->sbuf_bytes) {
         HIP_TRY(hipStreamSynchronize(P->sstream));
         if (P->sbuf) (void)hipFree(P->sbuf);
@@ -1755,21 +1766,40 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
     P->s_low = (double *)b; b += b_low;
     P->s_st = (int32_t *)b; b += b_st;
     P->s_it = (int32_t *)b; b += b_it;
-    P->s_coef_lb = (double *)b;
+    P->s_coef_lb = (double *)b; b += b_clb;
+    void *dwork = b_work ? (void *)b : nullptr;
     hipStream_t s = P->sstream;
     HIP_TRY(hipMemcpyAsync(dlab, lab, 4 * C, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(doff, off, 8 * (N + 1), hipMemcpyHostToDevice, s));
     if (warm) HIP_TRY(hipMemcpyAsync(dwarm, warm, 8 * C, hipMemcpyHostToDevice, s));
-    if (launch_support_eval(s, P->xtype, P->XT, P->npad, P->n, P->loss, P->y, dlab, doff, count, maxlen,
-                            warm ? dwarm : nullptr, P->lambda2, P->M, tol, max_iter, 10, P->s_coef, P->s_val,
-                            P->s_low, P->s_st, P->s_it, P->s_coef_lb) != 0)
-        return fail(KBNB_E_INVALID_ARGUMENT, "support too long");
+    SupportLaunch &SL = P->s_launch;
+    SL = SupportLaunch{};
+    SL.xtype = P->xtype; SL.XT = P->XT; SL.npad = P->npad; SL.n = P->n; SL.loss = P->loss; SL.y = P->y;
+    SL.lab = dlab; SL.off = doff; SL.count = count; SL.maxlen = maxlen; SL.warm = warm ? dwarm : nullptr;
+    SL.lambda2 = P->lambda2; SL.M = P->M; SL.tol = tol; SL.max_iter = max_iter; SL.cert_every = 10;
+    SL.beta_out = P->s_coef; SL.value = P->s_val; SL.lower = P->s_low; SL.status = P->s_st; SL.iters = P->s_it;
+    SL.beta_lb_out = P->s_coef_lb;
+    SL.groups = groups; SL.work = dwork; SL.work_bytes = b_work;
+    // split rows: as many step launches as the last batch needed to start
+    // with; collect adds more until every support has finished
+    P->s_steps = (groups > 1) ? std::min(max_iter + 1, P->s_steps_hint) : 0;
+    const int lrc = launch_support_start(s, SL, P->s_steps);
+    if (lrc == -1) return fail(KBNB_E_INVALID_ARGUMENT, "support too long");
+    if (lrc != 0) return fail(KBNB_E_DEVICE, "support re-optimisation launch failed");
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(P->sev, s));
     // the pageable-source copies above have consumed the inputs by now
     P->s_count = count;
     P->s_coefs = (int64_t)C;
     return KBNB_OK;
+}
+
+// Workgroups per support that eval_supports_launch would use for a batch of
+// `count` supports of at most maxlen features.
+int support_groups(kbnb_problem *P, int count, int maxlen)
+{
+    size_t wb = 0;
+    return support_eval_plan(P->xtype, P->n, count, maxlen, P->reopt_groups, &wb);
 }
 
 int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double *coefs, int32_t *status,
@@ -1781,6 +1811,28 @@ int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double
     P->s_count = 0;
     hipStream_t s = P->sstream;
     HIP_TRY(hipEventSynchronize(P->sev));
+    const SupportLaunch &SL = P->s_launch;
+    if (SL.groups > 1) {
+        // more step launches until every support has finished (max_iter + 1
+        // of them finish all), doubling each time
+        for (;;) {
+            int32_t nd = 0;
+            HIP_TRY(hipMemcpyAsync(&nd, support_done_counter(SL), 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (nd >= SL.count) break;
+            if (P->s_steps >= SL.max_iter + 1)
+                return fail(KBNB_E_DEVICE, "%d of %d supports unfinished after %d steps", SL.count - nd, SL.count,
+                            P->s_steps);
+            const int more = std::min(SL.max_iter + 1 - P->s_steps, std::max(32, P->s_steps));
+            if (launch_support_steps(s, SL, more) != 0) return fail(KBNB_E_DEVICE, "step launch failed");
+            HIP_TRY(hipGetLastError());
+            P->s_steps += more;
+        }
+        std::vector<int32_t> it(N);
+        HIP_TRY(hipMemcpyAsync(it.data(), P->s_it, 4 * N, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        P->s_steps_hint = std::max(16, 1 + *std::max_element(it.begin(), it.end()));
+    }
     HIP_TRY(hipMemcpyAsync(values, P->s_val, 8 * N, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(lower, P->s_low, 8 * N, hipMemcpyDeviceToHost, s));
     if (coefs && C) HIP_TRY(hipMemcpyAsync(coefs, P->s_coef, 8 * C, hipMemcpyDeviceToHost, s));

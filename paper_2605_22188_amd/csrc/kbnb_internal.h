@@ -156,14 +156,45 @@ void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int
 // coefficients are lab/coef[off[m] .. off[m + 1]); out has the same layout
 void launch_reliance(hipStream_t s, int xtype, const void *XT, int64_t npad, int n, int loss, const double *y,
                      const int32_t *lab, const int64_t *off, const double *coef, int nrec, double *out);
-// batched support re-optimisation in float64 (supports of at most 64 features;
-// returns -1 when maxlen exceeds that); lab/off as for launch_reliance
+// Batched support re-optimisation in float64 (supports of at most 64
+// features): one batch of supports lab[off[i] .. off[i + 1]) with its
+// outputs (coefficients in the layout of lab).  With groups > 1 the rows of
+// each support are split over that many workgroups: a set-up launch, then
+// one launch per step, the supports' state kept in `work` between them.
 constexpr int SUPPORT_EVAL_MAX = 64;
-int launch_support_eval(hipStream_t s, int xtype, const void *XT, int64_t npad, int n, int loss,
-                        const double *y, const int32_t *lab, const int64_t *off, int count, int maxlen,
-                        const double *warm, double lambda2, double M, double tol, int max_iter,
-                        int cert_every, double *beta_out, double *value, double *lower, int32_t *status,
-                        int32_t *iters, double *beta_lb_out = nullptr);
+struct SupportLaunch {
+    int xtype = 0;
+    const void *XT = nullptr;
+    int64_t npad = 0;
+    int n = 0, loss = 0;
+    const double *y = nullptr;
+    const int32_t *lab = nullptr;
+    const int64_t *off = nullptr;
+    int count = 0, maxlen = 0;
+    const double *warm = nullptr;  // nullable
+    double lambda2 = 0, M = 0, tol = 0;
+    int max_iter = 0, cert_every = 10;
+    double *beta_out = nullptr, *value = nullptr, *lower = nullptr;
+    int32_t *status = nullptr, *iters = nullptr;
+    double *beta_lb_out = nullptr;  // nullable
+    int groups = 1;
+    void *work = nullptr;
+    size_t work_bytes = 0;
+};
+// Workgroups per support for a batch of `count` supports of at most maxlen
+// features over n rows (want: 0 automatic, 1 one workgroup, g >= 2 that
+// many); *work_bytes gets the bytes of device work area the split needs (0
+// for one workgroup).
+int support_eval_plan(int xtype, int n, int count, int maxlen, int want, size_t *work_bytes);
+// Enqueue the batch: the whole of it with one workgroup per support;
+// otherwise the set-up and the first `steps` step launches.  -1 for a
+// support longer than SUPPORT_EVAL_MAX or a work area too small.
+int launch_support_start(hipStream_t s, const SupportLaunch &L, int steps);
+// groups > 1: `steps` more step launches (a launch leaves finished supports
+// alone; every support has finished after max_iter + 1 of them)
+int launch_support_steps(hipStream_t s, const SupportLaunch &L, int steps);
+// groups > 1: device counter of the supports that have finished
+const int32_t *support_done_counter(const SupportLaunch &L);
 // Arguments of the MFMA contraction kernels (kbnb_kernels.hip):
 // C[col][row] = sum_k A[row][k] * B[col][k] over the workgroup's k split.
 enum { EPI_DLOSS = 0, EPI_STORE = 1, EPI_CERT = 2, EPI_DLOSS_ANCHOR = 3 };

@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "kbnb_internal.h"
 
@@ -2191,6 +2193,16 @@ void launch_reliance(hipStream_t s, int xtype, const void *XT, int64_t npad, int
 // Psi, status (0 converged, 2 iteration limit) and the steps taken.
 // ---------------------------------------------------------------------------
 struct SupportArgs {
+    // split-row version (k_support_mw_init, k_support_mw_step): workgroups
+    // per support, and the state of each support kept between step launches
+    int groups;
+    double *part;       // [count][groups][KB + 2] partial sums of the current step
+    double *gram;       // [count][groups][KB (KB + 1) / 2] partial Gram matrices
+    double *st;         // [count][8] eta, theta, t, best primal, best dual, finished
+    double *vec;        // [count][4][KB] beta, Y, best-primal beta, best-dual beta
+    int32_t *step;      // [count] step index
+    int32_t *arrive;    // [count] workgroups through the current launch (0 between launches)
+    int32_t *ndone;     // supports finished
     const void *XT;
     int64_t npad;
     int n, loss;
@@ -2450,36 +2462,455 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
     }
 }
 
-int launch_support_eval(hipStream_t s, int xtype, const void *XT, int64_t npad, int n, int loss,
-                        const double *y, const int32_t *lab, const int64_t *off, int count, int maxlen,
-                        const double *warm, double lambda2, double M, double tol, int max_iter,
-                        int cert_every, double *beta_out, double *value, double *lower, int32_t *status,
-                        int32_t *iters, double *beta_lb_out)
+// ---------------------------------------------------------------------------
+// Re-optimisation with the rows of each support split over a.groups
+// workgroups (tall instances, where one workgroup walking every row per step
+// is latency-bound).  Workgroup g of support m owns a contiguous block of
+// rows.  k_support_mw_init forms the Gram matrix from the groups' partial
+// sums and sets up each support's state; then each launch of
+// k_support_mw_step is one step: every workgroup makes one pass over its
+// rows forming s_i = x_{i,S} . pt and, in the same pass, its part of the
+// gradient (or, at a certificate, of q = X_S^T zeta and the loss sums); the
+// last workgroup of the support to finish (an atomic arrival count) adds
+// the parts in group order and applies the update of k_support_eval.  No
+// workgroup ever waits for another, so the launch needs no residency
+// guarantee.  A finished support's workgroups return at once; a support
+// finishes at step max_iter at the latest, so max_iter + 1 step launches
+// finish every support.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void support_rows(const SupportArgs &a, int gg, int &r0, int &r1)
 {
-    if (count <= 0) return 0;
+    const int per = (a.n + a.groups - 1) / a.groups;
+    r0 = min(a.n, gg * per);
+    r1 = min(a.n, r0 + per);
+}
+
+// every thread: true in the workgroup that arrives last at support m
+__device__ __forceinline__ bool support_last_arrival(const SupportArgs &a, int m, int *flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // this workgroup's partial sums before its arrival
+        *flag = atomicAdd(&a.arrive[m], 1) == a.groups - 1;
+    }
+    __syncthreads();
+    const bool last = *flag != 0;
+    if (last) __threadfence();  // ... and every other workgroup's after it
+    return last;
+}
+
+template <typename TA, int KB>
+__global__ __launch_bounds__(256) void k_support_mw_init(SupportArgs a)
+{
+    constexpr int TR = 2048 / KB;
+    constexpr int NPAIR = KB * (KB + 1) / 2;
+    constexpr int PT = (NPAIR + 255) / 256;
+    __shared__ int32_t L[KB];
+    __shared__ double G[KB][KB + 1];
+    __shared__ double tile[TR][KB + 1];
+    __shared__ int s_last;
+    const TA *XT = reinterpret_cast<const TA *>(a.XT);
+    const int ng = a.groups, m = blockIdx.x / ng, gg = blockIdx.x % ng;
+    const int tid = threadIdx.x;
+    const int64_t o0 = a.off[m];
+    const int kl = (int)(a.off[m + 1] - o0);
+    int r0, r1;
+    support_rows(a, gg, r0, r1);
+    if (tid < KB) L[tid] = (tid < kl) ? a.lab[o0 + tid] : 0;
+    if (blockIdx.x == 0 && tid == 0) *a.ndone = 0;
+    __syncthreads();
+    // partial Gram matrix of this workgroup's rows: thread t owns pairs t + 256 v
+    int pr[PT], pq[PT];
+    double gacc[PT];
+#pragma unroll
+    for (int v = 0; v < PT; ++v) {
+        int pi = tid + 256 * v, r = 0;
+        const int np = kl * (kl + 1) / 2;
+        if (pi < np) {
+            while (pi >= kl - r) { pi -= kl - r; ++r; }
+            pr[v] = r;
+            pq[v] = r + pi;
+        } else {
+            pr[v] = -1;
+            pq[v] = 0;
+        }
+        gacc[v] = 0.0;
+    }
+    for (int i0 = r0; i0 < r1 && kl > 0; i0 += TR) {
+        for (int e = tid; e < TR * kl; e += 256) {
+            const int r = e / TR, row = e - r * TR, i = i0 + row;
+            tile[row][r] = (i < r1) ? cvt_d(XT[(int64_t)L[r] * a.npad + i]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < PT; ++v) {
+            if (pr[v] >= 0) {
+                double acc = 0.0;
+                for (int row = 0; row < TR; ++row) acc += tile[row][pr[v]] * tile[row][pq[v]];
+                gacc[v] += acc;
+            }
+        }
+        __syncthreads();
+    }
+    double *gp = a.gram + ((int64_t)m * ng + gg) * NPAIR;
+#pragma unroll
+    for (int v = 0; v < PT; ++v)
+        if (tid + 256 * v < NPAIR) gp[tid + 256 * v] = gacc[v];
+    if (!support_last_arrival(a, m, &s_last)) return;
+    // the last workgroup: the Gram matrix in group order, the step size and
+    // the starting state
+#pragma unroll
+    for (int v = 0; v < PT; ++v) {
+        if (pr[v] >= 0) {
+            double t = 0.0;
+            for (int q = 0; q < ng; ++q) t += a.gram[((int64_t)m * ng + q) * NPAIR + tid + 256 * v];
+            G[pr[v]][pq[v]] = t;
+            G[pq[v]][pr[v]] = t;
+        }
+    }
+    __syncthreads();
+    double *st = a.st + 8 * (int64_t)m;
+    if (tid < 64) {
+        double rs = 0.0, fr = 0.0;
+        if (tid < kl)
+            for (int q = 0; q < kl; ++q) {
+                rs += fabs(G[tid][q]);
+                fr += G[tid][q] * G[tid][q];
+            }
+        double gmax = rs;
+        for (int o = 32; o > 0; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o));
+        fr = wave_sum(fr);
+        if (tid == 0) {
+            const double Lc = a.c_loss * fmin(sqrt(fr), gmax);
+            st[0] = (Lc > 0.0) ? 1.0 / (Lc * 1.000001) : 1.0;
+            st[1] = 0.0;        // theta
+            st[2] = 1.0;        // t
+            st[3] = INFINITY;   // best primal
+            st[4] = -INFINITY;  // best dual
+            st[5] = 0.0;        // finished
+            a.step[m] = 0;
+            a.arrive[m] = 0;
+        }
+    }
+    if (tid < KB) {
+        double w = (a.warm && tid < kl) ? a.warm[o0 + tid] : 0.0;
+        w = (tid < kl) ? fmin(fmax(w, -a.M), a.M) : 0.0;
+        double *vec = a.vec + (int64_t)m * 4 * KB;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) vec[c * KB + tid] = w;
+    }
+}
+
+template <typename TA, int KB>
+__global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
+{
+    __shared__ int32_t L[KB];
+    __shared__ double Pt[KB], Bv[KB], Yv[KB], Bb[KB], Bd[KB], Bn[KB];
+    __shared__ double red[4][KB + 2];
+    __shared__ double sc[8];
+    __shared__ int s_last;
+    const TA *XT = reinterpret_cast<const TA *>(a.XT);
+    const int ng = a.groups, m = blockIdx.x / ng, gg = blockIdx.x % ng;
+    double *st = a.st + 8 * (int64_t)m;
+    if (st[5] != 0.0) return;  // finished (the same for the whole workgroup)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int it = a.step[m];
+    const bool cert = (it % a.cert_every) == 0 || it >= a.max_iter;
+    const int64_t o0 = a.off[m];
+    const int kl = (int)(a.off[m + 1] - o0);
+    int r0, r1;
+    support_rows(a, gg, r0, r1);
+    double *vec = a.vec + (int64_t)m * 4 * KB;
+    if (tid < KB) {
+        L[tid] = (tid < kl) ? a.lab[o0 + tid] : 0;
+        Pt[tid] = vec[(cert ? 0 : 1) * KB + tid];
+    }
+    __syncthreads();
+    // this workgroup's rows: gradient at Y, or (cert) the certificate terms at beta
+    {
+        double g[KB];
+#pragma unroll
+        for (int r = 0; r < KB; ++r) g[r] = 0.0;
+        double al = 0.0, ac = 0.0;
+        constexpr int U = (KB <= 16) ? 4 : ((KB <= 32) ? 2 : 1);
+        for (int i0 = r0 + tid; i0 < r1; i0 += 256 * U) {
+            int64_t ri[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ok[u] = i0 + 256 * u < r1;
+                ri[u] = ok[u] ? i0 + 256 * u : r0;
+            }
+            double sv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) sv[u] = 0.0;
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                if (r < kl) {
+                    const TA *col = XT + (int64_t)L[r] * a.npad;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) sv[u] += cvt_d(col[ri[u]]) * Pt[r];
+                }
+            }
+            double dv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double yi = a.y[ri[u]];
+                if (cert) {
+                    double z, lv, cv;
+                    cert_terms(a.loss, sv[u], yi, z, lv, cv);
+                    al += ok[u] ? lv : 0.0;
+                    ac += ok[u] ? cv : 0.0;
+                    dv[u] = ok[u] ? z : 0.0;
+                } else {
+                    dv[u] = ok[u] ? dloss_d(a.loss, sv[u], yi) : 0.0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                if (r < kl) {
+                    const TA *col = XT + (int64_t)L[r] * a.npad;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acc += cvt_d(col[ri[u]]) * dv[u];
+                    g[r] += acc;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+            if (r < kl) {
+                const double v = wave_sum(g[r]);
+                if (lane == 0) red[wave][r] = v;
+            }
+        }
+        al = wave_sum(al);
+        ac = wave_sum(ac);
+        if (lane == 0) {
+            red[wave][KB] = al;
+            red[wave][KB + 1] = ac;
+        }
+    }
+    __syncthreads();
+    double *pp = a.part + ((int64_t)m * ng + gg) * (KB + 2);
+    if (tid < KB + 2 && (tid < kl || tid >= KB)) pp[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    if (!support_last_arrival(a, m, &s_last)) return;
+    // the last workgroup: the step's sums in group order, then the update
+    if (tid < KB + 2 && (tid < kl || tid >= KB)) {
+        double t = 0.0;
+        for (int q = 0; q < ng; ++q) t += a.part[((int64_t)m * ng + q) * (KB + 2) + tid];
+        red[0][tid] = t;
+    }
+    if (tid < KB) {
+        Bv[tid] = vec[tid];
+        Yv[tid] = vec[KB + tid];
+        Bb[tid] = vec[2 * KB + tid];
+        Bd[tid] = vec[3 * KB + tid];
+    }
+    if (tid < 8) sc[tid] = st[tid];
+    __syncthreads();
+    const double eta = sc[0];
+    if (cert) {
+        if (tid < 64) {
+            double pen = 0.0, dterm = 0.0;
+            if (tid < kl) {
+                const double qv = red[0][tid] / (2.0 * a.lambda2);
+                pen = Bv[tid] * Bv[tid];
+                dterm = huber(qv, a.M);
+            }
+            pen = wave_sum(pen);
+            dterm = wave_sum(dterm);
+            if (tid == 0) {
+                const double phi = red[0][KB] + a.lambda2 * pen;
+                const double psi = -red[0][KB + 1] - 2.0 * a.lambda2 * dterm;
+                sc[6] = (phi < sc[3]) ? 1.0 : 0.0;
+                if (phi < sc[3]) sc[3] = phi;
+                sc[7] = (psi > sc[4]) ? 1.0 : 0.0;
+                if (psi > sc[4]) sc[4] = psi;
+                const double den = fmax(fabs(sc[3]), 1e-12);
+                sc[5] = ((sc[3] - sc[4]) <= a.tol * den || it >= a.max_iter) ? 1.0 : 0.0;
+            }
+        }
+        __syncthreads();
+        if (tid < kl && sc[6] != 0.0) Bb[tid] = Bv[tid];
+        if (tid < kl && sc[7] != 0.0) Bd[tid] = Bv[tid];
+    } else {
+        // proximal step from Y, restart test, momentum
+        const double shrink = 1.0 / (1.0 + 2.0 * eta * a.lambda2);
+        if (tid < 64) {
+            double dot = 0.0;
+            if (tid < kl) {
+                const double u = Yv[tid] - eta * red[0][tid];
+                const double bn = fmin(fmax(u * shrink, -a.M), a.M);
+                Bn[tid] = bn;
+                dot = (Yv[tid] - bn) * (bn - Bv[tid]);
+            }
+            dot = wave_sum(dot);
+            if (tid == 0) {
+                const double tm = sc[2];
+                if (dot > 0.0) {
+                    sc[2] = 1.0;
+                    sc[1] = 0.0;
+                } else {
+                    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tm * tm));
+                    sc[1] = (tm - 1.0) / tn;
+                    sc[2] = tn;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < kl) {
+            const double bp = Bv[tid];
+            Bv[tid] = Bn[tid];
+            Yv[tid] = Bn[tid] + sc[1] * (Bn[tid] - bp);
+        }
+    }
+    __syncthreads();
+    if (tid < KB) {
+        vec[tid] = Bv[tid];
+        vec[KB + tid] = Yv[tid];
+        vec[2 * KB + tid] = Bb[tid];
+        vec[3 * KB + tid] = Bd[tid];
+    }
+    if (tid < 6) st[tid] = sc[tid];
+    const bool fin = sc[5] != 0.0;
+    if (fin && tid < kl) {
+        a.beta_out[o0 + tid] = Bb[tid];
+        if (a.beta_lb_out) a.beta_lb_out[o0 + tid] = Bd[tid];
+    }
+    if (tid == 0) {
+        a.arrive[m] = 0;
+        if (fin) {
+            a.value[m] = sc[3];
+            a.lower[m] = fmin(sc[4], sc[3]);
+            a.status[m] = (sc[3] - sc[4] <= a.tol * fmax(fabs(sc[3]), 1e-12)) ? 0 : 2;
+            a.iters[m] = it;
+            atomicAdd(a.ndone, 1);
+        } else {
+            a.step[m] = it + 1;
+        }
+    }
+}
+static int support_kb(int maxlen) { return maxlen <= 16 ? 16 : (maxlen <= 32 ? 32 : 64); }
+
+// Rows per workgroup that the automatic split aims at (a step's pass over
+// them takes a few row sweeps of the workgroup), the batch size in
+// workgroups it stops growing at, and the height below which one workgroup
+// per support is kept.
+constexpr int SUPPORT_MW_ROWS = 2048;
+constexpr int SUPPORT_MW_BLOCKS = 1024;
+constexpr int SUPPORT_MW_MIN_N = 8192;
+
+struct MwLayout {
+    size_t part, gram, st, vec, step, arrive, ndone, total;
+};
+
+static MwLayout mw_layout(int count, int groups, int KB)
+{
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t blocks = (size_t)count * groups, c = (size_t)count;
+    MwLayout l;
+    size_t o = 0;
+    l.part = o;   o += al(blocks * (KB + 2) * 8);
+    l.gram = o;   o += al(blocks * (size_t)KB * (KB + 1) / 2 * 8);
+    l.st = o;     o += al(c * 8 * 8);
+    l.vec = o;    o += al(c * 4 * KB * 8);
+    l.step = o;   o += al(c * 4);
+    l.arrive = o; o += al(c * 4);
+    l.ndone = o;  o += 256;
+    l.total = o;
+    return l;
+}
+
+int support_eval_plan(int xtype, int n, int count, int maxlen, int want, size_t *work_bytes)
+{
+    (void)xtype;
+    *work_bytes = 0;
+    if (count <= 0 || maxlen > SUPPORT_EVAL_MAX || want == 1) return 1;
+    if (want == 0 && n < SUPPORT_MW_MIN_N) return 1;
+    int g = (want > 0) ? want
+                       : std::min((n + SUPPORT_MW_ROWS - 1) / SUPPORT_MW_ROWS,
+                                  std::max(1, SUPPORT_MW_BLOCKS / count));
+    g = std::min(g, std::max(n, 1));  // no more workgroups than rows
+    g = std::min<int64_t>(g, INT32_MAX / count);
+    if (g < 2) return 1;
+    *work_bytes = mw_layout(count, g, support_kb(maxlen)).total;
+    return g;
+}
+
+static SupportArgs support_args(const SupportLaunch &L)
+{
     SupportArgs a{};
-    a.beta_lb_out = beta_lb_out;
-    a.XT = XT; a.npad = npad; a.n = n; a.loss = loss; a.y = y; a.lab = lab; a.off = off; a.warm = warm;
-    a.lambda2 = lambda2; a.M = M; a.c_loss = (loss == 0) ? 2.0 : 0.25; a.tol = tol;
-    a.max_iter = max_iter; a.cert_every = cert_every;
-    a.beta_out = beta_out; a.value = value; a.lower = lower; a.status = status; a.iters = iters;
-    const dim3 grid(count);
-#define KBNB_SUP(TA, KB) KBNB_LAUNCH((k_support_eval<TA, KB>), grid, dim3(256), 0, s, a)
-#define KBNB_SUP_T(TA)                      \
-    do {                                    \
-        if (maxlen <= 16) KBNB_SUP(TA, 16); \
-        else if (maxlen <= 32) KBNB_SUP(TA, 32); \
-        else KBNB_SUP(TA, 64);              \
+    a.groups = L.groups;
+    a.XT = L.XT; a.npad = L.npad; a.n = L.n; a.loss = L.loss; a.y = L.y; a.lab = L.lab; a.off = L.off;
+    a.warm = L.warm; a.lambda2 = L.lambda2; a.M = L.M; a.c_loss = (L.loss == 0) ? 2.0 : 0.25; a.tol = L.tol;
+    a.max_iter = L.max_iter; a.cert_every = L.cert_every;
+    a.beta_out = L.beta_out; a.beta_lb_out = L.beta_lb_out; a.value = L.value; a.lower = L.lower;
+    a.status = L.status; a.iters = L.iters;
+    if (L.groups > 1) {
+        const MwLayout l = mw_layout(L.count, L.groups, support_kb(L.maxlen));
+        char *w = (char *)L.work;
+        a.part = (double *)(w + l.part);
+        a.gram = (double *)(w + l.gram);
+        a.st = (double *)(w + l.st);
+        a.vec = (double *)(w + l.vec);
+        a.step = (int32_t *)(w + l.step);
+        a.arrive = (int32_t *)(w + l.arrive);
+        a.ndone = (int32_t *)(w + l.ndone);
+    }
+    return a;
+}
+
+const int32_t *support_done_counter(const SupportLaunch &L)
+{
+    const MwLayout l = mw_layout(L.count, L.groups, support_kb(L.maxlen));
+    return (const int32_t *)((const char *)L.work + l.ndone);
+}
+
+#define KBNB_SUP_DISPATCH(KERNEL, GRID)                                          \
+    do {                                                                         \
+        const int kb_ = support_kb(L.maxlen);                                    \
+        if (L.xtype == XT_F64) {                                                 \
+            if (kb_ == 16) KBNB_LAUNCH((KERNEL<double, 16>), GRID, dim3(256), 0, s, a);   \
+            else if (kb_ == 32) KBNB_LAUNCH((KERNEL<double, 32>), GRID, dim3(256), 0, s, a); \
+            else KBNB_LAUNCH((KERNEL<double, 64>), GRID, dim3(256), 0, s, a);             \
+        } else if (L.xtype == XT_F32) {                                          \
+            if (kb_ == 16) KBNB_LAUNCH((KERNEL<float, 16>), GRID, dim3(256), 0, s, a);    \
+            else if (kb_ == 32) KBNB_LAUNCH((KERNEL<float, 32>), GRID, dim3(256), 0, s, a); \
+            else KBNB_LAUNCH((KERNEL<float, 64>), GRID, dim3(256), 0, s, a);              \
+        } else {                                                                 \
+            if (kb_ == 16) KBNB_LAUNCH((KERNEL<uint16_t, 16>), GRID, dim3(256), 0, s, a); \
+            else if (kb_ == 32) KBNB_LAUNCH((KERNEL<uint16_t, 32>), GRID, dim3(256), 0, s, a); \
+            else KBNB_LAUNCH((KERNEL<uint16_t, 64>), GRID, dim3(256), 0, s, a);           \
+        }                                                                        \
     } while (0)
-    if (maxlen > 64) return -1;
-    if (xtype == XT_F64) KBNB_SUP_T(double);
-    else if (xtype == XT_F32) KBNB_SUP_T(float);
-    else KBNB_SUP_T(uint16_t);
-#undef KBNB_SUP_T
-#undef KBNB_SUP
+
+int launch_support_steps(hipStream_t s, const SupportLaunch &L, int steps)
+{
+    if (L.count <= 0 || L.groups < 2) return 0;
+    const SupportArgs a = support_args(L);
+    const dim3 grid((unsigned)((size_t)L.count * L.groups));
+    for (int i = 0; i < steps; ++i) KBNB_SUP_DISPATCH(k_support_mw_step, grid);
     return 0;
 }
 
+int launch_support_start(hipStream_t s, const SupportLaunch &L, int steps)
+{
+    if (L.count <= 0) return 0;
+    if (L.maxlen > SUPPORT_EVAL_MAX) return -1;
+    const SupportArgs a = support_args(L);
+    if (L.groups < 2) {
+        KBNB_SUP_DISPATCH(k_support_eval, dim3(L.count));
+        return 0;
+    }
+    const MwLayout l = mw_layout(L.count, L.groups, support_kb(L.maxlen));
+    if (!L.work || L.work_bytes < l.total) return -1;
+    // arrival counts start at zero (each step's last workgroup clears its own)
+    if (hipMemsetAsync(a.arrive, 0, (size_t)L.count * 4, s) != hipSuccess) return -2;
+    KBNB_SUP_DISPATCH(k_support_mw_init, dim3((unsigned)((size_t)L.count * L.groups)));
+    return launch_support_steps(s, L, steps);
+}
+#undef KBNB_SUP_DISPATCH
 void launch_transpose(hipStream_t s, int xtype, const void *X, void *XT, int n, int p, int ldp,
                       int npad, int pm)
 {
