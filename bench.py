@@ -218,6 +218,7 @@ def large_leg(K, W, torch, args):
     K.kernel_stats(h, 1)
     K.bound_nodes(h, W.random_nodes(d["p"], args.large_batch, 7, 500, seed=3001), rel_tol=1e-6)
     ks = K.kernel_stats(h, 0)
+    reopt = reopt_probe(K, W, h, d, args.reopt_supports) if args.reopt_supports > 0 else None
     rash = None
     if args.large_rashomon > 0:
         # certify the optimum and collect every support within (1 + eps) of it
@@ -268,7 +269,48 @@ def large_leg(K, W, torch, args):
                                   "bfloat16 planes of the change since each node's last "
                                   "float64 certificate",
             "kernel_pass": {"nodes": args.large_batch, "nodes_per_launch": round(m_run, 1)},
-            "kernels": kern, "rashomon_bnb": rash}
+            "kernels": kern, "support_reopt": reopt, "rashomon_bnb": rash}
+
+
+def reopt_probe(K, W, h, d, count):
+    """Batched support re-optimisation (evaluate_supports, rel. tol 1e-7) on
+    the large problem: `count` supports near the true one (up to three of its
+    features swapped for random ones), rows split over workgroups as chosen
+    automatically, against the same supports bounded as nodes J1 = S, J0 =
+    the rest.  HBM roofline: each step of a running support reads its columns
+    of X (bfloat16) and y (float64) once, n (2 |S| + 8) bytes."""
+    true = np.flatnonzero(d["beta_true"])
+    g = np.random.Generator(np.random.PCG64(4040))
+    sups = []
+    for _ in range(count):
+        S = set(true.tolist())
+        for _ in range(int(g.integers(0, 4))):
+            S.discard(int(g.choice(sorted(S))))
+            S.add(int(g.integers(0, d["p"])))
+        sups.append(tuple(sorted(S)))
+    K.evaluate_supports(h, sups[:4], rel_tol=1e-7)
+    t = time.perf_counter()
+    r = K.evaluate_supports(h, sups, rel_tol=1e-7)
+    dt = time.perf_counter() - t
+    n = d["n"]
+    steps = r["iterations"] + 1
+    by = float(sum(int(st) * n * (2 * len(S) + 8) for st, S in zip(steps, sups)))
+    nodes = []
+    for S in sups:
+        ins = np.array(S, np.int32)
+        nodes.append(W.Node(ins, np.setdiff1d(np.arange(d["p"]), ins).astype(np.int32)))
+    t = time.perf_counter()
+    rn = K.bound_nodes(h, nodes, rel_tol=1e-7)
+    dtn = time.perf_counter() - t
+    gbs = by / dt / 1e9
+    out = {"supports": count, "rel_tol": 1e-7, "seconds": round(dt, 5),
+           "steps_max": int(steps.max()), "not_converged": int(np.sum(r["status"] != 0)),
+           "alg_bytes": round(by), "hbm_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+           "node_path_seconds": round(dtn, 4), "speedup_vs_node_path": round(dtn / dt, 2),
+           "max_value_diff_vs_node_path": float(max(abs(a - b["primal_value"]) / abs(a)
+                                                    for a, b in zip(r["value"], rn)))}
+    log(f"large: support re-optimisation {out}")
+    return out
 
 
 def importance_leg(K, W, torch, args):
@@ -521,6 +563,8 @@ def main():
     ap.add_argument("--large", type=int, default=1,
                     help="run the 100000 x 5000 bfloat16 logistic node-bound leg")
     ap.add_argument("--large-batch", type=int, default=256)
+    ap.add_argument("--reopt-supports", type=int, default=128,
+                    help="supports in the large problem's re-optimisation probe (0: skip)")
     ap.add_argument("--importance-seconds", type=float, default=20.0,
                     help="collection time of the variable-importance leg (0: skip)")
     ap.add_argument("--large-rashomon", type=float, default=0.01,

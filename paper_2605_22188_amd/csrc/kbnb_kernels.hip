@@ -2333,21 +2333,24 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
                 ok[u] = i0 + 256 * u < a.n;
                 ri[u] = ok[u] ? i0 + 256 * u : 0;
             }
-            double sv[U];
+            double sv[U], yv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) sv[u] = 0.0;
+            for (int u = 0; u < U; ++u) {
+                sv[u] = 0.0;
+                yv[u] = a.y[ri[u]];
+            }
+            // every column slot is read (slots past the support hold column
+            // 0 with weight 0), so all U * KB loads are issued together
 #pragma unroll
             for (int r = 0; r < KB; ++r) {
-                if (r < kl) {
-                    const TA *col = XT + (int64_t)L[r] * a.npad;
+                const TA *col = XT + (int64_t)L[r] * a.npad;
 #pragma unroll
-                    for (int u = 0; u < U; ++u) sv[u] += cvt_d(col[ri[u]]) * pt[r];
-                }
+                for (int u = 0; u < U; ++u) sv[u] += cvt_d(col[ri[u]]) * pt[r];
             }
             double dv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double yi = a.y[ri[u]];
+                const double yi = yv[u];
                 if (cert) {
                     double z, lv, cv;
                     cert_terms(a.loss, sv[u], yi, z, lv, cv);
@@ -2360,13 +2363,11 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
             }
 #pragma unroll
             for (int r = 0; r < KB; ++r) {
-                if (r < kl) {
-                    const TA *col = XT + (int64_t)L[r] * a.npad;
-                    double acc = 0.0;
+                const TA *col = XT + (int64_t)L[r] * a.npad;
+                double acc = 0.0;
 #pragma unroll
-                    for (int u = 0; u < U; ++u) acc += cvt_d(col[ri[u]]) * dv[u];
-                    g[r] += acc;
-                }
+                for (int u = 0; u < U; ++u) acc += cvt_d(col[ri[u]]) * dv[u];
+                g[r] += acc;  // unused past the support
             }
         }
 #pragma unroll
@@ -2485,6 +2486,22 @@ __device__ __forceinline__ void support_rows(const SupportArgs &a, int gg, int &
     r1 = min(a.n, r0 + per);
 }
 
+// sum_{q < ng} v[q * stride], added in q order, with eight loads in flight
+__device__ __forceinline__ double sum_in_order(const double *v, int ng, int64_t stride)
+{
+    double t = 0.0;
+    int q = 0;
+    for (; q + 8 <= ng; q += 8) {
+        double w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = v[(q + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t += w[u];
+    }
+    for (; q < ng; ++q) t += v[q * stride];
+    return t;
+}
+
 // every thread: true in the workgroup that arrives last at support m
 __device__ __forceinline__ bool support_last_arrival(const SupportArgs &a, int m, int *flag)
 {
@@ -2562,8 +2579,7 @@ __global__ __launch_bounds__(256) void k_support_mw_init(SupportArgs a)
 #pragma unroll
     for (int v = 0; v < PT; ++v) {
         if (pr[v] >= 0) {
-            double t = 0.0;
-            for (int q = 0; q < ng; ++q) t += a.gram[((int64_t)m * ng + q) * NPAIR + tid + 256 * v];
+            const double t = sum_in_order(a.gram + (int64_t)m * ng * NPAIR + tid + 256 * v, ng, NPAIR);
             G[pr[v]][pq[v]] = t;
             G[pq[v]][pr[v]] = t;
         }
@@ -2641,21 +2657,24 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
                 ok[u] = i0 + 256 * u < r1;
                 ri[u] = ok[u] ? i0 + 256 * u : r0;
             }
-            double sv[U];
+            double sv[U], yv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) sv[u] = 0.0;
+            for (int u = 0; u < U; ++u) {
+                sv[u] = 0.0;
+                yv[u] = a.y[ri[u]];
+            }
+            // every column slot is read (slots past the support hold column
+            // 0 with weight 0), so all U * KB loads are issued together
 #pragma unroll
             for (int r = 0; r < KB; ++r) {
-                if (r < kl) {
-                    const TA *col = XT + (int64_t)L[r] * a.npad;
+                const TA *col = XT + (int64_t)L[r] * a.npad;
 #pragma unroll
-                    for (int u = 0; u < U; ++u) sv[u] += cvt_d(col[ri[u]]) * Pt[r];
-                }
+                for (int u = 0; u < U; ++u) sv[u] += cvt_d(col[ri[u]]) * Pt[r];
             }
             double dv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double yi = a.y[ri[u]];
+                const double yi = yv[u];
                 if (cert) {
                     double z, lv, cv;
                     cert_terms(a.loss, sv[u], yi, z, lv, cv);
@@ -2668,13 +2687,11 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
             }
 #pragma unroll
             for (int r = 0; r < KB; ++r) {
-                if (r < kl) {
-                    const TA *col = XT + (int64_t)L[r] * a.npad;
-                    double acc = 0.0;
+                const TA *col = XT + (int64_t)L[r] * a.npad;
+                double acc = 0.0;
 #pragma unroll
-                    for (int u = 0; u < U; ++u) acc += cvt_d(col[ri[u]]) * dv[u];
-                    g[r] += acc;
-                }
+                for (int u = 0; u < U; ++u) acc += cvt_d(col[ri[u]]) * dv[u];
+                g[r] += acc;  // unused past the support
             }
         }
 #pragma unroll
@@ -2696,11 +2713,8 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
     if (tid < KB + 2 && (tid < kl || tid >= KB)) pp[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
     if (!support_last_arrival(a, m, &s_last)) return;
     // the last workgroup: the step's sums in group order, then the update
-    if (tid < KB + 2 && (tid < kl || tid >= KB)) {
-        double t = 0.0;
-        for (int q = 0; q < ng; ++q) t += a.part[((int64_t)m * ng + q) * (KB + 2) + tid];
-        red[0][tid] = t;
-    }
+    if (tid < KB + 2 && (tid < kl || tid >= KB))
+        red[0][tid] = sum_in_order(a.part + (int64_t)m * ng * (KB + 2) + tid, ng, KB + 2);
     if (tid < KB) {
         Bv[tid] = vec[tid];
         Yv[tid] = vec[KB + tid];
