@@ -114,10 +114,15 @@ def bnb_leg(K, W, torch, args):
     X = torch.from_numpy(inst.X_store).cuda()
     y = torch.from_numpy(inst.y).cuda()
     t = time.perf_counter()
-    tune = K.autotune(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
-                      widths=[64, 128, 256, 512, 1024, 2048], periods=[8, 16],
-                      max_iters=args.tune_iters, rel_tol=1e-6, time_limit_s=90.0, seed=2000,
-                      tune_tiles=True, refresh=True)
+    if args.bnb_tune:
+        tune = K.autotune(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
+                          widths=[64, 128, 256, 512, 1024, 2048], periods=[8, 16],
+                          max_iters=args.tune_iters, rel_tol=1e-6, time_limit_s=90.0, seed=2000,
+                          tune_tiles=True, refresh=True)
+    else:
+        # fixed choice (the autotuner's usual one at this shape), for profiling runs
+        tune = dict(batch_width=1024, cert_period=16, tile_rows=0, split_rows=0, tile_trials=0,
+                    rate=0.0, widths=[1024], periods=[16], rates=np.zeros((1, 1)), sample_nodes=0)
     t_tune = time.perf_counter() - t
     log(f"autotune {t_tune:.1f}s -> width {tune['batch_width']} period {tune['cert_period']} "
         f"tile rows {tune['tile_rows']} split rows {tune['split_rows']}; "
@@ -551,6 +556,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--bnb", type=int, default=1, help="run the time-to-zero-gap leg")
     ap.add_argument("--bnb-time-limit", type=float, default=150.0)
+    ap.add_argument("--bnb-tune", type=int, default=1,
+                    help="0: skip the autotuner in the time-to-zero-gap leg (width 1024, period 16)")
     ap.add_argument("--tune-iters", type=int, default=200)
     ap.add_argument("--serving", type=int, default=1, help="run the serving-mix latency leg")
     ap.add_argument("--serve-load", type=float, default=0.5)

@@ -30,9 +30,11 @@ constexpr int GEMM_BK = 16;
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 // Padded column length of the per-node kernels: the power of two >= p, at
-// least 256, at most 8192.  Up to 2048 a node runs on one wave; above, on
-// pp / 1024 waves, so every thread holds 16 coordinates.
-__host__ __device__ constexpr int node_waves(int pp) { return pp <= 2048 ? 1 : pp / 1024; }
+// least 256, at most 8192.  A node runs on pp / 256 waves (at most 16), so
+// every thread holds 4 coordinates (8 at pp = 8192): the per-node chain of
+// sort repair, scans and block search is short, and one workgroup per node
+// still keeps a thin frontier's nodes on separate CUs.
+__host__ __device__ constexpr int node_waves(int pp) { return pp <= 256 ? 1 : (pp / 256 < 16 ? pp / 256 : 16); }
 // Split-K partials summed per load batch by the per-node kernels (pp: the
 // coordinates one wave holds; element size in bytes), sized so a batch's
 // loads fit in registers.

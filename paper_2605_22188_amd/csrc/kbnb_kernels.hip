@@ -998,8 +998,8 @@ __device__ void bitonic_desc(double *key, TI *idx)
 }
 
 // ---------------------------------------------------------------------------
-// Per-node kernels run one workgroup of W waves per node (W = 1 up to
-// PP = 2048, more above).  Thread t owns the contiguous coordinates
+// Per-node kernels run one workgroup of W waves per node (W = PP / 256, at
+// most 16).  Thread t owns the contiguous coordinates
 // j = E t .. E t + E - 1 (E = PP / (64 W); PP >= 256 a power of two >= p),
 // i.e. E / 4 whole groups of four, so a node's column is read and written
 // with 16-byte vector accesses.  Groups at or beyond ldp (the padded column
