@@ -115,9 +115,9 @@ typedef struct {
                                   problems to release memory before KBNB_E_BUDGET_EXCEEDED
                                   (0: refuse at once) */
     int32_t tile_rows;         /* row height of the iteration's contraction tiles: 0 = chosen
-                                  by launch size; 32 or 64 for the per-tile MFMA kernels, 128 or
-                                  256 for the streaming kernel of bfloat16 X with a float32 or
-                                  anchored iteration (autotune chooses it) */
+                                  by launch size; 32 or 64 for the per-tile MFMA kernels, 64,
+                                  128 or 256 for the streaming kernel of bfloat16 X with a
+                                  float32 or anchored iteration (autotune chooses it) */
     int32_t split_rows;        /* rows of X per split-K part of X^T R: 0 = chosen by launch
                                   size; raised where it would give more than 32 parts */
     int32_t reopt_groups;      /* workgroups per support in the support re-optimisation
@@ -480,7 +480,7 @@ typedef struct {
  * row-major by width (0 where skipped or not reached).  desc->batch_width and
  * desc->cert_period are ignored.  With opts->tune_tiles a second stage runs
  * at the chosen width and period over the tile height (the launch-size rule
- * and its two alternatives: 32 / 64 rows, or 128 / 256 for the streaming
+ * and the explicit heights: 32 / 64 rows, or 64 / 128 / 256 for the streaming
  * kernel) and the split depth (the rule, half and twice its rows), and picks
  * the fastest (the rule on ties within tie_frac).  The choice is cached per
  * device and shape bucket (ceil(log2 n), ceil(log2 p), X dtype, loss,

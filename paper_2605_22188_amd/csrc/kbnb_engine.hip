@@ -1082,11 +1082,11 @@ extern "C" int create_problem(const kbnb_problem_desc *d, kbnb_problem **out)
     P->npad = (int)round_up(P->n, 64);
     P->pm = (int)round_up(P->ldp, 64);
     P->planes = (d->x_dtype == KBNB_DTYPE_BF16) && !P->iter_f64;
-    if (d->tile_rows && ((d->tile_rows >= 128) != P->planes)) {
+    if (d->tile_rows && (P->planes ? d->tile_rows < 64 : d->tile_rows > 64)) {
         const int tr = d->tile_rows;
         delete P;
         return fail(KBNB_E_INVALID_ARGUMENT,
-                    "tile_rows %d does not apply: 32 or 64 for the per-tile contractions, 128 or 256 "
+                    "tile_rows %d does not apply: 32 or 64 for the per-tile contractions, 64, 128 or 256 "
                     "for the streaming ones (bfloat16 X with a float32 or anchored iteration)", tr);
     }
     P->tile_rows = d->tile_rows;
@@ -1440,9 +1440,9 @@ extern "C" int problem_info(kbnb_problem *P, int64_t *i_out, double *d_out)
         // resolved tile height and split depth of the full-width launches
         const Variant &v = P->var.back();
         int tr = P->tile_rows;
-        if (!tr) {
-            if (P->planes) tr = 256;
-            else tr = ((int64_t)(P->npad / 64) * (v.mact / GEMM_BN) < 512) ? 32 : 64;  // the forward launch's rule
+        if (!tr) {  // the forward launch's rule
+            if (P->planes) tr = 4 * stream_wave_rows(0, P->npad, v.mact / GEMM_BN, 1);
+            else tr = ((int64_t)(P->npad / 64) * (v.mact / GEMM_BN) < 512) ? 32 : 64;
         }
         i_out[9] = tr;
         i_out[10] = v.gchunk;

@@ -235,6 +235,9 @@ struct GemmArgs {
 // or EPI_STORE (float32 split-K partials).  Returns -1 for an unsupported
 // combination.
 int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_n, int splits, int wr, int nb);
+// wave tile height (16, 32 or 64 rows) of a streaming launch over `rows`
+// rows of A: tile_rows / 4 when given, else chosen by launch size
+int stream_wave_rows(int tile_rows, int rows, int tiles_n, int splits);
 // tiled copy of a rows x cols bfloat16 matrix for k_gemm_stream (whose A is
 // this layout, with GemmArgs::lda = ceil(cols / 128)); dst holds
 // ceil(rows / 16) * 16 x ceil(cols / 128) * 128 elements

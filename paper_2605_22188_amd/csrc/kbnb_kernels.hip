@@ -786,6 +786,18 @@ void launch_tile_bf16(hipStream_t s, const uint16_t *src, int64_t lds, int rows,
     if (blocks > 0) KBNB_LAUNCH(k_tile_bf16, dim3(blocks), dim3(256), 0, s, src, lds, rows, cols, nrb, nkb, dst);
 }
 
+// Wave tile height of a streaming launch: the explicit tile (4 waves per
+// workgroup tile), else the tallest of 64 / 32 / 16 rows that still gives
+// the launch 256 workgroups (a thin frontier on a short X needs the smaller
+// tiles to occupy the CUs; tall tiles reuse each B super-step longer).
+int stream_wave_rows(int tile_rows, int rows, int tiles_n, int splits)
+{
+    if (tile_rows) return tile_rows / 4;
+    int wr = 64;
+    while (wr > 16 && (int64_t)((rows + 4 * wr - 1) / (4 * wr)) * tiles_n * splits < 256) wr /= 2;
+    return wr;
+}
+
 int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_n, int splits, int wr, int nb)
 {
     const int bm = 4 * wr;
@@ -797,13 +809,15 @@ int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_
     else if (g.tiles_m >= 8) nblocks = (g.tiles_m + 7) / 8 * 8 * tiles_n;
     else nblocks = g.tiles_m * tiles_n;
     const dim3 grid(nblocks, 1);
-    if ((wr != 32 && wr != 64) || (nb != 2 && nb != 3)) return -1;
+    if ((wr != 16 && wr != 32 && wr != 64) || (nb != 2 && nb != 3)) return -1;
 #define KBNB_STREAM(M)                                                                           \
     do {                                                                                         \
         if (wr == 64 && nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 64, 3>), grid, dim3(256), 0, s, g); \
         else if (wr == 64) KBNB_LAUNCH((k_gemm_stream<M, 64, 2>), grid, dim3(256), 0, s, g);       \
-        else if (nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 32, 3>), grid, dim3(256), 0, s, g);        \
-        else KBNB_LAUNCH((k_gemm_stream<M, 32, 2>), grid, dim3(256), 0, s, g);                     \
+        else if (wr == 32 && nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 32, 3>), grid, dim3(256), 0, s, g); \
+        else if (wr == 32) KBNB_LAUNCH((k_gemm_stream<M, 32, 2>), grid, dim3(256), 0, s, g);       \
+        else if (nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 16, 3>), grid, dim3(256), 0, s, g);        \
+        else KBNB_LAUNCH((k_gemm_stream<M, 16, 2>), grid, dim3(256), 0, s, g);                     \
     } while (0)
     if (mode == EPI_DLOSS) KBNB_STREAM(EPI_DLOSS);
     else if (mode == EPI_DLOSS_ANCHOR) KBNB_STREAM(EPI_DLOSS_ANCHOR);
@@ -1967,7 +1981,7 @@ void launch_fwd_dloss(hipStream_t s, int xtype, bool iter_f64, const void *X, co
         g.B = c.yp; g.b_plane = (int64_t)c.mpad * c.ldp;
         g.C = c.rp; g.c_plane = (int64_t)c.mpad * c.npad; g.rows_c = c.npad;
         (void)launch_gemm_stream(s, an.sc ? EPI_DLOSS_ANCHOR : EPI_DLOSS, g, c.npad, tn, 1,
-                                 c.tile_rows == 128 ? 32 : 64, c.nb);
+                                 stream_wave_rows(c.tile_rows, c.npad, tn, 1), c.nb);
         return;
     }
     // outside plane mode a float32 iteration has float32 X
@@ -1994,7 +2008,8 @@ void launch_bwd(hipStream_t s, int xtype, bool iter_f64, const void *XT, const v
     if (c.yp) {  // plane mode: stream the tiled X^T against the planes of R
         g.A = c.xttile; g.lda = c.nkb_xt; g.rows_a = c.pm;
         g.B = c.rp; g.b_plane = (int64_t)c.mpad * c.npad;
-        (void)launch_gemm_stream(s, EPI_STORE, g, c.pm, tn, gsplit, c.tile_rows == 128 ? 32 : 64, c.nb);
+        (void)launch_gemm_stream(s, EPI_STORE, g, c.pm, tn, gsplit, stream_wave_rows(c.tile_rows, c.pm, tn, gsplit),
+                                 c.nb);
         return;
     }
     if (iter_f64) {

@@ -238,12 +238,13 @@ extern "C" int autotune(const kbnb_problem_desc *desc, const kbnb_node_desc *nod
         destroy_problem(P);
         if (rc) return rc;
         const int tr_rule = (int)info[9], sr_rule = (int)info[10];
-        const bool streaming = tr_rule >= 128;
-        const int tiles[3] = {0, streaming ? 128 : 32, streaming ? 256 : 64};
+        const bool streaming = desc->x_dtype == KBNB_DTYPE_BF16 && info[8] != KBNB_ITER_F64;
+        const int tiles[4] = {0, streaming ? 64 : 32, streaming ? 128 : 64, streaming ? 256 : 0};
+        const int nt = streaming ? 4 : 3;
         const int splits[3] = {0, std::max(64, sr_rule / 2), 2 * sr_rule};
         double best_r = result->rate;  // the rule's rate from the first stage
         int bt = 0, bs = 0, t2 = 0;
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < nt; ++a) {
             for (int b = 0; b < 3; ++b) {
                 if (a == 0 && b == 0) continue;  // the first stage measured the rule
                 if (a > 0 && tiles[a] == tr_rule) continue;  // the rule under another name

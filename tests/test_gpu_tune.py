@@ -114,8 +114,11 @@ def test_tile_rows_apply_to_their_kernel_only():
         with pytest.raises(K.KbnbError) as e:
             K.create_from_instance(inst, batch_width=8, tile_rows=bad)
         assert e.value.code == -1
-    h = K.create_from_instance(bf, batch_width=8, tile_rows=128)
-    assert K.problem_info(h)["tile_rows"] == 128
-    res = K.bound_nodes(h, W.random_nodes(20, 8, 2, 5, seed=4), rel_tol=1e-6)
-    assert all(r["status"] == K.CONVERGED for r in res)
-    K.destroy_problem(h)
+    # the streaming kernel takes 64-, 128- and 256-row tiles; its rule picks
+    # the tallest that still gives a launch 256 workgroups, here the shortest
+    for tr, want in ((128, 128), (64, 64), (0, 64)):
+        h = K.create_from_instance(bf, batch_width=8, tile_rows=tr)
+        assert K.problem_info(h)["tile_rows"] == want
+        res = K.bound_nodes(h, W.random_nodes(20, 8, 2, 5, seed=4), rel_tol=1e-6)
+        assert all(r["status"] == K.CONVERGED for r in res)
+        K.destroy_problem(h)
