@@ -433,3 +433,20 @@ def test_node_bounds_wide_nodes(n, p, k, loss, dtype, it):
         assert list(g["support"]) == list(s_o)
         assert g["branch_index"] == br_o
     K.destroy_problem(h)
+
+
+@pytest.mark.parametrize("n,p,rho,loss,dtype", [(700, 50, 0.5, W.SQUARED, "f64"),
+                                                (3000, 400, 0.9, W.LOGISTIC, "bf16")])
+def test_step_constant_is_the_largest_eigenvalue(n, p, rho, loss, dtype):
+    """L = 1.02 c_l lambda_max(X^T X) (c_l = 2 squared, 1/4 logistic), with
+    lambda_max from the device's Lanczos iteration on the stored X, against
+    numpy's symmetric eigensolver in float64 (rho 0.9: a correlated design
+    with a large, well separated top eigenvalue)."""
+    announce(f"step constant {n}x{p} rho {rho} {dtype}")
+    inst = W.small_instance(n, p, 5, loss, seed=90, rho=rho, dtype=dtype)
+    h = K.create_from_instance(inst, batch_width=8)
+    L = K.problem_info(h)["L"]
+    K.destroy_problem(h)
+    lam = np.linalg.eigvalsh(inst.X.T @ inst.X)[-1]
+    c = 2.0 if loss == W.SQUARED else 0.25
+    assert L == pytest.approx(1.02 * c * lam, rel=1e-9)
