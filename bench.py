@@ -205,7 +205,8 @@ def large_leg(K, W, torch, args):
     torch.cuda.synchronize()
     t = time.perf_counter()
     h = K.create_problem(X, y, d["k"], d["loss"], d["lambda2"], d["M"], dtype=d["dtype"],
-                         batch_width=args.large_batch, cert_period=16)
+                         batch_width=args.large_batch, cert_period=16, tile_rows=args.large_tile_rows,
+                         split_rows=args.large_split_rows)
     t_setup = time.perf_counter() - t
     log(f"large: problem ready in {t_setup:.1f}s: {K.problem_info(h)}")
     del X, y
@@ -540,6 +541,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cert-period", type=int, default=16)
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="contraction tile height of the main workload (0: launch-size rule)")
+    ap.add_argument("--split-rows", type=int, default=0,
+                    help="split-K depth of the main workload (0: launch-size rule)")
     ap.add_argument("--window", type=int, default=1,
                     help="batches in flight (the next is submitted when one completes)")
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -570,6 +575,10 @@ def main():
     ap.add_argument("--large", type=int, default=1,
                     help="run the 100000 x 5000 bfloat16 logistic node-bound leg")
     ap.add_argument("--large-batch", type=int, default=256)
+    ap.add_argument("--large-tile-rows", type=int, default=0,
+                    help="contraction tile height of the large problem (0: launch-size rule)")
+    ap.add_argument("--large-split-rows", type=int, default=0,
+                    help="split-K depth of the large problem (0: launch-size rule)")
     ap.add_argument("--reopt-supports", type=int, default=128,
                     help="supports in the large problem's re-optimisation probe (0: skip)")
     ap.add_argument("--importance-seconds", type=float, default=20.0,
@@ -613,7 +622,8 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
     h = K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
-                         batch_width=args.batch, cert_period=args.cert_period)
+                         batch_width=args.batch, cert_period=args.cert_period, tile_rows=args.tile_rows,
+                         split_rows=args.split_rows)
     t_setup = time.perf_counter() - t_setup
     info = K.problem_info(h)
     log(f"problem ready in {t_setup:.2f}s: {info}")
