@@ -40,6 +40,8 @@
 #include <queue>
 #include <set>
 #include <string>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/kbnb.h"
@@ -67,16 +69,24 @@ struct Open {
     CertPtr cert;             // audit mode: the certificate of lb (null at the root)
 };
 
-// Queue order: best bound (smaller bound, then deeper, then first in), or
-// depth first (deeper, then smaller bound, then first in).
+// Queue entry: the ordering key kept beside the node, so heap operations
+// compare entries without touching the nodes.  Order: best bound (smaller
+// bound, then deeper, then first in), or depth first (deeper, then smaller
+// bound, then first in).
+struct OpenRef {
+    double lb;
+    int depth;
+    uint64_t seq;
+    Open *node;
+};
 struct OpenCmp {
     bool dfs = false;
-    bool operator()(const Open *a, const Open *b) const
+    bool operator()(const OpenRef &a, const OpenRef &b) const
     {
-        if (dfs && a->depth != b->depth) return a->depth < b->depth;
-        if (a->lb != b->lb) return a->lb > b->lb;
-        if (a->depth != b->depth) return a->depth < b->depth;
-        return a->seq > b->seq;
+        if (dfs && a.depth != b.depth) return a.depth < b.depth;
+        if (a.lb != b.lb) return a.lb > b.lb;
+        if (a.depth != b.depth) return a.depth < b.depth;
+        return a.seq > b.seq;
     }
 };
 
@@ -92,6 +102,21 @@ struct Candidate {
     double value;
     std::vector<double> beta;
 };
+
+// hash of an index sequence (supports as keys of the host's lookup tables)
+struct SeqHash {
+    size_t operator()(const std::vector<int32_t> &v) const
+    {
+        uint64_t h = 0x9E3779B97F4A7C15ull ^ v.size();
+        for (int32_t x : v) {
+            h ^= (uint64_t)(uint32_t)x + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+            h *= 0xBF58476D1CE4E5B9ull;
+        }
+        return (size_t)(h ^ (h >> 31));
+    }
+};
+template <typename V> using SeqMap = std::unordered_map<std::vector<int32_t>, V, SeqHash>;
+using SeqSet = std::unordered_set<std::vector<int32_t>, SeqHash>;
 
 }  // namespace
 
@@ -130,6 +155,7 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
                          const double *warm, double tol, int max_iter);
 int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double *coefs, int32_t *status,
                           int32_t *iters, double *coefs_lb);
+bool eval_supports_ready(kbnb_problem *P);
 int support_groups(kbnb_problem *P, int count, int maxlen);
 }  // namespace kbnb
 
@@ -168,7 +194,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     const bool dfs = opt->node_order == 1;
     const bool audit = opt->audit != 0;
     auto leaves = std::make_shared<std::vector<kbnb::AuditLeaf>>();
-    std::map<std::vector<int32_t>, CertPtr> support_cert;  // audit: certificate of each support's bound
+    SeqMap<CertPtr> support_cert;  // audit: certificate of each support's bound
     auto complement = [&](const std::vector<int32_t> &S) {
         std::vector<char> ins((size_t)p, 0);
         for (int32_t j : S) ins[(size_t)j] = 1;
@@ -181,28 +207,37 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                         const CertPtr &cert) {
         if (audit) leaves->push_back(kbnb::AuditLeaf{kind, in, out, bound, cert});
     };
-    std::priority_queue<Open *, std::vector<Open *>, OpenCmp> open(OpenCmp{dfs});
-    std::multiset<double> open_lbs;  // bounds of the open nodes (the least is the queue's)
+    std::priority_queue<OpenRef, std::vector<OpenRef>, OpenCmp> open(OpenCmp{dfs});
+    // bounds of the open nodes, kept in depth-first order only: in best-bound
+    // order the least bound is the queue's top
+    std::multiset<double> open_lbs;
     auto push_open = [&](Open *o) {
-        open_lbs.insert(o->lb);
-        open.push(o);
+        if (dfs) open_lbs.insert(o->lb);
+        open.push(OpenRef{o->lb, o->depth, o->seq, o});
     };
     auto pop_open = [&]() {
-        Open *o = open.top();
+        Open *o = open.top().node;
         open.pop();
-        open_lbs.erase(open_lbs.find(o->lb));
+        if (dfs) open_lbs.erase(open_lbs.find(o->lb));
         return o;
     };
-    std::map<uint64_t, Flight> flight;
+    auto least_open = [&]() {
+        if (open.empty()) return (double)INFINITY;
+        return dfs ? *open_lbs.begin() : open.top().lb;
+    };
+    std::unordered_map<uint64_t, Flight> flight;
+    flight.reserve((size_t)4 * m);
     std::multiset<double> flight_lb;
-    std::set<std::vector<int32_t>> evaluated;            // supports submitted or known
-    std::map<std::vector<int32_t>, Candidate> recorded;  // Rashomon mode: within the threshold when found
-    std::multiset<double> recorded_vals;
+    SeqSet evaluated;             // supports submitted or known
+    SeqMap<Candidate> recorded;   // Rashomon mode: within the threshold when found
+    // the capN smallest recorded values (a max-heap: its top is the N-th best
+    // once it holds capN of them)
+    std::priority_queue<double> best_vals;
     // Rashomon leaves: a leaf's certified bound is its support's evaluated
     // bound; leaves whose support is still being evaluated wait for it
     // (with their parent's bound, which holds meanwhile)
-    std::map<std::vector<int32_t>, double> support_lb;
-    std::map<std::vector<int32_t>, std::pair<double, CertPtr>> leaf_waiting;
+    SeqMap<double> support_lb;
+    SeqMap<std::pair<double, CertPtr>> leaf_waiting;
     uint64_t seq = 0, next_tag = 1;
     double UB = INFINITY;
     std::vector<int32_t> best_support;
@@ -213,11 +248,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     // Rashomon threshold: (1 + eps) UB, capped by the N-th best recorded value
     auto tau = [&]() {
         const double t = (1.0 + eps) * UB;
-        if (capN > 0 && (int64_t)recorded_vals.size() >= capN) {
-            auto it = recorded_vals.begin();
-            std::advance(it, capN - 1);
-            return std::min(t, *it);
-        }
+        if (capN > 0 && (int64_t)best_vals.size() >= capN) return std::min(t, best_vals.top());
         return t;
     };
     auto prunable = [&](double lb) { return rs ? lb > tau() : lb >= UB - prune_rel * std::fabs(UB); };
@@ -251,7 +282,14 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         }
         if (rs && std::isfinite(v) && v <= tau() && !recorded.count(S)) {
             recorded[S] = Candidate{v, std::vector<double>(beta, beta + p)};
-            recorded_vals.insert(v);
+            if (capN > 0) {
+                if ((int64_t)best_vals.size() < capN) {
+                    best_vals.push(v);
+                } else if (v < best_vals.top()) {
+                    best_vals.pop();
+                    best_vals.push(v);
+                }
+            }
         }
     };
 
@@ -341,12 +379,16 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     };
     // collect the batch in flight and launch the pending one
     auto cycle_supports = [&]() -> int {
+        // the batch in flight is collected once it has finished: the loop
+        // keeps bounding nodes meanwhile instead of waiting for it
+        if (!inflight.empty() && !kbnb::eval_supports_ready(P)) return 0;
         int erc = collect_supports();
         return erc ? erc : launch_supports();
     };
     // everything evaluated (blocking)
     auto flush_supports = [&]() -> int {
-        int erc = cycle_supports();
+        int erc = collect_supports();  // waits for the batch in flight
+        if (!erc) erc = launch_supports();
         return erc ? erc : collect_supports();
     };
     // a support evaluation: the node J1 = S, J0 = complement
@@ -393,15 +435,15 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
     for (;;) {
         // drop open nodes that the incumbent prunes: when the least open
         // bound is prunable, every open node is
-        if (!open_lbs.empty() && prunable(*open_lbs.begin())) {
-            leaf_lb = std::min(leaf_lb, *open_lbs.begin());
+        if (!open.empty() && prunable(least_open())) {
+            leaf_lb = std::min(leaf_lb, least_open());
             while (!open.empty()) {
                 Open *o = pop_open();
                 add_leaf(0, o->in, o->out, o->lb, o->cert);
                 delete o;
             }
         }
-        double lb_open = open_lbs.empty() ? INFINITY : *open_lbs.begin();
+        double lb_open = least_open();
         double lb_fl = flight_lb.empty() ? INFINITY : *flight_lb.begin();
         global_lb = std::min(lb_open, lb_fl);
         const bool batch_pending = !pending.empty() || !inflight.empty();

@@ -1840,6 +1840,16 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
     return KBNB_OK;
 }
 
+// True when no support batch is in flight or the one in flight has reached
+// its last enqueued step (eval_supports_collect then returns without waiting,
+// unless split-row supports need more steps).
+bool eval_supports_ready(kbnb_problem *P)
+{
+    std::lock_guard<std::mutex> g(P->api_mu);
+    if (P->s_count == 0 || !P->sev) return true;
+    return hipEventQuery(P->sev) == hipSuccess;
+}
+
 // Workgroups per support that eval_supports_launch would use for a batch of
 // `count` supports of at most maxlen features.
 int support_groups(kbnb_problem *P, int count, int maxlen)
