@@ -633,21 +633,40 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                     wi.push_back(q);
                     wv.push_back(beta[q]);
                 }
-            for (int side = 0; side < 2; ++side) {
+            // children z_j = 1 (a copy of the parent's sets) and z_j = 0 (the
+            // parent's sets moved); both index lists stay sorted.  The z_j = 0
+            // child comes first in queue order among equals (the smaller seq).
+            const uint64_t seq0 = seq;
+            seq += 2;
+            for (int side = 1; side >= 0; --side) {
                 Open *c = new Open();
                 c->lb = lb;
                 c->cert = cert;
                 c->depth = o->depth + 1;
-                c->seq = seq++;
-                c->in = o->in;
-                c->out = o->out;
-                std::vector<int32_t> &grow = (side == 0) ? c->out : c->in;  // both stay sorted
-                grow.insert(std::upper_bound(grow.begin(), grow.end(), j), j);
-                for (size_t r = 0; r < wi.size(); ++r) {
-                    if (side == 0 && wi[r] == j) continue;  // z_j = 0 zeroes beta_j
-                    c->wi.push_back(wi[r]);
-                    c->wv.push_back(wv[r]);
+                c->seq = seq0 + (uint64_t)side;
+                if (side == 1) {
+                    c->in = o->in;
+                    c->out = o->out;
+                    c->wi = wi;
+                    c->wv = wv;
+                } else {
+                    c->in = std::move(o->in);
+                    c->out = std::move(o->out);
+                    // z_j = 0 zeroes beta_j
+                    size_t w = 0;
+                    for (size_t r = 0; r < wi.size(); ++r)
+                        if (wi[r] != j) {
+                            wi[w] = wi[r];
+                            wv[w] = wv[r];
+                            ++w;
+                        }
+                    wi.resize(w);
+                    wv.resize(w);
+                    c->wi = std::move(wi);
+                    c->wv = std::move(wv);
                 }
+                std::vector<int32_t> &grow = (side == 0) ? c->out : c->in;
+                grow.insert(std::upper_bound(grow.begin(), grow.end(), j), j);
                 push_open(c);
             }
             delete o;

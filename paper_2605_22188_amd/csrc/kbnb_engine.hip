@@ -175,6 +175,9 @@ struct kbnb_problem {
     hipStream_t stream = nullptr;
     hipStream_t sstream = nullptr;  // support re-optimisation (created on first use)
     void *sbuf = nullptr;           // its device buffers, grown on demand
+    char *spin = nullptr;           // pinned host mirror of sbuf's input and output regions
+    size_t spin_bytes = 0;
+    size_t s_in_bytes = 0, s_out_off = 0, s_out_bytes = 0;  // those regions of the batch in flight
     size_t sbuf_bytes = 0;
     hipEvent_t sev = nullptr;       // end of the support batch in flight
     int s_count = 0;                // that batch: supports and stored coefficients
@@ -1056,6 +1059,7 @@ static void free_problem(kbnb_problem *P)
     if (P->sstream) (void)hipStreamSynchronize(P->sstream);
     if (P->sev) (void)hipEventDestroy(P->sev);
     if (P->sbuf) (void)hipFree(P->sbuf);
+    if (P->spin) (void)hipHostFree(P->spin);
     if (P->sstream) (void)hipStreamDestroy(P->sstream);
     if (P->gstream) (void)hipStreamDestroy(P->gstream);
     if (P->stream && P->own_stream) (void)hipStreamDestroy(P->stream);
@@ -1815,9 +1819,26 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
     P->s_coef_lb = (double *)b; b += b_clb;
     void *dwork = b_work ? (void *)b : nullptr;
     hipStream_t s = P->sstream;
-    HIP_TRY(hipMemcpyAsync(dlab, lab, 4 * C, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(doff, off, 8 * (N + 1), hipMemcpyHostToDevice, s));
-    if (warm) HIP_TRY(hipMemcpyAsync(dwarm, warm, 8 * C, hipMemcpyHostToDevice, s));
+    // inputs and outputs pass through a pinned mirror of the device buffer's
+    // layout: one copy each way
+    const size_t in_bytes = b_lab + b_off + b_warm, out_off = in_bytes,
+                 out_bytes = b_coef + b_val + b_low + b_st + b_it + b_clb;
+    if (in_bytes + out_bytes > P->spin_bytes) {
+        if (P->spin) (void)hipHostFree(P->spin);
+        P->spin = nullptr;
+        P->spin_bytes = 0;
+        const size_t want = std::max(in_bytes + out_bytes, (size_t)1 << 20);
+        if (hipHostMalloc((void **)&P->spin, want) != hipSuccess)
+            return fail(KBNB_E_OUT_OF_MEMORY, "hipHostMalloc failed");
+        P->spin_bytes = want;
+    }
+    memcpy(P->spin, lab, 4 * C);
+    memcpy(P->spin + b_lab, off, 8 * (N + 1));
+    if (warm) memcpy(P->spin + b_lab + b_off, warm, 8 * C);
+    HIP_TRY(hipMemcpyAsync(dlab, P->spin, warm ? in_bytes : b_lab + b_off, hipMemcpyHostToDevice, s));
+    P->s_in_bytes = in_bytes;
+    P->s_out_off = out_off;
+    P->s_out_bytes = out_bytes;
     SupportLaunch &SL = P->s_launch;
     SL = SupportLaunch{};
     SL.xtype = P->xtype; SL.XT = P->XT; SL.npad = P->npad; SL.n = P->n; SL.loss = P->loss; SL.y = P->y;
@@ -1834,7 +1855,6 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
     if (lrc != 0) return fail(KBNB_E_DEVICE, "support re-optimisation launch failed");
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(P->sev, s));
-    // the pageable-source copies above have consumed the inputs by now
     P->s_count = count;
     P->s_coefs = (int64_t)C;
     return KBNB_OK;
@@ -1889,13 +1909,17 @@ int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double
         HIP_TRY(hipStreamSynchronize(s));
         P->s_steps_hint = std::max(16, 1 + *std::max_element(it.begin(), it.end()));
     }
-    HIP_TRY(hipMemcpyAsync(values, P->s_val, 8 * N, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(lower, P->s_low, 8 * N, hipMemcpyDeviceToHost, s));
-    if (coefs && C) HIP_TRY(hipMemcpyAsync(coefs, P->s_coef, 8 * C, hipMemcpyDeviceToHost, s));
-    if (status) HIP_TRY(hipMemcpyAsync(status, P->s_st, 4 * N, hipMemcpyDeviceToHost, s));
-    if (iters) HIP_TRY(hipMemcpyAsync(iters, P->s_it, 4 * N, hipMemcpyDeviceToHost, s));
-    if (coefs_lb && C) HIP_TRY(hipMemcpyAsync(coefs_lb, P->s_coef_lb, 8 * C, hipMemcpyDeviceToHost, s));
+    // every output in one copy into the pinned mirror, then to the caller
+    char *pm = P->spin + P->s_out_off;
+    HIP_TRY(hipMemcpyAsync(pm, P->s_coef, P->s_out_bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    auto host = [&](const void *dev) { return pm + ((const char *)dev - (const char *)P->s_coef); };
+    memcpy(values, host(P->s_val), 8 * N);
+    memcpy(lower, host(P->s_low), 8 * N);
+    if (coefs && C) memcpy(coefs, host(P->s_coef), 8 * C);
+    if (status) memcpy(status, host(P->s_st), 4 * N);
+    if (iters) memcpy(iters, host(P->s_it), 4 * N);
+    if (coefs_lb && C) memcpy(coefs_lb, host(P->s_coef_lb), 8 * C);
     return KBNB_OK;
 }
 
