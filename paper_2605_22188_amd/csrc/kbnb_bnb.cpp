@@ -59,13 +59,20 @@ struct Cert {
 };
 typedef std::shared_ptr<const Cert> CertPtr;
 
+struct WarmStart {
+    std::vector<int32_t> idx;
+    std::vector<double> val;
+};
+
 struct Open {
     double lb;
     int depth;
     uint64_t seq;
     std::vector<int32_t> in, out;
-    std::vector<int32_t> wi;  // warm start, sparse
-    std::vector<double> wv;
+    // warm start: the parent's iterate (sparse, shared by both children),
+    // with coordinate warm_skip zeroed (the z_j = 0 child; -1 for none)
+    std::shared_ptr<const WarmStart> warm;
+    int32_t warm_skip = -1;
     CertPtr cert;             // audit mode: the certificate of lb (null at the root)
 };
 
@@ -516,7 +523,7 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             d.fixed_in = o->in.data();
             d.n_out = (int32_t)o->out.size();
             d.fixed_out = o->out.data();
-            if (!o->wi.empty()) {
+            if (o->warm) {
                 ++nwarm;
             }
             // the engine stops a node at bound >= ub - 1e-6 |ub|; in Rashomon
@@ -547,9 +554,11 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             warm_flat.assign((size_t)p * nwarm, 0.0);
             for (auto &d : batch) {
                 Flight &f = flight[d.tag];
-                if (f.kind == FL_NODE && !f.node->wi.empty()) {
+                if (f.kind == FL_NODE && f.node->warm) {
                     double *w = warm_flat.data() + (size_t)p * wsi++;
-                    for (size_t r = 0; r < f.node->wi.size(); ++r) w[f.node->wi[r]] = f.node->wv[r];
+                    const WarmStart &ws = *f.node->warm;
+                    for (size_t r = 0; r < ws.idx.size(); ++r) w[ws.idx[r]] = ws.val[r];
+                    if (f.node->warm_skip >= 0) w[f.node->warm_skip] = 0.0;
                     d.warm_start = w;
                 }
             }
@@ -620,19 +629,31 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 continue;
             }
             if (j < 0) {  // every free coordinate is zero: the first free index
-                std::vector<char> dec(p, 0);
-                for (int q : o->in) dec[q] = 1;
-                for (int q : o->out) dec[q] = 1;
-                for (int q = 0; q < p && j < 0; ++q)
-                    if (!dec[q]) j = q;
-            }
-            std::vector<int32_t> wi;
-            std::vector<double> wv;
-            for (int q = 0; q < p; ++q)
-                if (beta[q] != 0.0) {
-                    wi.push_back(q);
-                    wv.push_back(beta[q]);
+                // (the smallest index in neither sorted list)
+                size_t a = 0, b = 0;
+                for (int q = 0; q < p; ++q) {
+                    if (a < o->in.size() && o->in[a] == q) { ++a; continue; }
+                    if (b < o->out.size() && o->out[b] == q) { ++b; continue; }
+                    j = q;
+                    break;
                 }
+            }
+            // the parent's iterate, sparse, shared by both children
+            std::shared_ptr<WarmStart> ws;
+            {
+                size_t nnz = 0;
+                for (int q = 0; q < p; ++q) nnz += (beta[q] != 0.0);
+                if (nnz) {
+                    ws = std::make_shared<WarmStart>();
+                    ws->idx.reserve(nnz);
+                    ws->val.reserve(nnz);
+                    for (int q = 0; q < p; ++q)
+                        if (beta[q] != 0.0) {
+                            ws->idx.push_back(q);
+                            ws->val.push_back(beta[q]);
+                        }
+                }
+            }
             // children z_j = 1 (a copy of the parent's sets) and z_j = 0 (the
             // parent's sets moved); both index lists stay sorted.  The z_j = 0
             // child comes first in queue order among equals (the smaller seq).
@@ -644,26 +665,14 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 c->cert = cert;
                 c->depth = o->depth + 1;
                 c->seq = seq0 + (uint64_t)side;
+                c->warm = ws;
                 if (side == 1) {
                     c->in = o->in;
                     c->out = o->out;
-                    c->wi = wi;
-                    c->wv = wv;
                 } else {
                     c->in = std::move(o->in);
                     c->out = std::move(o->out);
-                    // z_j = 0 zeroes beta_j
-                    size_t w = 0;
-                    for (size_t r = 0; r < wi.size(); ++r)
-                        if (wi[r] != j) {
-                            wi[w] = wi[r];
-                            wv[w] = wv[r];
-                            ++w;
-                        }
-                    wi.resize(w);
-                    wv.resize(w);
-                    c->wi = std::move(wi);
-                    c->wv = std::move(wv);
+                    c->warm_skip = j;  // z_j = 0 zeroes beta_j
                 }
                 std::vector<int32_t> &grow = (side == 0) ? c->out : c->in;
                 grow.insert(std::upper_bound(grow.begin(), grow.end(), j), j);
