@@ -1849,7 +1849,7 @@ int eval_supports_launch(kbnb_problem *P, const int32_t *lab, const int64_t *off
     SL.groups = groups; SL.work = dwork; SL.work_bytes = b_work;
     // split rows: as many step launches as the last batch needed to start
     // with; collect adds more until every support has finished
-    P->s_steps = (groups > 1) ? std::min(max_iter + 1, P->s_steps_hint) : 0;
+    P->s_steps = b_work ? std::min(max_iter + 1, P->s_steps_hint) : 0;
     const int lrc = launch_support_start(s, SL, P->s_steps);
     if (lrc == -1) return fail(KBNB_E_INVALID_ARGUMENT, "support too long");
     if (lrc != 0) return fail(KBNB_E_DEVICE, "support re-optimisation launch failed");
@@ -1888,7 +1888,7 @@ int eval_supports_collect(kbnb_problem *P, double *values, double *lower, double
     hipStream_t s = P->sstream;
     HIP_TRY(hipEventSynchronize(P->sev));
     const SupportLaunch &SL = P->s_launch;
-    if (SL.groups > 1) {
+    if (SL.work) {
         // more step launches until every support has finished (max_iter + 1
         // of them finish all), doubling each time
         for (;;) {

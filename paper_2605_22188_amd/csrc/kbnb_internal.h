@@ -160,9 +160,10 @@ void launch_reliance(hipStream_t s, int xtype, const void *XT, int64_t npad, int
                      const int32_t *lab, const int64_t *off, const double *coef, int nrec, double *out);
 // Batched support re-optimisation in float64 (supports of at most 64
 // features): one batch of supports lab[off[i] .. off[i + 1]) with its
-// outputs (coefficients in the layout of lab).  With groups > 1 the rows of
-// each support are split over that many workgroups: a set-up launch, then
-// one launch per step, the supports' state kept in `work` between them.
+// outputs (coefficients in the layout of lab).  With a work area the rows of
+// each support are split over `groups` workgroups (one or more): a set-up
+// launch, then one launch per step, the supports' state kept in `work`
+// between them; without one, one workgroup per support runs every step.
 constexpr int SUPPORT_EVAL_MAX = 64;
 struct SupportLaunch {
     int xtype = 0;
@@ -184,18 +185,18 @@ struct SupportLaunch {
     size_t work_bytes = 0;
 };
 // Workgroups per support for a batch of `count` supports of at most maxlen
-// features over n rows (want: 0 automatic, 1 one workgroup, g >= 2 that
-// many); *work_bytes gets the bytes of device work area the split needs (0
-// for one workgroup).
+// features over n rows (want: 0 automatic, 1 the one-workgroup kernel,
+// g >= 2 that many); *work_bytes gets the bytes of device work area the
+// step-launch kernels need (0 for the one-workgroup kernel).
 int support_eval_plan(int xtype, int n, int count, int maxlen, int want, size_t *work_bytes);
-// Enqueue the batch: the whole of it with one workgroup per support;
-// otherwise the set-up and the first `steps` step launches.  -1 for a
+// Enqueue the batch: the whole of it on the one-workgroup kernel (no work
+// area); otherwise the set-up and the first `steps` step launches.  -1 for a
 // support longer than SUPPORT_EVAL_MAX or a work area too small.
 int launch_support_start(hipStream_t s, const SupportLaunch &L, int steps);
-// groups > 1: `steps` more step launches (a launch leaves finished supports
-// alone; every support has finished after max_iter + 1 of them)
+// with a work area: `steps` more step launches (a launch leaves finished
+// supports alone; every support has finished after max_iter + 1 of them)
 int launch_support_steps(hipStream_t s, const SupportLaunch &L, int steps);
-// groups > 1: device counter of the supports that have finished
+// with a work area: device counter of the supports that have finished
 const int32_t *support_done_counter(const SupportLaunch &L);
 // Arguments of the MFMA contraction kernels (kbnb_kernels.hip):
 // C[col][row] = sum_k A[row][k] * B[col][k] over the workgroup's k split.

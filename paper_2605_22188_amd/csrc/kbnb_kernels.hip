@@ -2494,11 +2494,32 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
 // finishes at step max_iter at the latest, so max_iter + 1 step launches
 // finish every support.
 // ---------------------------------------------------------------------------
+// rows [r0, r1) of workgroup gg; block starts are multiples of RT
+template <int RT = 1>
 __device__ __forceinline__ void support_rows(const SupportArgs &a, int gg, int &r0, int &r1)
 {
-    const int per = (a.n + a.groups - 1) / a.groups;
+    const int per = ((a.n + a.groups - 1) / a.groups + RT - 1) / RT * RT;
     r0 = min(a.n, gg * per);
     r1 = min(a.n, r0 + per);
+}
+
+// Rows per lane and load in the split-row step: the lane reads RT consecutive
+// rows of each of the KB column slots with one vector load, 256 bytes of
+// registers for the KB loads together (128 above 16 slots, where the KB
+// gradient sums take the rest of the registers).
+template <typename TA, int KB> struct MwRows {
+    static constexpr int B = (KB <= 16 ? 256 : 128) / (KB * (int)sizeof(TA));
+    static constexpr int RT = B < 1 ? 1 : B;
+};
+template <int NB> struct RawVec;
+template <> struct RawVec<16> { typedef uint4 t; };
+template <> struct RawVec<8> { typedef uint2 t; };
+template <> struct RawVec<4> { typedef uint32_t t; };
+template <> struct RawVec<2> { typedef uint16_t t; };
+// element j of RT consecutive stored values loaded as one raw vector
+template <typename TA, typename RV> __device__ __forceinline__ double raw_elem(const RV &v, int j)
+{
+    return cvt_d(reinterpret_cast<const TA *>(&v)[j]);
 }
 
 // sum_{q < ng} v[q * stride], added in q order, with eight loads in flight
@@ -2638,6 +2659,7 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
     __shared__ int32_t L[KB];
     __shared__ double Pt[KB], Bv[KB], Yv[KB], Bb[KB], Bd[KB], Bn[KB];
     __shared__ double red[4][KB + 2];
+    __shared__ double rsum[256];
     __shared__ double sc[8];
     __shared__ int s_last;
     const TA *XT = reinterpret_cast<const TA *>(a.XT);
@@ -2649,63 +2671,61 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
     const bool cert = (it % a.cert_every) == 0 || it >= a.max_iter;
     const int64_t o0 = a.off[m];
     const int kl = (int)(a.off[m + 1] - o0);
+    constexpr int RT = MwRows<TA, KB>::RT;
+    typedef typename RawVec<RT * (int)sizeof(TA)>::t RV;
     int r0, r1;
-    support_rows(a, gg, r0, r1);
+    support_rows<RT>(a, gg, r0, r1);
     double *vec = a.vec + (int64_t)m * 4 * KB;
     if (tid < KB) {
         L[tid] = (tid < kl) ? a.lab[o0 + tid] : 0;
         Pt[tid] = vec[(cert ? 0 : 1) * KB + tid];
     }
     __syncthreads();
-    // this workgroup's rows: gradient at Y, or (cert) the certificate terms at beta
+    // this workgroup's rows: gradient at Y, or (cert) the certificate terms
+    // at beta.  Lane t takes rows i0 .. i0 + RT - 1 (i0 a multiple of RT, so
+    // the loads are aligned; rows up to npad exist and are zero past n, and
+    // rows at or past r1 are masked).  Every column slot is read (slots past
+    // the support hold column 0 with weight 0), so the KB loads are issued
+    // together.
     {
         double g[KB];
 #pragma unroll
         for (int r = 0; r < KB; ++r) g[r] = 0.0;
         double al = 0.0, ac = 0.0;
-        constexpr int U = (KB <= 16) ? 4 : ((KB <= 32) ? 2 : 1);
-        for (int i0 = r0 + tid; i0 < r1; i0 += 256 * U) {
-            int64_t ri[U];
-            bool ok[U];
+        for (int i0 = r0 + tid * RT; i0 < r1; i0 += 256 * RT) {
+            RV xr[KB];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                ok[u] = i0 + 256 * u < r1;
-                ri[u] = ok[u] ? i0 + 256 * u : r0;
-            }
-            double sv[U], yv[U];
+            for (int r = 0; r < KB; ++r) xr[r] = *reinterpret_cast<const RV *>(XT + (int64_t)L[r] * a.npad + i0);
+            bool ok[RT];
+            double yv[RT], sv[RT];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < RT; ++u) {
+                ok[u] = i0 + u < r1;
+                yv[u] = ok[u] ? a.y[i0 + u] : 0.0;
                 sv[u] = 0.0;
-                yv[u] = a.y[ri[u]];
             }
-            // every column slot is read (slots past the support hold column
-            // 0 with weight 0), so all U * KB loads are issued together
 #pragma unroll
-            for (int r = 0; r < KB; ++r) {
-                const TA *col = XT + (int64_t)L[r] * a.npad;
+            for (int r = 0; r < KB; ++r)
 #pragma unroll
-                for (int u = 0; u < U; ++u) sv[u] += cvt_d(col[ri[u]]) * Pt[r];
-            }
-            double dv[U];
+                for (int u = 0; u < RT; ++u) sv[u] += raw_elem<TA>(xr[r], u) * Pt[r];
+            double dv[RT];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const double yi = yv[u];
+            for (int u = 0; u < RT; ++u) {
                 if (cert) {
                     double z, lv, cv;
-                    cert_terms(a.loss, sv[u], yi, z, lv, cv);
+                    cert_terms(a.loss, sv[u], yv[u], z, lv, cv);
                     al += ok[u] ? lv : 0.0;
                     ac += ok[u] ? cv : 0.0;
                     dv[u] = ok[u] ? z : 0.0;
                 } else {
-                    dv[u] = ok[u] ? dloss_d(a.loss, sv[u], yi) : 0.0;
+                    dv[u] = ok[u] ? dloss_d(a.loss, sv[u], yv[u]) : 0.0;
                 }
             }
 #pragma unroll
             for (int r = 0; r < KB; ++r) {
-                const TA *col = XT + (int64_t)L[r] * a.npad;
                 double acc = 0.0;
 #pragma unroll
-                for (int u = 0; u < U; ++u) acc += cvt_d(col[ri[u]]) * dv[u];
+                for (int u = 0; u < RT; ++u) acc += raw_elem<TA>(xr[r], u) * dv[u];
                 g[r] += acc;  // unused past the support
             }
         }
@@ -2728,8 +2748,25 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
     if (tid < KB + 2 && (tid < kl || tid >= KB)) pp[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
     if (!support_last_arrival(a, m, &s_last)) return;
     // the last workgroup: the step's sums in group order, then the update
-    if (tid < KB + 2 && (tid < kl || tid >= KB))
-        red[0][tid] = sum_in_order(a.part + (int64_t)m * ng * (KB + 2) + tid, ng, KB + 2);
+    {
+        // the groups' partials in a fixed order: thread (c, h) adds groups
+        // h, h + H, ... of column c, then the H sums are added in h order
+        constexpr int C = KB + 2, H = 256 / C;
+        const int c = tid % C, h = tid / C;
+        double t = 0.0;
+        if (h < H && (c < kl || c >= KB)) {
+            const double *src = a.part + (int64_t)m * ng * C + c;
+#pragma unroll 4
+            for (int q = h; q < ng; q += H) t += src[(int64_t)q * C];
+        }
+        rsum[tid] = t;
+        __syncthreads();
+        if (tid < C && (tid < kl || tid >= KB)) {
+            double u = 0.0;
+            for (int q = 0; q < H; ++q) u += rsum[q * C + tid];
+            red[0][tid] = u;
+        }
+    }
     if (tid < KB) {
         Bv[tid] = vec[tid];
         Yv[tid] = vec[KB + tid];
@@ -2822,12 +2859,14 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
 }
 static int support_kb(int maxlen) { return maxlen <= 16 ? 16 : (maxlen <= 32 ? 32 : 64); }
 
-// Rows per workgroup that the automatic split aims at (a step's pass over
-// them takes a few row sweeps of the workgroup), the batch size in
-// workgroups it stops growing at, and the height below which one workgroup
-// per support is kept.
+// The automatic split: at most SUPPORT_MW_ROWS rows per workgroup (one
+// vectorised sweep of the workgroup), and about one workgroup per CU over
+// the batch (a step is a latency-bound chain per workgroup, so a second wave
+// of workgroups costs a second chain; measured at 100000 rows: 49 groups for
+// one support, 16 for 16, 2 for 128).  Below SUPPORT_MW_MIN_N rows the
+// one-workgroup kernel with its internal step loop is kept.
 constexpr int SUPPORT_MW_ROWS = 2048;
-constexpr int SUPPORT_MW_BLOCKS = 1024;
+constexpr int SUPPORT_MW_BLOCKS = 256;
 constexpr int SUPPORT_MW_MIN_N = 8192;
 
 struct MwLayout {
@@ -2861,8 +2900,8 @@ int support_eval_plan(int xtype, int n, int count, int maxlen, int want, size_t 
                        : std::min((n + SUPPORT_MW_ROWS - 1) / SUPPORT_MW_ROWS,
                                   std::max(1, SUPPORT_MW_BLOCKS / count));
     g = std::min(g, std::max(n, 1));  // no more workgroups than rows
-    g = std::min<int64_t>(g, INT32_MAX / count);
-    if (g < 2) return 1;
+    g = std::max(1, (int)std::min<int64_t>(g, INT32_MAX / count));
+    // the step-launch kernels, with g workgroups per support (also for g = 1)
     *work_bytes = mw_layout(count, g, support_kb(maxlen)).total;
     return g;
 }
@@ -2876,7 +2915,7 @@ static SupportArgs support_args(const SupportLaunch &L)
     a.max_iter = L.max_iter; a.cert_every = L.cert_every;
     a.beta_out = L.beta_out; a.beta_lb_out = L.beta_lb_out; a.value = L.value; a.lower = L.lower;
     a.status = L.status; a.iters = L.iters;
-    if (L.groups > 1) {
+    if (L.work) {
         const MwLayout l = mw_layout(L.count, L.groups, support_kb(L.maxlen));
         char *w = (char *)L.work;
         a.part = (double *)(w + l.part);
@@ -2916,7 +2955,7 @@ const int32_t *support_done_counter(const SupportLaunch &L)
 
 int launch_support_steps(hipStream_t s, const SupportLaunch &L, int steps)
 {
-    if (L.count <= 0 || L.groups < 2) return 0;
+    if (L.count <= 0 || !L.work) return 0;
     const SupportArgs a = support_args(L);
     const dim3 grid((unsigned)((size_t)L.count * L.groups));
     for (int i = 0; i < steps; ++i) KBNB_SUP_DISPATCH(k_support_mw_step, grid);
@@ -2928,7 +2967,7 @@ int launch_support_start(hipStream_t s, const SupportLaunch &L, int steps)
     if (L.count <= 0) return 0;
     if (L.maxlen > SUPPORT_EVAL_MAX) return -1;
     const SupportArgs a = support_args(L);
-    if (L.groups < 2) {
+    if (!L.work_bytes) {
         KBNB_SUP_DISPATCH(k_support_eval, dim3(L.count));
         return 0;
     }
