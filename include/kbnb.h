@@ -141,6 +141,9 @@ typedef struct {
                                    certificate shows that the node cannot be pruned
                                    by a finite upper_bound (branch and bound only
                                    needs to branch it) */
+    int32_t warm_nnz;           /* sparse warm start, used when warm_start is NULL: */
+    const int32_t *warm_idx;    /*   warm_nnz distinct indices in [0, p) and their */
+    const double *warm_val;     /*   finite values (J0 entries are ignored) */
 } kbnb_node_desc;
 
 typedef struct {

@@ -53,7 +53,9 @@ class NodeDesc(ctypes.Structure):
                 ("fixed_in", ctypes.c_void_p), ("n_out", ctypes.c_int32),
                 ("fixed_out", ctypes.c_void_p), ("warm_start", ctypes.c_void_p),
                 ("upper_bound", ctypes.c_double), ("rel_tol", ctypes.c_double),
-                ("max_iters", ctypes.c_int32), ("stop_unprunable", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("stop_unprunable", ctypes.c_int32),
+                ("warm_nnz", ctypes.c_int32), ("warm_idx", ctypes.c_void_p),
+                ("warm_val", ctypes.c_void_p)]
 
 
 class BoundResult(ctypes.Structure):
@@ -291,14 +293,24 @@ def _node_array(nodes, upper_bound, rel_tol, max_iters, tags, warm_starts, stop_
         fin = np.ascontiguousarray(fin, dtype=np.int32)
         fout = np.ascontiguousarray(fout, dtype=np.int32)
         keep += [fin, fout]
-        w = None
+        # a warm start is a length-p array, or a sparse (indices, values) pair
+        w = wi = wv = None
         if warm_starts is not None and warm_starts[i] is not None:
-            w = np.ascontiguousarray(warm_starts[i], dtype=np.float64)
-            keep.append(w)
+            ws = warm_starts[i]
+            if isinstance(ws, tuple):
+                wi = np.ascontiguousarray(ws[0], dtype=np.int32)
+                wv = np.ascontiguousarray(ws[1], dtype=np.float64)
+                keep += [wi, wv]
+            else:
+                w = np.ascontiguousarray(ws, dtype=np.float64)
+                keep.append(w)
         arr[i] = NodeDesc(tag=int(tags[i]) if tags is not None else i, n_in=len(fin),
                           fixed_in=_p(fin) if len(fin) else None, n_out=len(fout),
                           fixed_out=_p(fout) if len(fout) else None,
                           warm_start=_p(w) if w is not None else None,
+                          warm_nnz=len(wi) if wi is not None else 0,
+                          warm_idx=_p(wi) if wi is not None and len(wi) else None,
+                          warm_val=_p(wv) if wv is not None and len(wv) else None,
                           upper_bound=float(pick(upper_bound, i)),
                           rel_tol=float(pick(rel_tol, i)), max_iters=int(pick(max_iters, i)),
                           stop_unprunable=int(pick(stop_unprunable, i)))

@@ -69,10 +69,10 @@ struct Open {
     int depth;
     uint64_t seq;
     std::vector<int32_t> in, out;
-    // warm start: the parent's iterate (sparse, shared by both children),
-    // with coordinate warm_skip zeroed (the z_j = 0 child; -1 for none)
+    // warm start: the parent's iterate (sparse, shared by both children; the
+    // engine ignores its entries on J0, so the z_j = 0 child starts from it
+    // with beta_j = 0)
     std::shared_ptr<const WarmStart> warm;
-    int32_t warm_skip = -1;
     CertPtr cert;             // audit mode: the certificate of lb (null at the root)
 };
 
@@ -308,7 +308,6 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
 
     const int cap_flight = 2 * m;
     std::vector<kbnb_node_desc> batch;
-    std::vector<double> warm_flat;  // dense warm starts of one fill, p entries each
     std::vector<std::vector<int32_t>> set_store;  // index lists of support evaluations
     std::vector<kbnb_bound_result> out(m);
     std::vector<int32_t> sup((size_t)m * k);
@@ -483,7 +482,6 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         // fill the device
         double tm = elapsed();
         batch.clear();
-        size_t nwarm = 0;
         set_store.clear();
         int room = cap_flight - (int)flight.size();
         while (room > 0 && !open.empty()) {
@@ -523,9 +521,6 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
             d.fixed_in = o->in.data();
             d.n_out = (int32_t)o->out.size();
             d.fixed_out = o->out.data();
-            if (o->warm) {
-                ++nwarm;
-            }
             // the engine stops a node at bound >= ub - 1e-6 |ub|; in Rashomon
             // mode that must imply bound > tau
             d.upper_bound = rs ? tau() * (1.0 + 4e-6) : UB;
@@ -548,18 +543,16 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
         }
         t_fill += elapsed() - tm;
         tm = elapsed();
-        // warm-start and index pointers are set once the storage no longer moves
+        // sparse warm starts, and the index pointers of support evaluations
+        // once set_store no longer moves
         {
-            size_t wsi = 0;
-            warm_flat.assign((size_t)p * nwarm, 0.0);
             for (auto &d : batch) {
                 Flight &f = flight[d.tag];
                 if (f.kind == FL_NODE && f.node->warm) {
-                    double *w = warm_flat.data() + (size_t)p * wsi++;
                     const WarmStart &ws = *f.node->warm;
-                    for (size_t r = 0; r < ws.idx.size(); ++r) w[ws.idx[r]] = ws.val[r];
-                    if (f.node->warm_skip >= 0) w[f.node->warm_skip] = 0.0;
-                    d.warm_start = w;
+                    d.warm_nnz = (int32_t)ws.idx.size();
+                    d.warm_idx = ws.idx.data();
+                    d.warm_val = ws.val.data();
                 }
             }
             bind_sets(batch);
@@ -672,7 +665,6 @@ extern "C" int branch_and_bound(kbnb_problem *P, const kbnb_bnb_options *opt, kb
                 } else {
                     c->in = std::move(o->in);
                     c->out = std::move(o->out);
-                    c->warm_skip = j;  // z_j = 0 zeroes beta_j
                 }
                 std::vector<int32_t> &grow = (side == 0) ? c->out : c->in;
                 grow.insert(std::upper_bound(grow.begin(), grow.end(), j), j);

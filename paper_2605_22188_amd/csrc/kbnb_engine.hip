@@ -90,6 +90,8 @@ struct PendingNode {
     double t_submit = 0;      // steady-clock seconds at submit_nodes
     std::vector<int8_t> st;  // ldp entries
     std::vector<double> warm; // empty or p entries
+    std::vector<int32_t> widx; // or a sparse warm start (warm empty)
+    std::vector<double> wval;
     int kbar, n0;
     double ub, tol;
     int max_iter;
@@ -591,7 +593,7 @@ static int enqueue_round_async(kbnb_problem *P, std::unique_lock<std::mutex> &lk
         h.slot = slot;
         h.kbar = nd.kbar;
         h.max_iter = nd.max_iter;
-        h.has_warm = nd.warm.empty() ? 0 : 1;
+        h.has_warm = (nd.warm.empty() && nd.widx.empty()) ? 0 : 1;
         h.ub = nd.ub;
         h.tol = nd.tol;
         h.early = nd.early;
@@ -599,7 +601,13 @@ static int enqueue_round_async(kbnb_problem *P, std::unique_lock<std::mutex> &lk
         memcpy(rec + sizeof(AdmitRec), nd.st.data(), P->ldp);
         if (h.has_warm) {
             const size_t woff = round_up(sizeof(AdmitRec) + P->ldp, 8);
-            memcpy(rec + woff, nd.warm.data(), sizeof(double) * P->p);
+            double *w = reinterpret_cast<double *>(rec + woff);
+            if (!nd.warm.empty()) {
+                memcpy(w, nd.warm.data(), sizeof(double) * P->p);
+            } else {
+                memset(w, 0, sizeof(double) * P->p);
+                for (size_t r = 0; r < nd.widx.size(); ++r) w[nd.widx[r]] = nd.wval[r];
+            }
         }
         P->slot_tag[slot] = nd.tag;
         P->slot_n0[slot] = nd.n0;
@@ -1366,6 +1374,17 @@ static int submit_locked(kbnb_problem *P, const kbnb_node_desc *nodes, int count
             pn.warm.assign(nd.warm_start, nd.warm_start + P->p);
             for (int j = 0; j < P->p; ++j)
                 if (!std::isfinite(pn.warm[j])) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: warm start not finite", i);
+        } else if (nd.warm_nnz > 0) {
+            if (!nd.warm_idx || !nd.warm_val || nd.warm_nnz > P->p)
+                return fail(KBNB_E_INVALID_ARGUMENT, "node %d: bad sparse warm start", i);
+            pn.widx.assign(nd.warm_idx, nd.warm_idx + nd.warm_nnz);
+            pn.wval.assign(nd.warm_val, nd.warm_val + nd.warm_nnz);
+            for (int r = 0; r < nd.warm_nnz; ++r)
+                if (pn.widx[r] < 0 || pn.widx[r] >= P->p || !std::isfinite(pn.wval[r]))
+                    return fail(KBNB_E_INVALID_ARGUMENT, "node %d: sparse warm start entry %d out of range or not finite",
+                                i, r);
+        } else if (nd.warm_nnz < 0) {
+            return fail(KBNB_E_INVALID_ARGUMENT, "node %d: negative warm_nnz", i);
         }
         if (std::isnan(nd.upper_bound)) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: upper bound is NaN", i);
         if (nd.rel_tol < 0 || std::isnan(nd.rel_tol)) return fail(KBNB_E_INVALID_ARGUMENT, "node %d: bad rel_tol", i);

@@ -450,3 +450,34 @@ def test_step_constant_is_the_largest_eigenvalue(n, p, rho, loss, dtype):
     lam = np.linalg.eigvalsh(inst.X.T @ inst.X)[-1]
     c = 2.0 if loss == W.SQUARED else 0.25
     assert L == pytest.approx(1.02 * c * lam, rel=1e-9)
+
+
+def test_sparse_warm_starts_match_dense():
+    """A warm start given sparsely (indices and values) is the dense one
+    with zeros elsewhere: the same nodes give bit-identical results either
+    way, entries on J0 are ignored as in the dense form, and malformed
+    sparse entries are rejected."""
+    announce("sparse warm starts, logistic 1500x90")
+    inst = W.small_instance(1500, 90, 6, W.LOGISTIC, seed=15, dtype="f32")
+    nodes = W.random_nodes(90, 40, 3, 20, seed=16)
+    r = rng(17)
+    dense, sparse = [], []
+    for nd in nodes:
+        w = np.zeros(90)
+        idx = np.sort(r.choice(90, size=12, replace=False)).astype(np.int32)
+        w[idx] = r.normal(0, 0.5, size=12)
+        dense.append(w)
+        sparse.append((idx, w[idx]))  # some indices fall on J0: ignored by both
+    h = K.create_from_instance(inst, batch_width=64, cert_period=8)
+    a = K.bound_nodes(h, nodes, rel_tol=1e-6, warm_starts=dense)
+    b = K.bound_nodes(h, nodes, rel_tol=1e-6, warm_starts=sparse)
+    for x, y in zip(a, b):
+        assert x["status"] == y["status"] == K.CONVERGED
+        assert x["lower_bound"] == y["lower_bound"] and x["primal_value"] == y["primal_value"]
+        assert x["iterations"] == y["iterations"] and np.array_equal(x["beta"], y["beta"])
+    for bad in ((np.array([3, 90], np.int32), np.array([0.1, 0.2])),
+                (np.array([3, -1], np.int32), np.array([0.1, 0.2])),
+                (np.array([3, 4], np.int32), np.array([0.1, np.nan]))):
+        with pytest.raises(K.KbnbError):
+            K.bound_nodes(h, nodes[:1], rel_tol=1e-6, warm_starts=[bad])
+    K.destroy_problem(h)
