@@ -2211,8 +2211,9 @@ struct SupportArgs {
     // split-row version (k_support_mw_init, k_support_mw_step): workgroups
     // per support, and the state of each support kept between step launches
     int groups;
+    int init_groups;    // workgroups per support of the set-up (Gram matrix) launch
     double *part;       // [count][groups][KB + 2] partial sums of the current step
-    double *gram;       // [count][groups][KB (KB + 1) / 2] partial Gram matrices
+    double *gram;       // [count][init_groups][KB (KB + 1) / 2] partial Gram matrices
     double *st;         // [count][8] eta, theta, t, best primal, best dual, finished
     double *vec;        // [count][4][KB] beta, Y, best-primal beta, best-dual beta
     int32_t *step;      // [count] step index
@@ -2494,11 +2495,11 @@ __global__ __launch_bounds__(256) void k_support_eval(SupportArgs a)
 // finishes at step max_iter at the latest, so max_iter + 1 step launches
 // finish every support.
 // ---------------------------------------------------------------------------
-// rows [r0, r1) of workgroup gg; block starts are multiples of RT
+// rows [r0, r1) of workgroup gg of ng; block starts are multiples of RT
 template <int RT = 1>
-__device__ __forceinline__ void support_rows(const SupportArgs &a, int gg, int &r0, int &r1)
+__device__ __forceinline__ void support_rows(const SupportArgs &a, int ng, int gg, int &r0, int &r1)
 {
-    const int per = ((a.n + a.groups - 1) / a.groups + RT - 1) / RT * RT;
+    const int per = ((a.n + ng - 1) / ng + RT - 1) / RT * RT;
     r0 = min(a.n, gg * per);
     r1 = min(a.n, r0 + per);
 }
@@ -2538,13 +2539,13 @@ __device__ __forceinline__ double sum_in_order(const double *v, int ng, int64_t 
     return t;
 }
 
-// every thread: true in the workgroup that arrives last at support m
-__device__ __forceinline__ bool support_last_arrival(const SupportArgs &a, int m, int *flag)
+// every thread: true in the workgroup that arrives last of the ng of support m
+__device__ __forceinline__ bool support_last_arrival(const SupportArgs &a, int m, int ng, int *flag)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();  // this workgroup's partial sums before its arrival
-        *flag = atomicAdd(&a.arrive[m], 1) == a.groups - 1;
+        *flag = atomicAdd(&a.arrive[m], 1) == ng - 1;
     }
     __syncthreads();
     const bool last = *flag != 0;
@@ -2563,12 +2564,12 @@ __global__ __launch_bounds__(256) void k_support_mw_init(SupportArgs a)
     __shared__ double tile[TR][KB + 1];
     __shared__ int s_last;
     const TA *XT = reinterpret_cast<const TA *>(a.XT);
-    const int ng = a.groups, m = blockIdx.x / ng, gg = blockIdx.x % ng;
+    const int ng = a.init_groups, m = blockIdx.x / ng, gg = blockIdx.x % ng;
     const int tid = threadIdx.x;
     const int64_t o0 = a.off[m];
     const int kl = (int)(a.off[m + 1] - o0);
     int r0, r1;
-    support_rows(a, gg, r0, r1);
+    support_rows(a, ng, gg, r0, r1);
     if (tid < KB) L[tid] = (tid < kl) ? a.lab[o0 + tid] : 0;
     if (blockIdx.x == 0 && tid == 0) *a.ndone = 0;
     __syncthreads();
@@ -2609,7 +2610,7 @@ __global__ __launch_bounds__(256) void k_support_mw_init(SupportArgs a)
 #pragma unroll
     for (int v = 0; v < PT; ++v)
         if (tid + 256 * v < NPAIR) gp[tid + 256 * v] = gacc[v];
-    if (!support_last_arrival(a, m, &s_last)) return;
+    if (!support_last_arrival(a, m, ng, &s_last)) return;
     // the last workgroup: the Gram matrix in group order, the step size and
     // the starting state
 #pragma unroll
@@ -2674,7 +2675,7 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
     constexpr int RT = MwRows<TA, KB>::RT;
     typedef typename RawVec<RT * (int)sizeof(TA)>::t RV;
     int r0, r1;
-    support_rows<RT>(a, gg, r0, r1);
+    support_rows<RT>(a, ng, gg, r0, r1);
     double *vec = a.vec + (int64_t)m * 4 * KB;
     if (tid < KB) {
         L[tid] = (tid < kl) ? a.lab[o0 + tid] : 0;
@@ -2746,7 +2747,7 @@ __global__ __launch_bounds__(256) void k_support_mw_step(SupportArgs a)
     __syncthreads();
     double *pp = a.part + ((int64_t)m * ng + gg) * (KB + 2);
     if (tid < KB + 2 && (tid < kl || tid >= KB)) pp[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    if (!support_last_arrival(a, m, &s_last)) return;
+    if (!support_last_arrival(a, m, ng, &s_last)) return;
     // the last workgroup: the step's sums in group order, then the update
     {
         // the groups' partials in a fixed order: thread (c, h) adds groups
@@ -2873,14 +2874,21 @@ struct MwLayout {
     size_t part, gram, st, vec, step, arrive, ndone, total;
 };
 
-static MwLayout mw_layout(int count, int groups, int KB)
+// the set-up launch forms the Gram matrix over workgroups of at most
+// SUPPORT_MW_ROWS rows whatever the step's split
+static int mw_init_groups(int n, int groups)
+{
+    return std::max(groups, (n + SUPPORT_MW_ROWS - 1) / SUPPORT_MW_ROWS);
+}
+
+static MwLayout mw_layout(int count, int groups, int init_groups, int KB)
 {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t blocks = (size_t)count * groups, c = (size_t)count;
     MwLayout l;
     size_t o = 0;
     l.part = o;   o += al(blocks * (KB + 2) * 8);
-    l.gram = o;   o += al(blocks * (size_t)KB * (KB + 1) / 2 * 8);
+    l.gram = o;   o += al((size_t)count * init_groups * (size_t)KB * (KB + 1) / 2 * 8);
     l.st = o;     o += al(c * 8 * 8);
     l.vec = o;    o += al(c * 4 * KB * 8);
     l.step = o;   o += al(c * 4);
@@ -2901,8 +2909,9 @@ int support_eval_plan(int xtype, int n, int count, int maxlen, int want, size_t 
                                   std::max(1, SUPPORT_MW_BLOCKS / count));
     g = std::min(g, std::max(n, 1));  // no more workgroups than rows
     g = std::max(1, (int)std::min<int64_t>(g, INT32_MAX / count));
+    if ((int64_t)count * mw_init_groups(n, g) > INT32_MAX) return 1;
     // the step-launch kernels, with g workgroups per support (also for g = 1)
-    *work_bytes = mw_layout(count, g, support_kb(maxlen)).total;
+    *work_bytes = mw_layout(count, g, mw_init_groups(n, g), support_kb(maxlen)).total;
     return g;
 }
 
@@ -2916,7 +2925,8 @@ static SupportArgs support_args(const SupportLaunch &L)
     a.beta_out = L.beta_out; a.beta_lb_out = L.beta_lb_out; a.value = L.value; a.lower = L.lower;
     a.status = L.status; a.iters = L.iters;
     if (L.work) {
-        const MwLayout l = mw_layout(L.count, L.groups, support_kb(L.maxlen));
+        a.init_groups = mw_init_groups(L.n, L.groups);
+        const MwLayout l = mw_layout(L.count, L.groups, a.init_groups, support_kb(L.maxlen));
         char *w = (char *)L.work;
         a.part = (double *)(w + l.part);
         a.gram = (double *)(w + l.gram);
@@ -2931,7 +2941,7 @@ static SupportArgs support_args(const SupportLaunch &L)
 
 const int32_t *support_done_counter(const SupportLaunch &L)
 {
-    const MwLayout l = mw_layout(L.count, L.groups, support_kb(L.maxlen));
+    const MwLayout l = mw_layout(L.count, L.groups, mw_init_groups(L.n, L.groups), support_kb(L.maxlen));
     return (const int32_t *)((const char *)L.work + l.ndone);
 }
 
@@ -2971,11 +2981,11 @@ int launch_support_start(hipStream_t s, const SupportLaunch &L, int steps)
         KBNB_SUP_DISPATCH(k_support_eval, dim3(L.count));
         return 0;
     }
-    const MwLayout l = mw_layout(L.count, L.groups, support_kb(L.maxlen));
+    const MwLayout l = mw_layout(L.count, L.groups, a.init_groups, support_kb(L.maxlen));
     if (!L.work || L.work_bytes < l.total) return -1;
-    // arrival counts start at zero (each step's last workgroup clears its own)
+    // arrival counts start at zero (each launch's last workgroup clears its own)
     if (hipMemsetAsync(a.arrive, 0, (size_t)L.count * 4, s) != hipSuccess) return -2;
-    KBNB_SUP_DISPATCH(k_support_mw_init, dim3((unsigned)((size_t)L.count * L.groups)));
+    KBNB_SUP_DISPATCH(k_support_mw_init, dim3((unsigned)((size_t)L.count * a.init_groups)));
     return launch_support_steps(s, L, steps);
 }
 #undef KBNB_SUP_DISPATCH
