@@ -181,7 +181,7 @@ int engine_streams(int32_t count);
 /*
  * create_problem -- validate the instance, copy X and y to the device in the
  * instance's storage type (plus a transposed copy for the X^T R products),
- * estimate the smoothness constant by power iteration on the device, size
+ * estimate the smoothness constant (Lanczos on X^T X, on the device), size
  * the node-slot batch from the HBM budget, and start the problem's engine.
  * Passage: Sec. 1 (problem) and App. E.4 (batch sizing from a memory budget).
  * Returns KBNB_E_INVALID_ARGUMENT for bad sizes/values, KBNB_E_BUDGET_EXCEEDED

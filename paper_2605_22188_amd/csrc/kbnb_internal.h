@@ -151,7 +151,7 @@ void launch_admit(hipStream_t s, bool iter_f64, const uint8_t *stage, int count,
 // standalone prox over a batch (u given), for the step-level entry point
 void launch_prox_batch(hipStream_t s, const double *U, const int8_t *st, const int32_t *kbar,
                        double *Bout, int m, double eta, const Consts &c);
-// power iteration pieces: out[r] = sum_c A[r][c] v[c] in float64
+// products of the Lanczos iteration for L: out[r] = sum_c A[r][c] v[c] in float64
 void launch_matvec_f64(hipStream_t s, int xtype, const void *A, int64_t lda, int rows, int cols,
                        const double *v, double *out);
 // fixed-model reliance of pool records (float64): record m's labels and
