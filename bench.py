@@ -405,22 +405,31 @@ def serving_leg(K, W, torch, args):
     # saturation: a burst of nodes on every problem at once
     burst = 64
     bursts = [requests(i, burst) for i in range(32)]
+    # algorithmic work of a result: its iterations times the two contractions
+    # over its non-excluded columns, 4 n (p - |J0|) FLOPs each
+    def alg_flops(i, node, r):
+        return float(r["iterations"]) * 4.0 * insts[i].n * (insts[i].p - len(node.fixed_out))
+
+    sat_out = [None] * 32
+
+    def saturate(i):
+        sat_out[i] = K.bound_nodes(handles[i], bursts[i], rel_tol=1e-6, max_iters=it_cap)
     t0 = time.perf_counter()
-    threads = [threading.Thread(target=K.bound_nodes, args=(handles[i], bursts[i]),
-                                kwargs=dict(rel_tol=1e-6, max_iters=it_cap)) for i in range(32)]
+    threads = [threading.Thread(target=saturate, args=(i,)) for i in range(32)]
     for th in threads:
         th.start()
     for th in threads:
         th.join()
     t_sat = time.perf_counter() - t0
     sat_rate = 32 * burst / t_sat
-    log(f"serving: saturated {sat_rate:.0f} node bounds/s")
+    sat_tflops = sum(alg_flops(i, nd, r) for i in range(32) for nd, r in zip(bursts[i], sat_out[i])) / t_sat / 1e12
+    log(f"serving: saturated {sat_rate:.0f} node bounds/s, {sat_tflops:.1f} algorithmic TFLOP/s")
     def stream(load, seed0):
         """Poisson arrivals at `load` times the saturated rate for serve_seconds;
         runs until every request has its result."""
         lam = load * sat_rate / 32
         dur = args.serve_seconds
-        lat, converged, done = [], [0], [0]
+        lat, converged, done, flops = [], [0], [0], [0.0]
         qs, ss = [], []
         lock = threading.Lock()
         rng_i = [np.random.Generator(np.random.PCG64(seed0 + i)) for i in range(32)]
@@ -452,6 +461,7 @@ def serving_leg(K, W, torch, args):
                 with lock:
                     for r in res:
                         a = sub.pop(r["tag"])
+                        flops[0] += alg_flops(i, nodes[r["tag"]], r)
                         lat.append(tnow - a)
                         qs.append(r["queue_seconds"])
                         ss.append(r["solve_seconds"])
@@ -471,6 +481,7 @@ def serving_leg(K, W, torch, args):
         q_ms, s_ms = np.array(qs) * 1e3, np.array(ss) * 1e3
         return {"offered_load": load, "requests": int(done[0]), "seconds": round(wall, 2),
                 "bounds_per_s": round(done[0] / wall, 1),
+                "alg_tflops": round(flops[0] / wall / 1e12, 2),
                 "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                                "p99": round(float(np.percentile(lat_ms, 99)), 3)},
                 "queue_ms": {"p50": round(float(np.percentile(q_ms, 50)), 3),
@@ -489,7 +500,12 @@ def serving_leg(K, W, torch, args):
     K.device_budget(0)
     K.engine_streams(0)
     res = {"workload": "serving_mix_32_problems_f32", "problems": 32,
-           "saturated_rate": round(sat_rate, 1), "max_iters": it_cap, "batch_widths": widths,
+           "saturated_rate": round(sat_rate, 1),
+           "saturated_alg_tflops": round(sat_tflops, 2),
+           "saturated_frac_of_fp32_mfma": round(sat_tflops / PEAK_TFLOPS["f32"], 4),
+           "work_measure": "contraction FLOPs 4 n (p - |J0|) per iteration of each result (the certificates "
+                           "not counted), over wall time",
+           "max_iters": it_cap, "batch_widths": widths,
            "budget_bytes_per_problem": 2 << 30, "device_budget_bytes": 64 << 30,
            "device_bytes_in_use": int(in_use), "shared_streams": args.serve_streams}
     res.update(main)
