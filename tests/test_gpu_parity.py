@@ -481,3 +481,29 @@ def test_sparse_warm_starts_match_dense():
         with pytest.raises(K.KbnbError):
             K.bound_nodes(h, nodes[:1], rel_tol=1e-6, warm_starts=[bad])
     K.destroy_problem(h)
+
+
+def test_bnb_support_paths_and_reopt_controls():
+    """The three ways of re-optimising rounding supports (automatic, the
+    re-optimisation kernel, the node engine; rows split over forced
+    workgroups too) reach the oracle's optimum of the 500x30 search; invalid
+    values of the controls are rejected."""
+    announce("branch_and_bound 500x30 over support paths and reopt_groups")
+    inst = W.plain_bnb_squared_500x30()
+    P = oracle.Problem.from_instance(inst)
+    ref = P.bnb()
+    for groups in (0, 1, 3):
+        h = K.create_from_instance(inst, batch_width=64, reopt_groups=groups)
+        for path in (0, 1, 2):
+            out = K.branch_and_bound(h, support_path=path)
+            assert out["status"] == 0 and out["rel_gap"] <= 1e-6, (groups, path)
+            assert list(out["support"]) == list(ref["support"]), (groups, path)
+            assert out["objective"] == pytest.approx(ref["objective"], rel=1e-6)
+            assert out["lower_bound"] <= ref["objective"] * (1 + 1e-9)
+        if groups == 0:
+            with pytest.raises(K.KbnbError):
+                K.branch_and_bound(h, support_path=3)
+        K.destroy_problem(h)
+    for bad in (-1, 1025):
+        with pytest.raises(K.KbnbError):
+            K.create_from_instance(inst, batch_width=64, reopt_groups=bad)
