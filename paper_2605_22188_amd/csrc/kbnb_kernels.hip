@@ -560,8 +560,8 @@ __device__ __forceinline__ void store_planes4(uint16_t *C, int64_t plane, int64_
 // (split-K float32 partials).  Rows of A past rows_a repeat the last row
 // block and are not stored (rows_c / rows_valid).
 // ---------------------------------------------------------------------------
-template <int MODE, int WR, int NB>
-__global__ __launch_bounds__(256) void k_gemm_stream(GemmArgs g)
+template <int MODE, int WR, int NB, bool ADB = true>
+__global__ __launch_bounds__(256, ADB ? 1 : 2) void k_gemm_stream(GemmArgs g)
 {
     constexpr int BM = 4 * WR, BN = GEMM_BN, SK = 128;
     constexpr int FI = WR / 16, FJ = 4;
@@ -688,11 +688,26 @@ __global__ __launch_bounds__(256) void k_gemm_stream(GemmArgs g)
         if (nss > 1) load_b(kbeg + SK);
     }
     __syncthreads();
-    // two super-steps per trip, so the A register sets are fixed at compile time
-    for (int s = 0; s < nss; s += 2) {
-        step(s, ra0, ra1, nss);
-        if (s + 1 >= nss) break;
-        step(s + 1, ra1, ra0, nss);
+    if constexpr (ADB) {
+        // two super-steps per trip, so the A register sets are fixed at compile time
+        for (int s = 0; s < nss; s += 2) {
+            step(s, ra0, ra1, nss);
+            if (s + 1 >= nss) break;
+            step(s + 1, ra1, ra0, nss);
+        }
+    } else {
+        // one A register set, loaded at the start of its own super-step: the
+        // freed registers let a second workgroup share the CU and cover that
+        // load's latency
+        for (int s = 0; s < nss; ++s) {
+            if (s > 0) load_a(kbeg + s * SK, ra0);
+            compute(ra0, s & 1);
+            if (s + 1 < nss) {
+                stage_b((s + 1) & 1, kbeg + (s + 1) * SK);
+                if (s + 2 < nss) load_b(kbeg + (s + 2) * SK);
+            }
+            __syncthreads();
+        }
     }
 
     // ---- epilogue: acc[f][j][r] holds C at row = wrow + 16 f + 4 lg + r,
@@ -810,6 +825,19 @@ int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_
     else nblocks = g.tiles_m * tiles_n;
     const dim3 grid(nblocks, 1);
     if ((wr != 16 && wr != 32 && wr != 64) || (nb != 2 && nb != 3)) return -1;
+    // the two-plane forward launches with 64-row wave tiles run with one A
+    // register set at two workgroups per CU (5-9% faster at 100000 x 5000);
+    // three planes do not fit two workgroups, and the split-K backward gains
+    // nothing, so those keep the prefetching A set
+#define KBNB_STREAM_FWD(M)                                                                       \
+    do {                                                                                         \
+        if (wr == 64 && nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 64, 3>), grid, dim3(256), 0, s, g); \
+        else if (wr == 64) KBNB_LAUNCH((k_gemm_stream<M, 64, 2, false>), grid, dim3(256), 0, s, g);       \
+        else if (wr == 32 && nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 32, 3>), grid, dim3(256), 0, s, g); \
+        else if (wr == 32) KBNB_LAUNCH((k_gemm_stream<M, 32, 2>), grid, dim3(256), 0, s, g);       \
+        else if (nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 16, 3>), grid, dim3(256), 0, s, g);        \
+        else KBNB_LAUNCH((k_gemm_stream<M, 16, 2>), grid, dim3(256), 0, s, g);                     \
+    } while (0)
 #define KBNB_STREAM(M)                                                                           \
     do {                                                                                         \
         if (wr == 64 && nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 64, 3>), grid, dim3(256), 0, s, g); \
@@ -819,11 +847,12 @@ int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_
         else if (nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 16, 3>), grid, dim3(256), 0, s, g);        \
         else KBNB_LAUNCH((k_gemm_stream<M, 16, 2>), grid, dim3(256), 0, s, g);                     \
     } while (0)
-    if (mode == EPI_DLOSS) KBNB_STREAM(EPI_DLOSS);
-    else if (mode == EPI_DLOSS_ANCHOR) KBNB_STREAM(EPI_DLOSS_ANCHOR);
+    if (mode == EPI_DLOSS) KBNB_STREAM_FWD(EPI_DLOSS);
+    else if (mode == EPI_DLOSS_ANCHOR) KBNB_STREAM_FWD(EPI_DLOSS_ANCHOR);
     else if (mode == EPI_STORE) KBNB_STREAM(EPI_STORE);
     else return -1;
 #undef KBNB_STREAM
+#undef KBNB_STREAM_FWD
     return 0;
 }
 
