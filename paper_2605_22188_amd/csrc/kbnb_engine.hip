@@ -267,10 +267,12 @@ static size_t per_slot_bytes(const kbnb_problem *P)
 static void splits_for(const kbnb_problem *P, int mact, Variant &v)
 {
     if (P->planes) {
-        // the streaming X^T R: 256-row tiles; about two workgroups per CU, at
-        // most 32 splits of a multiple of 128 rows (the tiled layout's k block)
+        // the streaming X^T R: 256-row tiles; at least 2048 workgroups (eight
+        // per CU) where 32 splits allow, in a multiple of 8 splits so that no
+        // split slot of the launch grid (8 per tile group) stays empty, and
+        // splits of a multiple of 128 rows (the tiled layout's k block)
         const int st = ((P->pm + 255) / 256) * (mact / GEMM_BN);
-        int ws = std::min(32, std::max(1, (512 + st - 1) / st));
+        int ws = std::min(32, (int)round_up(std::max(1, (2048 + st - 1) / st), 8));
         int ch = (int)round_up((P->npad + ws - 1) / ws, 128);
         if (P->split_rows > 0) ch = (int)round_up(std::max(P->split_rows, (P->npad + 31) / 32), 128);
         v.gchunk = ch;

@@ -193,8 +193,10 @@ __device__ __forceinline__ bool map_tile(const GemmArgs &g, int &tm, int &tn, in
         const int T = g.tiles_m * g.tiles_n;
         split = xcd + 8 * (q / T);
         const int t = q % T;
-        tm = t % g.tiles_m;
-        tn = t / g.tiles_m;
+        // the column tiles that share a row block of A run next to each other
+        // on one XCD, so its L2 serves A to all of them
+        tn = t % g.tiles_n;
+        tm = t / g.tiles_n;
         return split < g.nsplit;
     }
     split = 0;
@@ -825,11 +827,12 @@ int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_
     else nblocks = g.tiles_m * tiles_n;
     const dim3 grid(nblocks, 1);
     if ((wr != 16 && wr != 32 && wr != 64) || (nb != 2 && nb != 3)) return -1;
-    // the two-plane forward launches with 64-row wave tiles run with one A
-    // register set at two workgroups per CU (5-9% faster at 100000 x 5000);
-    // three planes do not fit two workgroups, and the split-K backward gains
-    // nothing, so those keep the prefetching A set
-#define KBNB_STREAM_FWD(M)                                                                       \
+    // two-plane launches with 64-row wave tiles run with one A register set
+    // at two workgroups per CU: the forward always (5-9% faster at 100000 x
+    // 5000), the split-K backward from two column tiles up (4-10% at widths
+    // 128-512; a single column tile keeps the prefetch); three planes do not
+    // fit two workgroups and keep the prefetching A set
+#define KBNB_STREAM_1A(M)                                                                       \
     do {                                                                                         \
         if (wr == 64 && nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 64, 3>), grid, dim3(256), 0, s, g); \
         else if (wr == 64) KBNB_LAUNCH((k_gemm_stream<M, 64, 2, false>), grid, dim3(256), 0, s, g);       \
@@ -847,12 +850,13 @@ int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_
         else if (nb == 3) KBNB_LAUNCH((k_gemm_stream<M, 16, 3>), grid, dim3(256), 0, s, g);        \
         else KBNB_LAUNCH((k_gemm_stream<M, 16, 2>), grid, dim3(256), 0, s, g);                     \
     } while (0)
-    if (mode == EPI_DLOSS) KBNB_STREAM_FWD(EPI_DLOSS);
-    else if (mode == EPI_DLOSS_ANCHOR) KBNB_STREAM_FWD(EPI_DLOSS_ANCHOR);
+    if (mode == EPI_DLOSS) KBNB_STREAM_1A(EPI_DLOSS);
+    else if (mode == EPI_DLOSS_ANCHOR) KBNB_STREAM_1A(EPI_DLOSS_ANCHOR);
+    else if (mode == EPI_STORE && tiles_n >= 2) KBNB_STREAM_1A(EPI_STORE);
     else if (mode == EPI_STORE) KBNB_STREAM(EPI_STORE);
     else return -1;
 #undef KBNB_STREAM
-#undef KBNB_STREAM_FWD
+#undef KBNB_STREAM_1A
     return 0;
 }
 

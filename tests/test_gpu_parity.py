@@ -246,6 +246,17 @@ def test_node_bounds_small_all_nodes(loss, dtype, it):
     _bound_parity(inst, nodes, batch_width=64, cert_period=4, iter_dtype=it)
 
 
+@pytest.mark.parametrize("loss", [W.SQUARED, W.LOGISTIC])
+def test_node_bounds_bf16_anchored_three_column_tiles(loss):
+    """Two-plane streaming products over three 64-column tiles (150 nodes on
+    192 slots): the split-K X^T R runs with one A register set and the column
+    tiles of a row block side by side; every node against the oracle."""
+    announce(f"node bounds 700x50 loss={loss} X bf16 anchored, 150 nodes on 192 slots")
+    inst = W.small_instance(700, 50, 6, loss, seed=11 + loss, rho=0.6, dtype="bf16")
+    nodes = W.random_nodes(50, 150, 3, 15, seed=78)
+    _bound_parity(inst, nodes, batch_width=192, cert_period=4, iter_dtype="anchored")
+
+
 def test_node_bounds_logistic_5000x200_launch():
     announce("node bounds logistic 5000x200, one 256-node launch, 16 sampled")
     inst = W.node_bounds_logistic_5000x200()
