@@ -1086,17 +1086,24 @@ __device__ __forceinline__ void store_y4(const Consts &c, Ti *Yi, int64_t o, con
     }
 }
 
+// Registers a split batch may hold in a workgroup of W waves.
+__host__ __device__ constexpr int split_regs(int w) { return w >= 16 ? 32 : (w >= 8 ? 64 : 128); }
+
 // Sum of split-K partials for a thread's chunk: acc[e] += sum_s col[s * stride + j0 + e].
 // Splits are taken in batches of SB with no conditions inside, so all SB * NQ
 // 16-byte loads of a batch are in flight together; the remaining splits
-// (nsplit is the same for the whole workgroup) go one at a time.  Group
+// (nsplit is the same for the whole workgroup) go one at a time.  A batch
+// holds at most RB registers (the workgroup size caps a wave's registers:
+// 1024 threads leave 128, and a larger batch spills to scratch).  Group
 // addresses are clamped into the column with min(): a group past ldp reads
 // valid memory and its (unused) value belongs to a padding coordinate.
-template <typename T, int NQ>
+template <typename T, int NQ, int RB>
 __device__ __forceinline__ void sum_splits(const T *__restrict__ col, int nsplit, int64_t stride,
                                            int j0, int ldp, double (&acc)[4 * NQ])
 {
-    constexpr int SB = split_batch(4 * NQ * 64, (int)sizeof(T));
+    constexpr int SB0 = split_batch(4 * NQ * 64, (int)sizeof(T));
+    constexpr int SBR = RB / (4 * NQ * ((int)sizeof(T) / 4));
+    constexpr int SB = SBR < 1 ? 1 : (SBR < SB0 ? SBR : SB0);
     int go[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) go[q] = min(j0 + 4 * q, ldp - 4);
@@ -1460,7 +1467,7 @@ __global__ __launch_bounds__(64 * W) void k_prox_iter(const Ti *__restrict__ Gp,
         }
     }
     // grad F(Y) = (grad F(beta_c) when anchored) + sum of the partials
-    sum_splits<Ti, NQ>(Gp + off, gsplit, gstride, j0, c.ldp, g);
+    sum_splits<Ti, NQ, split_regs(W)>(Gp + off, gsplit, gstride, j0, c.ldp, g);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         y[e] = bo[e] + th * (bo[e] - bp[e]);
@@ -1610,7 +1617,7 @@ __global__ __launch_bounds__(64 * W) void k_cert_finish(const double *__restrict
             sv[4 * q + e] = ok ? sv[4 * q + e] : -1;
         }
     }
-    sum_splits<double, NQ>(Qp + off, qsplit, qstride, j0, c.ldp, qv);
+    sum_splits<double, NQ, split_regs(W)>(Qp + off, qsplit, qstride, j0, c.ldp, qv);
     // smooth parts
     double fl = 0.0, fc = 0.0;
     for (int q = t; q < tiles_n; q += T) {
