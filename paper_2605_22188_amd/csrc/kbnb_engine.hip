@@ -284,6 +284,15 @@ static void splits_for(const kbnb_problem *P, int mact, Variant &v)
     want = std::max(want, (P->npad + 4095) / 4096);
     want = std::min(want, std::max(1, kt / 4));
     want = std::min(want, 32);
+    // split s runs on XCD s % 8: a count off a multiple of 8 leaves some XCDs
+    // a split more than the rest (25 splits: XCD 0 takes 4, the others 3),
+    // and fewer than 8 leaves XCDs idle; round to a multiple of 8 within the caps
+    if (want > 1 && want % 8) {
+        const int cap = std::min(32, std::max(1, kt / 4));
+        const int up = (want + 7) / 8 * 8, down = want / 8 * 8;
+        if (up <= cap) want = up;
+        else if (down >= 8) want = down;
+    }
     const int chunk = (int)round_up((P->npad + want - 1) / want, GEMM_BK);
     v.mact = mact;
     if (!P->planes) {
