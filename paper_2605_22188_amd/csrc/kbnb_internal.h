@@ -230,11 +230,12 @@ struct GemmArgs {
     int64_t a_plane, b_plane, c_plane;
     int rows_a, rows_c;
 };
-// streaming contraction for bfloat16 A (one plane) and three B planes, tile
-// (4 wr) x 64 with wr = 32 or 64 rows per wave and nb = 2 or 3 planes of B
-// (k_gemm_stream); modes EPI_DLOSS, EPI_DLOSS_ANCHOR (C: nb bfloat16 planes)
-// or EPI_STORE (float32 split-K partials).  Returns -1 for an unsupported
-// combination.
+// streaming contraction for bfloat16 A (one plane) against nb = 2 or 3
+// bfloat16 planes of B, tile (4 wr) x 64 with wr = 16, 32 or 64 rows per wave
+// (k_gemm_stream; two-plane launches with 64-row wave tiles take the variant
+// with one A register set, except a split-K launch of one column tile);
+// modes EPI_DLOSS, EPI_DLOSS_ANCHOR (C: nb bfloat16 planes) or EPI_STORE
+// (float32 split-K partials).  Returns -1 for an unsupported combination.
 int launch_gemm_stream(hipStream_t s, int mode, GemmArgs g, int rows, int tiles_n, int splits, int wr, int nb);
 // wave tile height (16, 32 or 64 rows) of a streaming launch over `rows`
 // rows of A: tile_rows / 4 when given, else chosen by launch size
