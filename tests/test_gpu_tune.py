@@ -122,3 +122,26 @@ def test_tile_rows_apply_to_their_kernel_only():
         res = K.bound_nodes(h, W.random_nodes(20, 8, 2, 5, seed=4), rel_tol=1e-6)
         assert all(r["status"] == K.CONVERGED for r in res)
         K.destroy_problem(h)
+
+
+def test_split_count_is_a_multiple_of_eight():
+    """Split s of a split-K launch runs on XCD s % 8, so the plain contractions
+    round the split count to a multiple of 8.  At 12000 x 1000 float64 and
+    width 1024 the launch-size rule asks for 3 splits (at most 4096 rows
+    each), which would leave five XCDs idle; the count is 8.  600 nodes at
+    full width give the same certified bounds as a problem forced to 3 splits
+    (split depth 4096 rows)."""
+    print("[gpu-test] split count 12000x1000 f64 at width 1024, 600 nodes, against 3 splits", flush=True)
+    inst = W.small_instance(12000, 1000, 10, W.SQUARED, seed=21, dtype="f64")
+    nodes = W.random_nodes(1000, 600, 3, 20, seed=22)
+    out = []
+    for sr, want in ((0, 8), (4096, 3)):
+        h = K.create_from_instance(inst, batch_width=1024, cert_period=8, split_rows=sr)
+        info = K.problem_info(h)
+        assert info["gsplit"] == want, info
+        out.append(K.bound_nodes(h, nodes, rel_tol=1e-6))
+        K.destroy_problem(h)
+    for a, g in zip(*out):
+        assert a["status"] == K.CONVERGED and g["status"] == K.CONVERGED
+        scale = max(abs(a["primal_value"]), abs(g["primal_value"]))
+        assert abs(g["lower_bound"] - a["lower_bound"]) <= 2e-6 * scale
