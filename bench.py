@@ -656,7 +656,7 @@ def main():
 
     run_stream(K, h, preps[:args.warmup], out, args.window)
     log(f"warmup done ({args.warmup} steps)")
-    # the driver's own garbage collection stays out of the timed regions
+    # Python's garbage collection stays out of the timed regions
     import gc
     gc.collect()
     gc.disable()
