@@ -194,7 +194,8 @@ def _draw(kind, q=None):
 def large_leg(K, W, torch, args):
     """Node bounds on the 100000 x 5000 bfloat16 logistic workload (rho 0.7,
     k 15, |beta*_j| ~ U[0.5, 2], lambda2 1, M 4): one batch of nodes with
-    |J1| ~ U{0..7}, |J0| ~ U{0..500}, through the bfloat16 MFMA path."""
+    |J1| ~ U{0..7}, |J0| ~ U{0..500}, through the bfloat16 MFMA path, a float64
+    certificate every --large-period steps (32)."""
     t = time.perf_counter()
     log("large: drawing the 100000 x 5000 instance")
     d = _draw("large")
@@ -205,7 +206,8 @@ def large_leg(K, W, torch, args):
     torch.cuda.synchronize()
     t = time.perf_counter()
     h = K.create_problem(X, y, d["k"], d["loss"], d["lambda2"], d["M"], dtype=d["dtype"],
-                         batch_width=args.large_batch, cert_period=16, tile_rows=args.large_tile_rows,
+                         batch_width=args.large_batch, cert_period=args.large_period,
+                         tile_rows=args.large_tile_rows,
                          split_rows=args.large_split_rows)
     t_setup = time.perf_counter() - t
     log(f"large: problem ready in {t_setup:.1f}s: {K.problem_info(h)}")
@@ -266,7 +268,7 @@ def large_leg(K, W, torch, args):
                 kern[name]["frac_of_hbm_peak"] = round(by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     log(f"large: {len(res)} nodes in {dt:.2f}s -> {rate:.1f} node bounds/s; kernels {kern}")
     return {"workload": "logistic_100000x5000_bf16_rho0.7_k15", "value": round(rate, 2),
-            "unit": "node bounds/s", "nodes": len(res), "batch_width": args.large_batch,
+            "unit": "node bounds/s", "nodes": len(res), "batch_width": args.large_batch, "cert_period": args.large_period,
             "seconds": round(dt, 3), "setup_s": round(t_setup, 2),
             "iterations": {"mean": round(float(np.mean(iters)), 1), "max": int(np.max(iters))},
             "not_converged": int(sum(r["status"] != K.CONVERGED for r in res)),
@@ -593,6 +595,9 @@ def main():
     ap.add_argument("--large", type=int, default=1,
                     help="run the 100000 x 5000 bfloat16 logistic node-bound leg")
     ap.add_argument("--large-batch", type=int, default=256)
+    ap.add_argument("--large-period", type=int, default=32,
+                    help="certificate period of the 100000 x 5000 leg (32 measured fastest "
+                         "there: 459 against 360-381 node bounds/s at 16; 5000 x 200 keeps 16)")
     ap.add_argument("--large-tile-rows", type=int, default=0,
                     help="contraction tile height of the large problem (0: launch-size rule)")
     ap.add_argument("--large-split-rows", type=int, default=0,
