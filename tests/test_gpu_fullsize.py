@@ -2,7 +2,7 @@
 times, on sampled outputs the oracle can check one by one:
 
   * 100000 x 5000 bfloat16 logistic (rho 0.7, k 15): sampled nodes of a
-    256-node launch (anchored bfloat16 iteration, certificate every 16
+    256-node launch (anchored bfloat16 iteration, certificate every 32
     steps) satisfy the duality bracket at the returned iterate,
     LB <= Phi_oracle(beta) and Phi_oracle(beta) - LB <= 1e-6 |Phi_oracle|,
     with the rounding support and branching index bit-exact at beta; the
@@ -44,7 +44,7 @@ def test_large_logistic_100000x5000_sampled_nodes_and_rashomon():
     X = torch.from_numpy(inst.X_store).cuda()
     y = torch.from_numpy(inst.y).cuda()
     h = K.create_problem(X, y, inst.k, inst.loss, inst.lambda2, inst.M, dtype=inst.dtype,
-                         batch_width=256, cert_period=16)
+                         batch_width=256, cert_period=32)
     del X, y
     P = oracle.Problem.from_instance(inst)
     nodes = W.random_nodes(inst.p, 256, 7, 500, seed=3000)
