@@ -108,7 +108,11 @@ typedef struct {
                           then runs on its own streams. */
     uint64_t hbm_budget_bytes; /* device-memory budget of this problem; 0 = 8 GiB */
     int32_t batch_width;       /* node slots; 0 = chosen from the budget (max 1024) */
-    int32_t cert_period;       /* iterations between float64 certificates; 0 = 8 */
+    int32_t cert_period;       /* iterations between float64 certificates; 0 = 8.  A node
+                                  finishes only at a certificate, so a longer period adds
+                                  steps past convergence and saves certificates: it pays
+                                  where the FP64 contractions are costly next to a step
+                                  (tall bfloat16 X); autotune measures periods */
     int32_t iter_dtype;        /* KBNB_ITER_*: precision of the iteration's products */
     int32_t admit_timeout_ms;  /* when the process-wide device budget (device_budget) cannot
                                   hold the problem: how long create_problem waits for other
